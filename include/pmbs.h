@@ -1,0 +1,181 @@
+/*
+ * pmbs.h -- C ABI of the batched push-transition library (libpmbs.so).
+ *
+ * The library advances thousands of independent tabletop environments
+ * (cuboids on a plane, one kinematic box pusher each) through push actions
+ * on one MI355X, evaluates the retrieval reward on them, and keeps a host-
+ * side UCT tree that batches leaves with virtual loss.  It is the batched
+ * expansion/simulation of "Parallel Monte Carlo Tree Search with Batched
+ * Rigid-body Simulations" (Sec. IV-C: selection with virtual loss, batch
+ * expansion, batch simulation, backpropagation; Alg. 1 and Alg. 2).
+ *
+ * Conventions for every entry point:
+ *  - Units are SI.  Quaternions are (w,x,y,z), Hamilton, body to world.
+ *  - Device memory is never allocated after pmbs_sim_create: all of it lives
+ *    in the caller's workspace, sized by pmbs_sim_query_workspace.
+ *  - Work is enqueued on the stream given at create (a hipStream_t, or NULL
+ *    for the default stream).  Calls returning results in host memory
+ *    synchronise that stream; all others are asynchronous.
+ *  - A negative pmbs_status is an error; out-parameters are then untouched
+ *    and pmbs_last_error() holds a message (per calling thread).  Device
+ *    faults surface at the next synchronising call as PMBS_ERR_HIP.
+ *  - Problems of one environment (contact overflow, non-finite state, a
+ *    discarded push) are not call errors: they are bits of that
+ *    environment's status word (pmbs_sim_env_status).
+ *  - Input arrays in host memory are copied before the call returns; input
+ *    arrays in device memory are read in place when the stream reaches the
+ *    call, so they must stay valid until then.
+ *  - One handle is used by one host thread at a time.
+ */
+#ifndef PMBS_H
+#define PMBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pmbs_status;
+#define PMBS_OK 0
+#define PMBS_ERR_INVALID_ARG (-1)
+#define PMBS_ERR_WORKSPACE (-2)
+#define PMBS_ERR_HIP (-3)
+#define PMBS_ERR_CAPACITY (-4)
+#define PMBS_ERR_STATE (-5)
+
+/* environment status bits */
+#define PMBS_ENV_CONTACT_OVERFLOW 1u /* more contacts than max_contacts; tail dropped */
+#define PMBS_ENV_NONFINITE 2u        /* a NaN or Inf appeared in the state */
+#define PMBS_ENV_PUSH_INVALID 4u     /* last push started inside a box: discarded (Sec. IV-B) */
+
+/* bodies per environment, excluding the pusher */
+#define PMBS_MAX_BODIES_PER_ENV 31
+
+const char* pmbs_status_string(pmbs_status s);
+const char* pmbs_last_error(void);
+
+/* ------------------------------------------------------------------ */
+/* simulator                                                           */
+/* ------------------------------------------------------------------ */
+
+/* Capacities and the constants of the push transition.  The paper leaves
+ * the simulator unspecified (Sec. III-A defines the transition as quasi-
+ * static motion with friction and collisions; Sec. V-A fixes 5 cm pushes),
+ * so every constant of the algorithm is explicit here; the defaults are the
+ * documented readings. */
+typedef struct pmbs_sim_config {
+    int32_t max_envs;      /* environment slots */
+    int32_t max_bodies;    /* bodies over all environments (packed) */
+    int32_t max_contacts;  /* per environment: 256 or 512 */
+    int32_t solver_iters;  /* Jacobi iterations per substep (10) */
+    int32_t pool_slots;    /* tree-node state slots resident on the device (0: none) */
+    int32_t pool_stride;   /* bodies per pool slot (>= bodies of any pooled env) */
+    float dt;              /* substep (1/240 s) */
+    float gravity;         /* along -z (9.81) */
+    float margin;          /* contact and AABB margin (0.002 m) */
+    float beta;            /* Baumgarte factor (0.2) */
+    float slop;            /* allowed penetration (0.0005 m) */
+    float mu_plane;        /* friction of the table (0.5) */
+    float mu_pusher;       /* friction of the pusher (0.5) */
+    float pusher_half[3];  /* pusher half extents (0.01, 0.01, 0.02) */
+    float pusher_z;        /* pusher centre height (0.022 m) */
+    float push_speed;      /* pusher speed (0.1 m/s) */
+    float push_length;     /* contour-push length (0.05 m, Sec. V-A) */
+    float push_standoff;   /* contour-push start gap beyond the pusher half width (0.005 m) */
+    float tau_face;        /* SAT hysteresis for face axes (1e-5 m) */
+    float tau_edge;        /* SAT hysteresis for edge axes (5e-4 m) */
+    float edge_eps;        /* skip edge axes with |a x b| below this (1e-4) */
+} pmbs_sim_config;
+
+typedef struct pmbs_sim pmbs_sim_t;
+
+/* Fills every field with the defaults above (capacities: 1024 envs,
+ * 32768 bodies, 256 contacts, no pool). */
+void pmbs_sim_config_default(pmbs_sim_config* cfg);
+
+/* Exact device bytes the configuration needs (256-byte aligned regions). */
+pmbs_status pmbs_sim_query_workspace(const pmbs_sim_config* cfg, size_t* bytes);
+
+/* Creates a simulator over the caller's device workspace (d_workspace,
+ * at least query_workspace bytes, 256-byte aligned, owned by the caller and
+ * kept alive until destroy) and borrows hip_stream. */
+pmbs_status pmbs_sim_create(const pmbs_sim_config* cfg, void* d_workspace, size_t bytes,
+                            void* hip_stream, pmbs_sim_t** out);
+void pmbs_sim_destroy(pmbs_sim_t* sim);
+
+/* Loads n_envs environments (the state s_t of Sec. III-A: per-object pose
+ * and geometry).  env_offset (host, n_envs+1 entries, env_offset[0] = 0,
+ * non-decreasing, at most PMBS_MAX_BODIES_PER_ENV bodies per env) packs
+ * uneven body counts.  state: SoA float32 [13][n] rows px,py,pz, qw,qx,qy,
+ * qz, vx,vy,vz, wx,wy,wz with n = env_offset[n_envs]; host or device per
+ * state_is_device.  body: host SoA float32 [5][n] rows hx,hy,hz (half
+ * extents > 0), mass (> 0), mu (>= 0).  Copies before returning (host) or
+ * in stream order (device).  PMBS_ERR_STATE for a non-finite or non-unit
+ * quaternion host state; PMBS_ERR_CAPACITY beyond the configured sizes. */
+pmbs_status pmbs_sim_set_state(pmbs_sim_t* sim, int32_t n_envs, const int32_t* env_offset,
+                               const float* state, int32_t state_is_device, const float* body);
+
+/* Copies the state out in the set_state layout [13][n].  A host
+ * destination synchronises the stream. */
+pmbs_status pmbs_sim_get_state(pmbs_sim_t* sim, float* state_out, int32_t dst_is_device);
+
+/* One push a^p = (x_s, y_s, x_e, y_e) per environment (Sec. III-A) as
+ * float32 [n_envs][4], host or device, then n_substeps substeps of the
+ * transition.  The pusher starts at (x_s, y_s, pusher_z) facing the push,
+ * moves at push_speed for round(|e - s| / (push_speed dt)) substeps and then
+ * stays.  A push whose start pose overlaps a box is discarded (Sec. IV-B):
+ * the pusher is parked away, the substeps still run and the env status gets
+ * PMBS_ENV_PUSH_INVALID.  Asynchronous. */
+pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_device,
+                          int32_t n_substeps);
+
+/* Status word per environment, cleared by every step.  A host destination
+ * synchronises. */
+pmbs_status pmbs_sim_env_status(pmbs_sim_t* sim, uint32_t* status_out, int32_t dst_is_device);
+
+/* Contact list of every environment at the current poses, with the pusher
+ * placed by `push` (as in step; NULL leaves it parked).  Device outputs only:
+ * counts [n_envs] int32 and contacts float32 [n_envs][max_contacts][9] rows
+ * a, b, px, py, pz, nx, ny, nz, sep (a = -1 is the plane, index n_b of an
+ * env is its pusher; n points from a to b).  The state is not changed. */
+pmbs_status pmbs_sim_collide(pmbs_sim_t* sim, const float* push, int32_t push_is_device,
+                             int32_t* d_counts, float* d_contacts);
+
+/* Retrieval reward of every environment (the grasp classifier's stand-in,
+ * Sec. III-A / IV-B): clearance = distance from the footprint of body
+ * target[e] (local index) to the nearest other footprint (0 if they
+ * overlap); reward = 1 if clearance > width, else clearance / width.
+ * target: int32 [n_envs] host or device; out: float32 [n_envs] device. */
+pmbs_status pmbs_eval_reward(pmbs_sim_t* sim, const int32_t* target, int32_t target_is_device,
+                             float width, float* d_reward, float* d_clearance);
+
+/* Per environment, summed over the substeps of the last step: contacts
+ * solved and candidate pairs from the broadphase (int64 [n_envs][2], host;
+ * synchronises).  The benchmark turns these into algorithmic work. */
+pmbs_status pmbs_sim_stats(pmbs_sim_t* sim, int64_t* out);
+
+/* ------------------------------------------------------------------ */
+/* device state pool: tree-node states resident in HBM                */
+/* ------------------------------------------------------------------ */
+
+/* Batch expansion loads every environment with a selected node's state
+ * (Sec. IV-C, batch expansion).  gather: env e <- pool slot slots[e];
+ * scatter: pool slot slots[e] <- env e.  slots: int32 [n_envs], host or
+ * device; a negative slot leaves that env alone.  Only the dynamic state
+ * (13 floats per body) moves; geometry stays with the env.  Every env must
+ * have at most pool_stride bodies.  Asynchronous. */
+pmbs_status pmbs_pool_gather(pmbs_sim_t* sim, const int32_t* slots, int32_t slots_is_device);
+pmbs_status pmbs_pool_scatter(pmbs_sim_t* sim, const int32_t* slots, int32_t slots_is_device);
+
+/* Waits for all work enqueued on the simulator's stream. */
+pmbs_status pmbs_sim_sync(pmbs_sim_t* sim);
+
+/* Number of environments and bodies of the loaded state. */
+pmbs_status pmbs_sim_shape(const pmbs_sim_t* sim, int32_t* n_envs, int32_t* n_bodies);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

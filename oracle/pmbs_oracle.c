@@ -27,7 +27,12 @@
  *                         Benevolenski and Voroshilov 2012): each body's
  *                         inverse-mass terms are multiplied by the number of
  *                         contacts touching it, without which plain Jacobi
- *                         diverges in the friction rows of a resting box
+ *                         diverges in the friction rows of a resting box.
+ *                         Warm start: every contact starts from the
+ *                         accumulated impulses of the previous substep's
+ *                         contact with the same key (pair and feature),
+ *                         applied before the first iteration; the memory is
+ *                         cleared when a push begins
  *   5. position stage     x += v dt; q <- normalise(q + dt/2 (0,w) q)
  *
  * Every readings' constant comes in through orc_config (gravity, margin,
@@ -100,7 +105,11 @@ typedef struct {
     double kn, kt1, kt2, vstar, mu;
     double ln, lt1, lt2;
     v3 P;                 /* impulse change of the current iteration */
+    int key;              /* (a+1, b, feature): strictly increasing along the list */
 } contact_t;
+
+/* accumulated impulses of the previous substep, by contact key */
+typedef struct { int key; double ln, lt1, lt2; } warm_t;
 
 typedef struct {
     int nb;
@@ -111,6 +120,8 @@ typedef struct {
     int status;
     contact_t* c;
     int nc, cap;
+    warm_t* warm;         /* previous substep's contacts (sorted by key) */
+    int nwarm;
 } env_t;
 
 static void body_setup(body_t* b) {
@@ -139,11 +150,14 @@ static void body_frame(body_t* b, int dynamic) {
 /* geometry view of index i: 0..nb-1 bodies, nb = pusher */
 static const body_t* geom(const env_t* e, int i) { return i == e->nb ? &e->pusher : &e->body[i]; }
 
-static void add_contact(env_t* e, int a, int b, v3 p, v3 n, double sep) {
+/* feature: vertex index for box-plane, ordinal of the kept clip point for a
+ * face manifold, 0 for an edge contact */
+static void add_contact(env_t* e, int a, int b, v3 p, v3 n, double sep, int feature) {
     if (e->nc >= e->cap) { e->status |= ORC_STATUS_CONTACT_OVERFLOW; return; }
     contact_t* c = &e->c[e->nc++];
     memset(c, 0, sizeof(*c));
     c->a = a; c->b = b; c->p = p; c->n = n; c->sep = sep;
+    c->key = ((a + 1) << 16) | (b << 8) | feature;
 }
 
 /* ------------------------------------------------------------------ */
@@ -181,7 +195,7 @@ static void box_plane(env_t* e, const orc_config* cfg, int i) {
         v3 s = V((k & 1) ? b->h.x : -b->h.x, (k & 2) ? b->h.y : -b->h.y, (k & 4) ? b->h.z : -b->h.z);
         v3 vtx = add(b->x, mv(&b->R, s));
         double sep = vtx.z;
-        if (sep <= cfg->margin) add_contact(e, -1, i, sub(vtx, V(0, 0, 0.5 * sep)), V(0, 0, 1), sep);
+        if (sep <= cfg->margin) add_contact(e, -1, i, sub(vtx, V(0, 0, 0.5 * sep)), V(0, 0, 1), sep, k);
     }
 }
 
@@ -327,9 +341,10 @@ static void box_box(env_t* e, const orc_config* cfg, int ia, int ib) {
         np = clip(tmp, np, poly, f, u, -1.0, hu);
         np = clip(poly, np, tmp, f, vv, +1.0, hv);
         np = clip(tmp, np, poly, f, vv, -1.0, hv);
+        int ord = 0;
         for (int i = 0; i < np; ++i) {
             double sep = dot(nref, sub(poly[i], f));
-            if (sep <= cfg->margin) add_contact(e, ia, ib, sub(poly[i], scl(nref, 0.5 * sep)), n, sep);
+            if (sep <= cfg->margin) add_contact(e, ia, ib, sub(poly[i], scl(nref, 0.5 * sep)), n, sep, ord++);
         }
     } else {
         /* edge axis: closest points of the two extreme parallel edges */
@@ -357,7 +372,7 @@ static void box_box(env_t* e, const orc_config* cfg, int ia, int ib) {
             ss = clampd(tt * c - ar, -ha, ha);
         }
         v3 qa = add(pa, scl(ai, ss)), qb = add(pb, scl(bj, tt));
-        add_contact(e, ia, ib, scl(add(qa, qb), 0.5), n, s.s);
+        add_contact(e, ia, ib, scl(add(qa, qb), 0.5), n, s.s, 0);
     }
 }
 
@@ -417,7 +432,14 @@ static void prep(env_t* e, const orc_config* cfg) {
         c->mu = 0.5 * (mu_of(e, cfg, c->a) + mu_of(e, cfg, c->b));
         if (c->sep > 0) c->vstar = -c->sep / cfg->dt;
         else c->vstar = cfg->beta * fmax(-c->sep - cfg->slop, 0.0) / cfg->dt;
+        /* warm start: the previous substep's accumulated impulses of the
+         * contact with the same key (none at the first substep of a push) */
         c->ln = c->lt1 = c->lt2 = 0;
+        for (int w = 0; w < e->nwarm; ++w)
+            if (e->warm[w].key == c->key) {
+                c->ln = e->warm[w].ln; c->lt1 = e->warm[w].lt1; c->lt2 = e->warm[w].lt2;
+                break;
+            }
     }
 }
 
@@ -427,8 +449,29 @@ static void vel_of(const env_t* e, const v3* vs, const v3* ws, int i, v3* v, v3*
     *v = vs[i]; *w = ws[i];
 }
 
+/* v_i += m_i^-1 sum_c s_ci P_c, w_i += I_i^-1 sum_c s_ci r_ci x P_c in contact order */
+static void apply_impulses(env_t* e) {
+    for (int i = 0; i < e->nb; ++i) {
+        v3 sp = V(0, 0, 0), st = V(0, 0, 0);
+        for (int k = 0; k < e->nc; ++k) {
+            const contact_t* c = &e->c[k];
+            if (c->a == i) { sp = sub(sp, c->P); st = sub(st, cross(c->ra, c->P)); }
+            if (c->b == i) { sp = add(sp, c->P); st = add(st, cross(c->rb, c->P)); }
+        }
+        body_t* b = &e->body[i];
+        b->v = add(b->v, scl(sp, b->inv_mass));
+        b->w = add(b->w, mv(&b->inv_iw, st));
+    }
+}
+
 static void jacobi(env_t* e, const orc_config* cfg) {
     v3 vs[ORC_MAX_BODIES], ws[ORC_MAX_BODIES];
+    /* apply the warm-start impulses, then iterate from them */
+    for (int k = 0; k < e->nc; ++k) {
+        contact_t* c = &e->c[k];
+        c->P = add(scl(c->n, c->ln), add(scl(c->t1, c->lt1), scl(c->t2, c->lt2)));
+    }
+    apply_impulses(e);
     for (int it = 0; it < cfg->iters; ++it) {
         for (int i = 0; i < e->nb; ++i) { vs[i] = e->body[i].v; ws[i] = e->body[i].w; }
         for (int k = 0; k < e->nc; ++k) {
@@ -451,17 +494,13 @@ static void jacobi(env_t* e, const orc_config* cfg) {
             c->lt1 = lt1; c->lt2 = lt2;
             c->P = add(scl(c->n, dln), add(scl(c->t1, dl1), scl(c->t2, dl2)));
         }
-        for (int i = 0; i < e->nb; ++i) {
-            v3 sp = V(0, 0, 0), st = V(0, 0, 0);
-            for (int k = 0; k < e->nc; ++k) {
-                const contact_t* c = &e->c[k];
-                if (c->a == i) { sp = sub(sp, c->P); st = sub(st, cross(c->ra, c->P)); }
-                if (c->b == i) { sp = add(sp, c->P); st = add(st, cross(c->rb, c->P)); }
-            }
-            body_t* b = &e->body[i];
-            b->v = add(b->v, scl(sp, b->inv_mass));
-            b->w = add(b->w, mv(&b->inv_iw, st));
-        }
+        apply_impulses(e);
+    }
+    /* remember the accumulated impulses for the next substep */
+    e->nwarm = e->nc;
+    for (int k = 0; k < e->nc; ++k) {
+        e->warm[k].key = e->c[k].key;
+        e->warm[k].ln = e->c[k].ln; e->warm[k].lt1 = e->c[k].lt1; e->warm[k].lt2 = e->c[k].lt2;
     }
 }
 
@@ -474,6 +513,7 @@ static void push_begin(env_t* e, const orc_config* cfg, const double* push) {
     double len = norm(d);
     e->push_dir = len > 0 ? scl(d, 1.0 / len) : V(1, 0, 0);
     e->n_move = (int)lround(len / (cfg->push_speed * cfg->dt));
+    e->nwarm = 0;   /* impulses are carried within one push only */
     double yaw = atan2(e->push_dir.y, e->push_dir.x);
     body_t* p = &e->pusher;
     p->x = V(push[0], push[1], cfg->pusher_z);
@@ -551,7 +591,7 @@ static void load(env_t* e, const orc_config* cfg, int nb, const double* st, cons
     memset(&e->pusher, 0, sizeof(e->pusher));
     e->pusher.h = V(cfg->pusher_half[0], cfg->pusher_half[1], cfg->pusher_half[2]);
     e->pusher.x = V(0, 0, 10.0); e->pusher.q = (qt){1, 0, 0, 0};
-    e->valid = 0; e->n_move = 0; e->status = 0; e->nc = 0;
+    e->valid = 0; e->n_move = 0; e->status = 0; e->nc = 0; e->nwarm = 0;
 }
 
 static void store(const env_t* e, double* st) {
@@ -568,10 +608,11 @@ static void store(const env_t* e, double* st) {
 static int env_alloc(env_t* e, int cap) {
     e->body = (body_t*)calloc(ORC_MAX_BODIES, sizeof(body_t));
     e->c = (contact_t*)calloc((size_t)cap, sizeof(contact_t));
+    e->warm = (warm_t*)calloc((size_t)cap, sizeof(warm_t));
     e->cap = cap;
-    return e->body && e->c;
+    return e->body && e->c && e->warm;
 }
-static void env_free(env_t* e) { free(e->body); free(e->c); }
+static void env_free(env_t* e) { free(e->body); free(e->c); free(e->warm); }
 
 static int check_env(int nb) { return nb >= 0 && nb <= ORC_MAX_BODIES; }
 

@@ -1,0 +1,54 @@
+// pmbs_kernels.h -- launch interface between the host library and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pmbs.h"
+
+namespace pmbs {
+
+// Constants of the push transition (float copies of pmbs_sim_config).
+struct Params {
+  float dt, gravity, margin, beta, slop, mu_plane, mu_pusher;
+  float phx, phy, phz, pusher_z, push_speed;
+  float tau_face, tau_edge, edge_eps;
+  int iters;
+};
+
+struct StepArgs {
+  float* state;             // SoA [13][stride]
+  const float* bconst;      // SoA [8][stride]: hx,hy,hz, inv mass, inv Ibody xyz, mu
+  const int* env_offset;    // [n_envs+1]
+  const float4* push;       // [n_envs] (x_s, y_s, x_e, y_e) or null
+  uint32_t* env_status;     // [n_envs]
+  int* dbg_count;           // collide-only outputs
+  float* dbg_contacts;
+  long long* stats;         // optional [n_envs][2]: sum over substeps of contacts, candidate pairs
+  int n_envs, env_base, n_substeps, stride, collide_only;
+  Params p;
+};
+
+struct RewardArgs {
+  const float* state;
+  const float* bconst;
+  const int* env_offset;
+  const int* target;
+  float* reward;
+  float* clearance;
+  int n_envs, stride;
+  float width;
+};
+
+struct PoolArgs {
+  float* state;
+  float* pool;
+  const int* env_offset;
+  const int* slots;
+  int n_envs, stride, pool_slots, pool_stride, to_pool;
+};
+
+hipError_t launch_pool(const PoolArgs& a, hipStream_t stream);
+hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream);
+hipError_t launch_reward(const RewardArgs& a, hipStream_t stream);
+
+}  // namespace pmbs

@@ -1,0 +1,1026 @@
+// pmbs_kernels.hip -- CDNA4 (gfx950) kernels of the batched push transition.
+//
+// One 64-lane wavefront advances one environment (cuboids on a plane plus a
+// kinematic box pusher) through a push: the batch expansion / simulation of
+// PMBS (Sec. IV-C), with the transition of Sec. III-A made explicit.
+//
+// Lane roles inside a wave (b = lane & 31):
+//   lane b       owns body b's position and linear velocity
+//   lane b + 32  owns body b's orientation, angular velocity, world inverse
+//                inertia (so two lanes carry every body)
+//   lane l       holds contacts l, l+64, l+128, ... in VGPR slots (K slots)
+// Shared state goes through LDS: body frames, the broadphase pair list, the
+// contact staging array (reused for the impulse exchange of the solver) and
+// per-lane polygon scratch for face clipping.
+//
+// Per substep (all in one launch, state stays in registers/LDS; HBM is
+// touched once in and once out per call):
+//   velocity stage -> frames -> sort-and-sweep broadphase -> box-plane and
+//   box-box/pusher-box contacts (15-axis SAT, Sutherland-Hodgman face
+//   clipping or edge-edge closest points) -> contact prep (mass splitting,
+//   Tonge et al. 2012) -> I projected-Jacobi iterations (normal clamp, then
+//   circular friction cone; per-body sums in contact-index order) ->
+//   symplectic position stage.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pmbs_kernels.h"
+
+namespace pmbs {
+
+constexpr int MAXB = 32;             // boxes (<= 31) + the pusher
+constexpr int PLANE = MAXB;          // LDS index of the table
+constexpr int NOBJ = MAXB + 1;
+constexpr int MAX_PAIRS = MAXB * (MAXB - 1) / 2;
+constexpr int CLIP_LANES = 32;       // pair lanes per narrowphase round
+constexpr int POLY = 8;              // clip polygon capacity
+
+// ------------------------------------------------------------------ vectors
+struct f3 { float x, y, z; };
+__device__ __forceinline__ f3 mk(float x, float y, float z) { return {x, y, z}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(f3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ f3 neg(f3 a) { return {-a.x, -a.y, -a.z}; }
+__device__ __forceinline__ f3 sel(bool c, f3 a, f3 b) { return {c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z}; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ f3 xyz(float4 v) { return {v.x, v.y, v.z}; }
+__device__ __forceinline__ float4 f4(f3 v, float w) { return make_float4(v.x, v.y, v.z, w); }
+__device__ __forceinline__ float comp(f3 v, int k) {
+  float r;
+  switch (k) {
+    case 0: r = v.x; break;
+    case 1: r = v.y; break;
+    default: r = v.z; break;
+  }
+  return r;
+}
+
+// ------------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int wave_excl_scan(int x, int* total) {
+  const int lane = threadIdx.x;
+  int v = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_up(v, d, 64);
+    if (lane >= d) v += y;
+  }
+  *total = __shfl(v, 63, 64);
+  return v - x;
+}
+
+__device__ __forceinline__ void wave_sync() { __syncthreads(); }
+
+// ------------------------------------------------------------------ LDS layout
+template <int K>
+struct Smem {
+  static constexpr int C = 64 * K;
+  float4 pos[NOBJ];                  // centre
+  float4 col[3][NOBJ];               // rotation columns (body axes in world)
+  float4 half[NOBJ];                 // hx, hy, hz, inverse mass
+  float4 iwa[NOBJ];                  // world inverse inertia xx, yy, zz, xy
+  float4 iwb[NOBJ];                  // xz, yz, mu, -
+  float4 vel[NOBJ];                  // solver snapshot: linear
+  float4 ang[NOBJ];                  // solver snapshot: angular
+  int cnt[NOBJ];                     // contacts touching each body (mass splitting)
+  float lo[3][MAXB], hi[3][MAXB];    // AABBs
+  int sorted[MAXB];
+  unsigned mask[MAXB];
+  unsigned short pairs[MAX_PAIRS];
+  int cab[C];                        // packed a | b << 8 | feature << 16 of each contact
+  int wkey[C];                       // previous substep's contact keys (sorted)
+  float wl[3][C];                    // and their accumulated impulses (n, t1, t2)
+  union {
+    float4 stage[C][2];              // narrowphase output: (p, sep), (n, -)
+    float imp[9][C];                 // solver exchange: P, ra x P, rb x P
+  } u;
+  float clip[2][POLY][3][CLIP_LANES];
+};
+
+// Contact key (a+1, b, feature) with the table as a = -1: strictly
+// increasing along the contact list, so the previous list is searchable.
+__device__ __forceinline__ int contact_key(int ab) {
+  const int a = ab & 255, b = (ab >> 8) & 255, f = ab >> 16;
+  return ((a == PLANE ? 0 : a + 1) << 16) | (b << 8) | f;
+}
+
+// ------------------------------------------------------------------ geometry
+struct Box {
+  f3 c, a0, a1, a2, h;
+};
+
+// switch (not a conditional on struct lvalues) keeps the boxes in registers
+__device__ __forceinline__ f3 axis(const Box& b, int k) {
+  f3 r;
+  switch (k) {
+    case 0: r = b.a0; break;
+    case 1: r = b.a1; break;
+    default: r = b.a2; break;
+  }
+  return r;
+}
+__device__ __forceinline__ float hcomp(const Box& b, int k) {
+  float r;
+  switch (k) {
+    case 0: r = b.h.x; break;
+    case 1: r = b.h.y; break;
+    default: r = b.h.z; break;
+  }
+  return r;
+}
+
+template <int K>
+__device__ __forceinline__ Box load_box(const Smem<K>& s, int i) {
+  Box b;
+  b.c = xyz(s.pos[i]);
+  b.a0 = xyz(s.col[0][i]);
+  b.a1 = xyz(s.col[1][i]);
+  b.a2 = xyz(s.col[2][i]);
+  b.h = xyz(s.half[i]);
+  return b;
+}
+
+__device__ __forceinline__ float radius_along(const Box& b, f3 L) {
+  return b.h.x * fabsf(dot(b.a0, L)) + b.h.y * fabsf(dot(b.a1, L)) + b.h.z * fabsf(dot(b.a2, L));
+}
+
+// candidate axis idx: 0-2 faces of A, 3-5 faces of B, 6-14 edge crosses
+// (axes are read from LDS so the loop need not be unrolled)
+template <int K>
+__device__ __forceinline__ bool sat_axis(const Smem<K>& s, int ia, int ib, int idx, float eps, f3* L) {
+  if (idx < 3) { *L = xyz(s.col[idx][ia]); return true; }
+  if (idx < 6) { *L = xyz(s.col[idx - 3][ib]); return true; }
+  f3 v = cross(xyz(s.col[(idx - 6) / 3][ia]), xyz(s.col[(idx - 6) % 3][ib]));
+  float len = sqrtf(dot(v, v));
+  if (len < eps) return false;
+  *L = v * (1.0f / len);
+  return true;
+}
+
+// max over the candidate axes of s(L) = |d.L| - r_A(L) - r_B(L)
+template <int K>
+__device__ __forceinline__ float sat_max(const Smem<K>& s, int ia, int ib, float eps) {
+  const Box A = load_box(s, ia), B = load_box(s, ib);
+  f3 d = B.c - A.c;
+  float best = -INFINITY;
+#pragma unroll 1
+  for (int idx = 0; idx < 15; ++idx) {
+    f3 L;
+    if (!sat_axis(s, ia, ib, idx, eps, &L)) continue;
+    float sv = fabsf(dot(d, L)) - radius_along(A, L) - radius_along(B, L);
+    best = fmaxf(best, sv);
+  }
+  return best;
+}
+
+struct SatResult {
+  float s;
+  int idx;  // -1: separated beyond the margin
+  f3 L;
+};
+
+// contact axis: early out when any s > margin; the kept axis starts at the
+// first candidate and is replaced only when s exceeds it by tau (face) or
+// tau_edge (edge axes)
+template <int K>
+__device__ __forceinline__ SatResult sat_best(const Smem<K>& s, int ia, int ib, const Params& p) {
+  const Box A = load_box(s, ia), B = load_box(s, ib);
+  SatResult r;
+  r.s = -INFINITY;
+  r.idx = -1;
+  r.L = mk(0, 0, 0);
+  f3 d = B.c - A.c;
+  int best = -1;
+#pragma unroll 1
+  for (int idx = 0; idx < 15; ++idx) {
+    f3 L;
+    if (!sat_axis(s, ia, ib, idx, p.edge_eps, &L)) continue;
+    float sv = fabsf(dot(d, L)) - radius_along(A, L) - radius_along(B, L);
+    if (sv > p.margin) { r.idx = -1; return r; }
+    float tau = idx < 6 ? p.tau_face : p.tau_edge;
+    if (best < 0 || sv > r.s + tau) { r.s = sv; best = idx; r.L = L; }
+  }
+  r.idx = best;
+  return r;
+}
+
+// ------------------------------------------------------------------ clipping
+template <int K>
+__device__ __forceinline__ f3 cl_get(const Smem<K>& s, int buf, int i, int lane) {
+  return mk(s.clip[buf][i][0][lane], s.clip[buf][i][1][lane], s.clip[buf][i][2][lane]);
+}
+template <int K>
+__device__ __forceinline__ void cl_put(Smem<K>& s, int buf, int i, int lane, f3 v) {
+  s.clip[buf][i][0][lane] = v.x;
+  s.clip[buf][i][1][lane] = v.y;
+  s.clip[buf][i][2][lane] = v.z;
+}
+
+// Sutherland-Hodgman against sign * ((x - f).dir) - h <= 0, from buffer
+// `src` (n points) into `dst`; at most POLY points are kept.
+template <int K>
+__device__ __forceinline__ int clip_stage(Smem<K>& s, int src, int n, int dst, int lane, f3 f, f3 dir, float sign, float h) {
+  if (n == 0) return 0;
+  int m = 0;
+  f3 prev = cl_get(s, src, n - 1, lane);
+  float dp = sign * dot(prev - f, dir) - h;
+  for (int i = 0; i < n; ++i) {
+    f3 cur = cl_get(s, src, i, lane);
+    float dc = sign * dot(cur - f, dir) - h;
+    if (dc <= 0.0f) {
+      if (dp > 0.0f) {
+        if (m < POLY) cl_put(s, dst, m, lane, prev + (cur - prev) * (dp / (dp - dc)));
+        ++m;
+      }
+      if (m < POLY) cl_put(s, dst, m, lane, cur);
+      ++m;
+    } else if (dp <= 0.0f) {
+      if (m < POLY) cl_put(s, dst, m, lane, prev + (cur - prev) * (dp / (dp - dc)));
+      ++m;
+    }
+    prev = cur;
+    dp = dc;
+  }
+  return m < POLY ? m : POLY;
+}
+
+// Axis k and half extent k of LDS body i (dynamic k reads LDS, so no
+// register array is indexed at run time).
+template <int K>
+__device__ __forceinline__ f3 lds_axis(const Smem<K>& s, int i, int k) {
+  return xyz(s.col[k][i]);
+}
+template <int K>
+__device__ __forceinline__ float lds_half(const Smem<K>& s, int i, int k) {
+  return reinterpret_cast<const float*>(&s.half[i])[k];
+}
+
+// Face-axis manifold: reference face of the axis owner, incident face of the
+// other box, clipped by the reference face's side planes (+u, -u, +v, -v).
+// Leaves the polygon in clip buffer 1 and returns its size; nref, f for sep.
+template <int K>
+__device__ __forceinline__ int face_manifold(Smem<K>& s, int ia, int ib, int idx, f3 n, int lane, f3* nref_out,
+                                             f3* f_out) {
+  const bool a_ref = idx < 3;
+  const int ri = a_ref ? ia : ib;
+  const int ii = a_ref ? ib : ia;
+  const int k = a_ref ? idx : idx - 3;
+  f3 nref = sel(a_ref, n, neg(n));
+  f3 f = xyz(s.pos[ri]) + nref * lds_half(s, ri, k);
+  int ku = k == 2 ? 0 : k + 1, kv = k == 0 ? 2 : k - 1;
+  f3 u = lds_axis(s, ri, ku), v = lds_axis(s, ri, kv);
+  float hu = lds_half(s, ri, ku), hv = lds_half(s, ri, kv);
+  int best = 0;
+  float bd = INFINITY;
+#pragma unroll
+  for (int fi = 0; fi < 6; ++fi) {
+    float sg = (fi & 1) ? -1.0f : 1.0f;
+    float dd = sg * dot(xyz(s.col[fi >> 1][ii]), nref);
+    if (dd < bd) { bd = dd; best = fi; }
+  }
+  int m = best >> 1;
+  float sg = (best & 1) ? -1.0f : 1.0f;
+  int pa = m == 2 ? 0 : m + 1, qa = m == 0 ? 2 : m - 1;
+  f3 fc = xyz(s.pos[ii]) + lds_axis(s, ii, m) * (sg * lds_half(s, ii, m));
+  f3 ep = lds_axis(s, ii, pa) * lds_half(s, ii, pa);
+  f3 eq = lds_axis(s, ii, qa) * lds_half(s, ii, qa);
+  cl_put(s, 1, 0, lane, fc + (ep + eq));
+  cl_put(s, 1, 1, lane, fc + (eq - ep));
+  cl_put(s, 1, 2, lane, fc - (ep + eq));
+  cl_put(s, 1, 3, lane, fc + (ep - eq));
+  int np = 4;
+  np = clip_stage(s, 1, np, 0, lane, f, u, 1.0f, hu);
+  np = clip_stage(s, 0, np, 1, lane, f, u, -1.0f, hu);
+  np = clip_stage(s, 1, np, 0, lane, f, v, 1.0f, hv);
+  np = clip_stage(s, 0, np, 1, lane, f, v, -1.0f, hv);
+  *nref_out = nref;
+  *f_out = f;
+  return np;
+}
+
+// Edge-axis contact: closest points of the two extreme edges parallel to the
+// axis's edge directions (A extreme along +n, B along -n; sign 0 -> +).
+template <int K>
+__device__ __forceinline__ f3 edge_point(const Smem<K>& s, int ia, int ib, int idx, f3 n) {
+  const int i = (idx - 6) / 3, j = (idx - 6) % 3;
+  f3 pa = xyz(s.pos[ia]), pb = xyz(s.pos[ib]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k != i) {
+      f3 ak = xyz(s.col[k][ia]);
+      pa = pa + ak * ((dot(n, ak) >= 0.0f ? 1.0f : -1.0f) * lds_half(s, ia, k));
+    }
+    if (k != j) {
+      f3 bk = xyz(s.col[k][ib]);
+      pb = pb + bk * ((dot(neg(n), bk) >= 0.0f ? 1.0f : -1.0f) * lds_half(s, ib, k));
+    }
+  }
+  f3 ai = lds_axis(s, ia, i), bj = lds_axis(s, ib, j);
+  float ha = lds_half(s, ia, i), hb = lds_half(s, ib, j);
+  f3 r = pa - pb;
+  float c = dot(ai, bj), ar = dot(ai, r), br = dot(bj, r);
+  float denom = 1.0f - c * c;
+  float ss = fminf(fmaxf((c * br - ar) / denom, -ha), ha);
+  float tt = br + ss * c;
+  if (tt < -hb || tt > hb) {
+    tt = fminf(fmaxf(tt, -hb), hb);
+    ss = fminf(fmaxf(tt * c - ar, -ha), ha);
+  }
+  f3 qa = pa + ai * ss, qb = pb + bj * tt;
+  return (qa + qb) * 0.5f;
+}
+
+// ------------------------------------------------------------------ contact record in VGPRs
+struct Contact {
+  int ab;
+  f3 n, t1, ra, rb;
+  float kn, kt1, kt2, vstar, mu;
+  float ln, lt1, lt2;
+};
+
+template <int K>
+__device__ __forceinline__ float eff_mass_side(const Smem<K>& s, int i, f3 r, f3 d) {
+  f3 cr = cross(r, d);
+  float4 ia = s.iwa[i], ib = s.iwb[i];
+  // symmetric Iw^-1 times cr
+  f3 m = mk(ia.x * cr.x + ia.w * cr.y + ib.x * cr.z,
+            ia.w * cr.x + ia.y * cr.y + ib.y * cr.z,
+            ib.x * cr.x + ib.y * cr.y + ia.z * cr.z);
+  return s.half[i].w + dot(cr, m);
+}
+
+template <int K>
+__device__ __forceinline__ void prep_contact(const Smem<K>& s, int c, const Params& p, int nwarm, Contact* ct) {
+  float4 s0 = s.u.stage[c][0], s1 = s.u.stage[c][1];
+  f3 pt = xyz(s0);
+  float sep = s0.w;
+  int ab = s.cab[c];
+  int a = ab & 255, b = (ab >> 8) & 255;
+  ct->ab = ab;
+  f3 n = xyz(s1);
+  ct->n = n;
+  ct->ra = pt - xyz(s.pos[a]);
+  ct->rb = pt - xyz(s.pos[b]);
+  float ax = fabsf(n.x), ay = fabsf(n.y), az = fabsf(n.z);
+  const int ei = (ax <= ay && ax <= az) ? 0 : (ay <= az ? 1 : 2);
+  f3 e = mk(ei == 0 ? 1.0f : 0.0f, ei == 1 ? 1.0f : 0.0f, ei == 2 ? 1.0f : 0.0f);
+  f3 t1 = cross(e, n);
+  t1 = t1 * (1.0f / sqrtf(dot(t1, t1)));
+  f3 t2 = cross(n, t1);
+  ct->t1 = t1;
+  float ca = (float)s.cnt[a], cb = (float)s.cnt[b];
+  ct->kn = 1.0f / (ca * eff_mass_side(s, a, ct->ra, n) + cb * eff_mass_side(s, b, ct->rb, n));
+  ct->kt1 = 1.0f / (ca * eff_mass_side(s, a, ct->ra, t1) + cb * eff_mass_side(s, b, ct->rb, t1));
+  ct->kt2 = 1.0f / (ca * eff_mass_side(s, a, ct->ra, t2) + cb * eff_mass_side(s, b, ct->rb, t2));
+  ct->mu = 0.5f * (s.iwb[a].z + s.iwb[b].z);
+  ct->vstar = sep > 0.0f ? -sep / p.dt : p.beta * fmaxf(-sep - p.slop, 0.0f) / p.dt;
+  // warm start from the previous substep's contact with the same key
+  ct->ln = ct->lt1 = ct->lt2 = 0.0f;
+  const int key = contact_key(ab);
+  int lo = 0, hi = nwarm - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int km = s.wkey[mid];
+    if (km == key) {
+      ct->ln = s.wl[0][mid];
+      ct->lt1 = s.wl[1][mid];
+      ct->lt2 = s.wl[2][mid];
+      break;
+    }
+    if (km < key) lo = mid + 1;
+    else hi = mid - 1;
+  }
+}
+
+// ------------------------------------------------------------------ the step kernel
+template <int K>
+__global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
+  __shared__ Smem<K> s;
+  constexpr int C = Smem<K>::C;
+  const Params& p = g.p;
+  const int lane = threadIdx.x;
+  const int b = lane & 31;
+  const int part = lane >> 5;
+  const int e = g.env_base + blockIdx.x;
+  if (e >= g.n_envs) return;
+  const int base = g.env_offset[e];
+  const int nb = g.env_offset[e + 1] - base;
+  const bool active = b < nb;
+  const int N = g.stride;
+  const float dt = p.dt;
+
+  // ---- load (coalesced SoA): part 0 linear, part 1 angular
+  f3 x = mk(0, 0, 0), v = mk(0, 0, 0), w = mk(0, 0, 0), h = mk(0, 0, 0), invI = mk(0, 0, 0);
+  float q0 = 1, q1 = 0, q2 = 0, q3 = 0, invm = 0, mu = 0;
+  if (active) {
+    const int i = base + b;
+    const float* st = g.state;
+    const float* bc = g.bconst;
+    if (part == 0) {
+      x = mk(st[0 * N + i], st[1 * N + i], st[2 * N + i]);
+      v = mk(st[7 * N + i], st[8 * N + i], st[9 * N + i]);
+      invm = bc[3 * N + i];
+    } else {
+      q0 = st[3 * N + i]; q1 = st[4 * N + i]; q2 = st[5 * N + i]; q3 = st[6 * N + i];
+      w = mk(st[10 * N + i], st[11 * N + i], st[12 * N + i]);
+      invI = mk(bc[4 * N + i], bc[5 * N + i], bc[6 * N + i]);
+    }
+    h = mk(bc[0 * N + i], bc[1 * N + i], bc[2 * N + i]);
+    mu = bc[7 * N + i];
+  }
+  if (lane == 0) {
+    s.pos[PLANE] = make_float4(0, 0, 0, 0);
+    s.col[0][PLANE] = make_float4(1, 0, 0, 0);
+    s.col[1][PLANE] = make_float4(0, 1, 0, 0);
+    s.col[2][PLANE] = make_float4(0, 0, 1, 0);
+    s.half[PLANE] = make_float4(0, 0, 0, 0);
+    s.iwa[PLANE] = make_float4(0, 0, 0, 0);
+    s.iwb[PLANE] = make_float4(0, 0, p.mu_plane, 0);
+    s.vel[PLANE] = make_float4(0, 0, 0, 0);
+    s.ang[PLANE] = make_float4(0, 0, 0, 0);
+    s.cnt[PLANE] = 1;
+  }
+
+  // ---- push begin (uniform across the wave)
+  float4 push = g.push ? g.push[e] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  bool have_push = g.push != nullptr;
+  f3 pdir = mk(1, 0, 0);
+  int n_move = 0;
+  f3 xp = mk(0, 0, 10.0f);
+  f3 pc0 = mk(1, 0, 0), pc1 = mk(0, 1, 0);
+  if (have_push) {
+    float dx = push.z - push.x, dy = push.w - push.y;
+    float len = sqrtf(dx * dx + dy * dy);
+    if (len > 0.0f) pdir = mk(dx / len, dy / len, 0.0f);
+    n_move = (int)roundf(len / (p.push_speed * dt));
+    xp = mk(push.x, push.y, p.pusher_z);
+    float yaw = atan2f(pdir.y, pdir.x);
+    float cy = cosf(0.5f * yaw), sy = sinf(0.5f * yaw);
+    // rotation about z from the half-angle quaternion (cy, 0, 0, sy)
+    pc0 = mk(1.0f - 2.0f * sy * sy, 2.0f * cy * sy, 0.0f);
+    pc1 = mk(-2.0f * cy * sy, 1.0f - 2.0f * sy * sy, 0.0f);
+  }
+  const f3 ph = mk(p.phx, p.phy, p.phz);
+
+  // frames of the bodies + the pusher entry (index nb)
+  auto write_frames = [&](f3 vp) {
+    if (active) {
+      if (part == 0) {
+        s.pos[b] = f4(x, 0.0f);
+        s.half[b] = f4(h, invm);
+      } else {
+        float r00 = 1 - 2 * (q2 * q2 + q3 * q3), r01 = 2 * (q1 * q2 - q0 * q3), r02 = 2 * (q1 * q3 + q0 * q2);
+        float r10 = 2 * (q1 * q2 + q0 * q3), r11 = 1 - 2 * (q1 * q1 + q3 * q3), r12 = 2 * (q2 * q3 - q0 * q1);
+        float r20 = 2 * (q1 * q3 - q0 * q2), r21 = 2 * (q2 * q3 + q0 * q1), r22 = 1 - 2 * (q1 * q1 + q2 * q2);
+        s.col[0][b] = make_float4(r00, r10, r20, 0.0f);
+        s.col[1][b] = make_float4(r01, r11, r21, 0.0f);
+        s.col[2][b] = make_float4(r02, r12, r22, 0.0f);
+        // Iw^-1 = R diag(invI) R^T
+        float xx = r00 * invI.x * r00 + r01 * invI.y * r01 + r02 * invI.z * r02;
+        float yy = r10 * invI.x * r10 + r11 * invI.y * r11 + r12 * invI.z * r12;
+        float zz = r20 * invI.x * r20 + r21 * invI.y * r21 + r22 * invI.z * r22;
+        float xy = r00 * invI.x * r10 + r01 * invI.y * r11 + r02 * invI.z * r12;
+        float xz = r00 * invI.x * r20 + r01 * invI.y * r21 + r02 * invI.z * r22;
+        float yz = r10 * invI.x * r20 + r11 * invI.y * r21 + r12 * invI.z * r22;
+        s.iwa[b] = make_float4(xx, yy, zz, xy);
+        s.iwb[b] = make_float4(xz, yz, mu, 0.0f);
+      }
+    }
+    if (lane == 32) {
+      s.pos[nb] = f4(xp, 0.0f);
+      s.col[0][nb] = f4(pc0, 0.0f);
+      s.col[1][nb] = f4(pc1, 0.0f);
+      s.col[2][nb] = make_float4(0, 0, 1, 0);
+      s.half[nb] = f4(ph, 0.0f);
+      s.iwa[nb] = make_float4(0, 0, 0, 0);
+      s.iwb[nb] = make_float4(0, 0, p.mu_pusher, 0);
+      s.vel[nb] = f4(vp, 0.0f);
+      s.ang[nb] = make_float4(0, 0, 0, 0);
+      s.cnt[nb] = 1;
+    }
+  };
+
+  // validity of the start pose: SAT separation from every box must be > 0
+  bool valid = false;
+  if (have_push) {
+    write_frames(mk(0, 0, 0));
+    wave_sync();
+    bool bad = false;
+    if (active && part == 0) {
+      bad = !(sat_max(s, b, nb, p.edge_eps) > 0.0f);
+    }
+    valid = __ballot(bad) == 0;
+    wave_sync();
+  }
+  if (!valid) {
+    xp = mk(0, 0, 10.0f);
+    pc0 = mk(1, 0, 0);
+    pc1 = mk(0, 1, 0);
+    n_move = 0;
+  }
+  uint32_t status = (have_push && !valid) ? PMBS_ENV_PUSH_INVALID : 0u;
+
+  // contact slots
+  Contact ct[K];
+  unsigned long long mA[K], mB[K];
+
+  const int n_obj = nb + 1;
+  const int n_sub = g.collide_only ? 1 : g.n_substeps;
+  long long stat_nc = 0, stat_pairs = 0;
+  int nwarm = 0;  // impulses are carried within one push only
+  for (int k = 0; k < n_sub; ++k) {
+    // ---- 1. velocity stage
+    if (active && part == 0) v.z -= p.gravity * dt;
+    const float vs = (valid && k < n_move) ? p.push_speed : 0.0f;
+    f3 vp = pdir * vs;
+    if (g.collide_only) vp = mk(0, 0, 0);
+
+    // ---- 2. frames
+    write_frames(vp);
+    wave_sync();
+
+    // ---- 3. broadphase: AABBs, rank sort on min-x, sweep
+    if (lane < n_obj) {
+      f3 c = xyz(s.pos[lane]);
+      f3 a0 = xyz(s.col[0][lane]), a1 = xyz(s.col[1][lane]), a2 = xyz(s.col[2][lane]);
+      f3 hh = xyz(s.half[lane]);
+      float ex = fabsf(a0.x) * hh.x + fabsf(a1.x) * hh.y + fabsf(a2.x) * hh.z + p.margin;
+      float ey = fabsf(a0.y) * hh.x + fabsf(a1.y) * hh.y + fabsf(a2.y) * hh.z + p.margin;
+      float ez = fabsf(a0.z) * hh.x + fabsf(a1.z) * hh.y + fabsf(a2.z) * hh.z + p.margin;
+      s.lo[0][lane] = c.x - ex; s.hi[0][lane] = c.x + ex;
+      s.lo[1][lane] = c.y - ey; s.hi[1][lane] = c.y + ey;
+      s.lo[2][lane] = c.z - ez; s.hi[2][lane] = c.z + ez;
+      s.mask[lane] = 0u;
+    }
+    wave_sync();
+    if (lane < n_obj) {
+      // NaN keys sort last (ranks stay a permutation whatever the state holds)
+      float key = s.lo[0][lane];
+      key = key == key ? key : INFINITY;
+      int rank = 0;
+      for (int j = 0; j < n_obj; ++j) {
+        float kj = s.lo[0][j];
+        kj = kj == kj ? kj : INFINITY;
+        rank += (kj < key || (kj == key && j < lane)) ? 1 : 0;
+      }
+      s.sorted[rank] = lane;
+    }
+    wave_sync();
+    if (lane < n_obj) {
+      int i = s.sorted[lane] & (MAXB - 1);
+      float hix = s.hi[0][i], loy = s.lo[1][i], hiy = s.hi[1][i], loz = s.lo[2][i], hiz = s.hi[2][i];
+      for (int q = lane + 1; q < n_obj; ++q) {
+        int j = s.sorted[q] & (MAXB - 1);
+        if (s.lo[0][j] > hix) break;
+        if (loy <= s.hi[1][j] && s.lo[1][j] <= hiy && loz <= s.hi[2][j] && s.lo[2][j] <= hiz) {
+          int lo_i = i < j ? i : j, hi_i = i < j ? j : i;
+          atomicOr(&s.mask[lo_i], 1u << hi_i);
+        }
+      }
+    }
+    wave_sync();
+    int n_pairs;
+    {
+      unsigned m = lane < n_obj ? s.mask[lane] : 0u;
+      int off = wave_excl_scan(__popc(m), &n_pairs);
+      int t = 0;
+      while (m) {
+        int j = __builtin_ctz(m);
+        m &= m - 1;
+        if (off + t < MAX_PAIRS) s.pairs[off + t] = (unsigned short)((lane << 8) | j);
+        ++t;
+      }
+    }
+    wave_sync();
+
+    // ---- 4a. box-plane contacts (body order, vertex order)
+    int nc_raw;
+    {
+      f3 a0 = mk(0, 0, 0), a1 = mk(0, 0, 0), a2 = mk(0, 0, 0);
+      unsigned flags = 0;
+      if (active && part == 0) {
+        a0 = xyz(s.col[0][b]); a1 = xyz(s.col[1][b]); a2 = xyz(s.col[2][b]);
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
+          float vz = x.z + (a0.z * sx + a1.z * sy + a2.z * sz);
+          if (vz <= p.margin) flags |= 1u << kk;
+        }
+      }
+      int total;
+      int off = wave_excl_scan(__popc(flags), &total);
+      int t = 0;
+      while (flags) {
+        const int kk = __builtin_ctz(flags);
+        flags &= flags - 1;
+        float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
+        f3 vtx = x + mk(a0.x * sx + a1.x * sy + a2.x * sz, a0.y * sx + a1.y * sy + a2.y * sz,
+                        a0.z * sx + a1.z * sy + a2.z * sz);
+        const int c = off + t++;
+        if (c < C) {
+          s.u.stage[c][0] = f4(vtx - mk(0, 0, 0.5f * vtx.z), vtx.z);
+          s.u.stage[c][1] = make_float4(0, 0, 1, 0);
+          s.cab[c] = PLANE | (b << 8) | (kk << 16);
+        }
+      }
+      nc_raw = total;
+    }
+
+    // ---- 4b. box-box and pusher-box contacts, pairs in lexicographic order
+    for (int r0 = 0; r0 < n_pairs; r0 += CLIP_LANES) {
+      const int pi = r0 + lane;
+      const bool has = lane < CLIP_LANES && pi < n_pairs && pi < MAX_PAIRS;
+      int cnt = 0, np = 0, ia = 0, ib = 0;
+      SatResult sr;
+      sr.idx = -1;
+      f3 n = mk(0, 0, 0), nref = mk(0, 0, 0), fref = mk(0, 0, 0), ept = mk(0, 0, 0);
+      if (has) {
+        unsigned pr = s.pairs[pi];
+        ia = pr >> 8;
+        ib = pr & 255;
+        sr = sat_best(s, ia, ib, p);
+        if (sr.idx >= 0) {
+          f3 d = xyz(s.pos[ib]) - xyz(s.pos[ia]);
+          n = sel(dot(d, sr.L) >= 0.0f, sr.L, neg(sr.L));
+          if (sr.idx < 6) {
+            np = face_manifold(s, ia, ib, sr.idx, n, lane, &nref, &fref);
+            for (int i = 0; i < np; ++i) {
+              float sep = dot(nref, cl_get(s, 1, i, lane) - fref);
+              cnt += sep <= p.margin ? 1 : 0;
+            }
+          } else {
+            ept = edge_point(s, ia, ib, sr.idx, n);
+            cnt = 1;
+          }
+        }
+      }
+      int total;
+      int off = nc_raw + wave_excl_scan(cnt, &total);
+      if (has && cnt > 0) {
+        const int ab = ia | (ib << 8);
+        if (sr.idx < 6) {
+          int t = 0;
+          for (int i = 0; i < np; ++i) {
+            f3 pt = cl_get(s, 1, i, lane);
+            float sep = dot(nref, pt - fref);
+            if (sep <= p.margin) {
+              const int c = off + t;
+              if (c < C) {
+                s.u.stage[c][0] = f4(pt - nref * (0.5f * sep), sep);
+                s.u.stage[c][1] = f4(n, 0.0f);
+                s.cab[c] = ab | (t << 16);
+              }
+              ++t;
+            }
+          }
+        } else if (off < C) {
+          s.u.stage[off][0] = f4(ept, sr.s);
+          s.u.stage[off][1] = f4(n, 0.0f);
+          s.cab[off] = ab;
+        }
+      }
+      nc_raw += total;
+    }
+    if (nc_raw > C) status |= PMBS_ENV_CONTACT_OVERFLOW;
+    const int nc = nc_raw < C ? nc_raw : C;
+    stat_nc += nc;
+    stat_pairs += n_pairs;
+    wave_sync();
+
+    if (g.collide_only) {
+      if (lane == 0) g.dbg_count[e] = nc;
+      float* out = g.dbg_contacts + (size_t)e * C * 9;
+      for (int c = lane; c < nc; c += 64) {
+        float4 s0 = s.u.stage[c][0], s1 = s.u.stage[c][1];
+        int ab = s.cab[c];
+        int a = ab & 255, bb = (ab >> 8) & 255;
+        out[c * 9 + 0] = a == PLANE ? -1.0f : (float)a;
+        out[c * 9 + 1] = (float)bb;
+        out[c * 9 + 2] = s0.x; out[c * 9 + 3] = s0.y; out[c * 9 + 4] = s0.z;
+        out[c * 9 + 5] = s1.x; out[c * 9 + 6] = s1.y; out[c * 9 + 7] = s1.z;
+        out[c * 9 + 8] = s0.w;
+      }
+      if (lane == 0) g.env_status[e] = status;
+      return;
+    }
+
+    // ---- 5. incidence masks per body (contact-index order) and counts
+    if (active) {
+#pragma unroll
+      for (int sl = 0; sl < K; ++sl) {
+        unsigned long long ma = 0, mb = 0;
+        const int c_end = min(nc, 64 * (sl + 1));
+        for (int c = 64 * sl; c < c_end; ++c) {
+          int ab = s.cab[c];
+          unsigned long long bit = 1ull << (c - 64 * sl);
+          if ((ab & 255) == b) ma |= bit;
+          if (((ab >> 8) & 255) == b) mb |= bit;
+        }
+        mA[sl] = ma;
+        mB[sl] = mb;
+      }
+      if (part == 0) {
+        int cn = 0;
+#pragma unroll
+        for (int sl = 0; sl < K; ++sl) cn += __popcll(mA[sl] | mB[sl]);
+        s.cnt[b] = cn;
+      }
+    }
+    wave_sync();
+
+    // ---- 6. contact prep into VGPR slots
+#pragma unroll
+    for (int sl = 0; sl < K; ++sl) {
+      const int c = 64 * sl + lane;
+      if (c < nc) prep_contact(s, c, p, nwarm, &ct[sl]);
+    }
+
+    // ---- 7. projected Jacobi, I iterations
+    f3 iw_d = mk(0, 0, 0), iw_o = mk(0, 0, 0);  // Iw^-1 diagonal / off-diagonal (xy, xz, yz)
+    if (active && part == 1) {
+      float4 ia = s.iwa[b], ib = s.iwb[b];
+      iw_d = mk(ia.x, ia.y, ia.z);
+      iw_o = mk(ia.w, ib.x, ib.y);
+    }
+    // it = -1 applies the warm-start impulses; it >= 0 are the Jacobi iterations
+    wave_sync();
+    for (int it = -1; it < p.iters; ++it) {
+      if (it >= 0) {
+        if (active) {
+          if (part == 0) s.vel[b] = f4(v, 0.0f);
+          else s.ang[b] = f4(w, 0.0f);
+        }
+        wave_sync();
+      }
+#pragma unroll
+      for (int sl = 0; sl < K; ++sl) {
+        const int c = 64 * sl + lane;
+        if (c < nc) {
+          Contact& q = ct[sl];
+          const f3 t2 = cross(q.n, q.t1);
+          f3 P;
+          if (it < 0) {
+            P = q.n * q.ln + (q.t1 * q.lt1 + t2 * q.lt2);
+          } else {
+            const int a = q.ab & 255, bb = (q.ab >> 8) & 255;
+            f3 va = xyz(s.vel[a]), wa = xyz(s.ang[a]), vb = xyz(s.vel[bb]), wb = xyz(s.ang[bb]);
+            f3 u = (vb + cross(wb, q.rb)) - (va + cross(wa, q.ra));
+            float ln = fmaxf(q.ln + q.kn * (q.vstar - dot(u, q.n)), 0.0f);
+            float dln = ln - q.ln;
+            q.ln = ln;
+            float lt1 = q.lt1 - q.kt1 * dot(u, q.t1);
+            float lt2 = q.lt2 - q.kt2 * dot(u, t2);
+            float lim = q.mu * ln, mag2 = lt1 * lt1 + lt2 * lt2;
+            if (mag2 > lim * lim) {
+              float sc = lim / sqrtf(mag2);
+              lt1 *= sc;
+              lt2 *= sc;
+            }
+            float dl1 = lt1 - q.lt1, dl2 = lt2 - q.lt2;
+            q.lt1 = lt1;
+            q.lt2 = lt2;
+            P = q.n * dln + (q.t1 * dl1 + t2 * dl2);
+          }
+          f3 Ta = cross(q.ra, P), Tb = cross(q.rb, P);
+          s.u.imp[0][c] = P.x; s.u.imp[1][c] = P.y; s.u.imp[2][c] = P.z;
+          s.u.imp[3][c] = Ta.x; s.u.imp[4][c] = Ta.y; s.u.imp[5][c] = Ta.z;
+          s.u.imp[6][c] = Tb.x; s.u.imp[7][c] = Tb.y; s.u.imp[8][c] = Tb.z;
+        }
+      }
+      wave_sync();
+      if (active) {
+        f3 acc = mk(0, 0, 0);
+        const int o = part == 0 ? 0 : 3;
+#pragma unroll
+        for (int sl = 0; sl < K; ++sl) {
+          unsigned long long m = mA[sl] | mB[sl];
+          while (m) {
+            int bit = __builtin_ctzll(m);
+            m &= m - 1;
+            const int c = 64 * sl + bit;
+            const bool side_b = (mB[sl] >> bit) & 1ull;
+            const int oo = (part == 1 && side_b) ? 6 : o;
+            f3 val = mk(s.u.imp[oo][c], s.u.imp[oo + 1][c], s.u.imp[oo + 2][c]);
+            acc = side_b ? acc + val : acc - val;
+          }
+        }
+        if (part == 0) {
+          v = v + acc * invm;
+        } else {
+          w = w + mk(iw_d.x * acc.x + iw_o.x * acc.y + iw_o.y * acc.z,
+                     iw_o.x * acc.x + iw_d.y * acc.y + iw_o.z * acc.z,
+                     iw_o.y * acc.x + iw_o.z * acc.y + iw_d.z * acc.z);
+        }
+      }
+    }
+    // remember this substep's accumulated impulses by key
+#pragma unroll
+    for (int sl = 0; sl < K; ++sl) {
+      const int c = 64 * sl + lane;
+      if (c < nc) {
+        s.wkey[c] = contact_key(ct[sl].ab);
+        s.wl[0][c] = ct[sl].ln;
+        s.wl[1][c] = ct[sl].lt1;
+        s.wl[2][c] = ct[sl].lt2;
+      }
+    }
+    nwarm = nc;
+
+    // ---- 8. position stage
+    if (active) {
+      if (part == 0) {
+        x = x + v * dt;
+      } else {
+        float dw = -(w.x * q1 + w.y * q2 + w.z * q3);
+        float dx = q0 * w.x + (w.y * q3 - w.z * q2);
+        float dy = q0 * w.y + (w.z * q1 - w.x * q3);
+        float dz = q0 * w.z + (w.x * q2 - w.y * q1);
+        float hd = 0.5f * dt;
+        q0 += hd * dw; q1 += hd * dx; q2 += hd * dy; q3 += hd * dz;
+        float l = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        q0 /= l; q1 /= l; q2 /= l; q3 /= l;
+      }
+    }
+    xp = xp + vp * dt;
+    wave_sync();
+  }
+
+  // ---- write back
+  bool bad = false;
+  if (active) {
+    const int i = base + b;
+    float* st = g.state;
+    if (part == 0) {
+      st[0 * N + i] = x.x; st[1 * N + i] = x.y; st[2 * N + i] = x.z;
+      st[7 * N + i] = v.x; st[8 * N + i] = v.y; st[9 * N + i] = v.z;
+      bad = !(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z));
+    } else {
+      st[3 * N + i] = q0; st[4 * N + i] = q1; st[5 * N + i] = q2; st[6 * N + i] = q3;
+      st[10 * N + i] = w.x; st[11 * N + i] = w.y; st[12 * N + i] = w.z;
+      bad = !(isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3) && isfinite(w.x) && isfinite(w.y) &&
+              isfinite(w.z));
+    }
+  }
+  if (__ballot(bad) != 0) status |= PMBS_ENV_NONFINITE;
+  if (lane == 0) {
+    g.env_status[e] = status;
+    if (g.stats) {
+      g.stats[2 * e] = stat_nc;
+      g.stats[2 * e + 1] = stat_pairs;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ state pool
+// env e <-> pool slot slots[e] (slot < 0: env left alone).  Pool slot layout
+// [13][pool_stride]; env bodies are the packed rows env_offset[e]...
+__global__ __launch_bounds__(64) void pool_kernel(PoolArgs g) {
+  const int e = blockIdx.x;
+  if (e >= g.n_envs) return;
+  const int slot = g.slots[e];
+  if (slot < 0 || slot >= g.pool_slots) return;
+  const int base = g.env_offset[e];
+  const int nb = g.env_offset[e + 1] - base;
+  if (nb > g.pool_stride) return;
+  float* pool = g.pool + (size_t)slot * 13 * g.pool_stride;
+  for (int t = threadIdx.x; t < 13 * nb; t += 64) {
+    const int r = t / nb, i = t - r * nb;
+    float* env_p = g.state + (size_t)r * g.stride + base + i;
+    float* pool_p = pool + (size_t)r * g.pool_stride + i;
+    if (g.to_pool) *pool_p = *env_p;
+    else *env_p = *pool_p;
+  }
+}
+
+// ------------------------------------------------------------------ reward
+// Footprint of a box = projection of the box onto the table plane (a
+// zonotope with generators h_k * a_k projected).  Overlap test: separating
+// axis among the generators' normals.  Distance when disjoint: minimum over
+// projected vertices of one against projected box edges of the other (the
+// silhouette edges are among them).
+struct Foot {
+  float cx, cy;
+  float gx[3], gy[3];
+};
+
+__device__ __forceinline__ float seg_dist(float px, float py, float ax, float ay, float bx, float by) {
+  float dx = bx - ax, dy = by - ay;
+  float l2 = dx * dx + dy * dy;
+  float t = l2 > 0.0f ? ((px - ax) * dx + (py - ay) * dy) / l2 : 0.0f;
+  t = fminf(fmaxf(t, 0.0f), 1.0f);
+  float ex = ax + t * dx - px, ey = ay + t * dy - py;
+  return sqrtf(ex * ex + ey * ey);
+}
+
+__device__ __forceinline__ void foot_vertex(const Foot& f, int k, float* x, float* y) {
+  float sx = (k & 1) ? 1.0f : -1.0f, sy = (k & 2) ? 1.0f : -1.0f, sz = (k & 4) ? 1.0f : -1.0f;
+  *x = f.cx + (f.gx[0] * sx + f.gx[1] * sy + f.gx[2] * sz);
+  *y = f.cy + (f.gy[0] * sx + f.gy[1] * sy + f.gy[2] * sz);
+}
+
+__device__ float foot_point_dist(const Foot& P, const Foot& Q) {
+  // min over vertices of P to the 12 projected edges of Q
+  float best = INFINITY;
+  for (int i = 0; i < 8; ++i) {
+    float px, py;
+    foot_vertex(P, i, &px, &py);
+    for (int a = 0; a < 8; ++a) {
+      for (int bit = 1; bit < 8; bit <<= 1) {
+        if (a & bit) continue;
+        float ax, ay, bx, by;
+        foot_vertex(Q, a, &ax, &ay);
+        foot_vertex(Q, a | bit, &bx, &by);
+        best = fminf(best, seg_dist(px, py, ax, ay, bx, by));
+      }
+    }
+  }
+  return best;
+}
+
+__device__ float foot_distance(const Foot& P, const Foot& Q) {
+  float dx = Q.cx - P.cx, dy = Q.cy - P.cy;
+  bool sep = false;
+  for (int pass = 0; pass < 2; ++pass) {
+    const Foot& F = pass ? Q : P;
+    for (int k = 0; k < 3; ++k) {
+      float lx = -F.gy[k], ly = F.gx[k];
+      float rp = fabsf(P.gx[0] * lx + P.gy[0] * ly) + fabsf(P.gx[1] * lx + P.gy[1] * ly) +
+                 fabsf(P.gx[2] * lx + P.gy[2] * ly);
+      float rq = fabsf(Q.gx[0] * lx + Q.gy[0] * ly) + fabsf(Q.gx[1] * lx + Q.gy[1] * ly) +
+                 fabsf(Q.gx[2] * lx + Q.gy[2] * ly);
+      if (fabsf(dx * lx + dy * ly) > rp + rq) sep = true;
+    }
+  }
+  if (!sep) return 0.0f;
+  return fminf(foot_point_dist(P, Q), foot_point_dist(Q, P));
+}
+
+__device__ Foot make_foot(const float* st, const float* bc, int N, int i) {
+  float q0 = st[3 * N + i], q1 = st[4 * N + i], q2 = st[5 * N + i], q3 = st[6 * N + i];
+  float hx = bc[0 * N + i], hy = bc[1 * N + i], hz = bc[2 * N + i];
+  Foot f;
+  f.cx = st[0 * N + i];
+  f.cy = st[1 * N + i];
+  // first two rows of the rotation matrix, columns scaled by the half extents
+  f.gx[0] = (1 - 2 * (q2 * q2 + q3 * q3)) * hx;
+  f.gx[1] = 2 * (q1 * q2 - q0 * q3) * hy;
+  f.gx[2] = 2 * (q1 * q3 + q0 * q2) * hz;
+  f.gy[0] = 2 * (q1 * q2 + q0 * q3) * hx;
+  f.gy[1] = (1 - 2 * (q1 * q1 + q3 * q3)) * hy;
+  f.gy[2] = 2 * (q2 * q3 - q0 * q1) * hz;
+  return f;
+}
+
+__global__ __launch_bounds__(64) void reward_kernel(RewardArgs g) {
+  const int e = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (e >= g.n_envs) return;
+  const int base = g.env_offset[e];
+  const int nb = g.env_offset[e + 1] - base;
+  const int t = g.target[e];
+  float d = INFINITY;
+  if (t >= 0 && t < nb) {
+    Foot T = make_foot(g.state, g.bconst, g.stride, base + t);
+    for (int j = lane; j < nb; j += 64) {
+      if (j == t) continue;
+      Foot J = make_foot(g.state, g.bconst, g.stride, base + j);
+      d = fminf(d, foot_distance(T, J));
+    }
+  } else {
+    d = NAN;
+  }
+  for (int off = 32; off > 0; off >>= 1) d = fminf(d, __shfl_xor(d, off, 64));
+  if (lane == 0) {
+    if (g.clearance) g.clearance[e] = d;
+    g.reward[e] = d > g.width ? 1.0f : d / g.width;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream) {
+  const int n = a.n_envs - a.env_base;
+  if (n <= 0) return hipSuccess;
+  if (max_contacts <= 256) {
+    hipLaunchKernelGGL(step_kernel<4>, dim3(n), dim3(64), 0, stream, a);
+  } else {
+    hipLaunchKernelGGL(step_kernel<8>, dim3(n), dim3(64), 0, stream, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pool(const PoolArgs& a, hipStream_t stream) {
+  if (a.n_envs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pool_kernel, dim3(a.n_envs), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reward(const RewardArgs& a, hipStream_t stream) {
+  if (a.n_envs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reward_kernel, dim3(a.n_envs), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace pmbs

@@ -1,0 +1,466 @@
+// pmbs_sim.cpp -- host side of the C ABI (include/pmbs.h): workspace carving,
+// input validation, uploads and kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pmbs.h"
+#include "pmbs_internal.h"
+#include "pmbs_kernels.h"
+
+namespace {
+thread_local std::string g_last_error;
+}  // namespace
+
+namespace pmbs {
+
+pmbs_status fail(pmbs_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+pmbs_status hip_fail(hipError_t e, const char* what) {
+  return fail(PMBS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace regions, in order.  Every region starts 256-byte aligned.
+struct Layout {
+  size_t state, bconst, env_offset, push, status, target, reward, clearance, slots, stats, pool, total;
+};
+
+static Layout layout_of(const pmbs_sim_config& c) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  const size_t nb = (size_t)c.max_bodies, ne = (size_t)c.max_envs;
+  L.state = take(13 * nb * sizeof(float));
+  L.bconst = take(8 * nb * sizeof(float));
+  L.env_offset = take((ne + 1) * sizeof(int32_t));
+  L.push = take(ne * 4 * sizeof(float));
+  L.status = take(ne * sizeof(uint32_t));
+  L.target = take(ne * sizeof(int32_t));
+  L.reward = take(ne * sizeof(float));
+  L.clearance = take(ne * sizeof(float));
+  L.slots = take(ne * sizeof(int32_t));
+  L.stats = take(ne * 2 * sizeof(long long));
+  L.pool = take((size_t)c.pool_slots * (size_t)c.pool_stride * 13 * sizeof(float));
+  L.total = o;
+  return L;
+}
+
+static pmbs_status check_config(const pmbs_sim_config* c) {
+  if (!c) return fail(PMBS_ERR_INVALID_ARG, "config is null");
+  if (c->max_envs <= 0 || c->max_bodies <= 0) return fail(PMBS_ERR_INVALID_ARG, "max_envs and max_bodies must be > 0");
+  if (c->max_contacts != 256 && c->max_contacts != 512)
+    return fail(PMBS_ERR_INVALID_ARG, "max_contacts must be 256 or 512 (got %d)", c->max_contacts);
+  if (c->solver_iters < 0 || c->solver_iters > 1000) return fail(PMBS_ERR_INVALID_ARG, "solver_iters out of range");
+  if (c->pool_slots < 0 || c->pool_stride < 0) return fail(PMBS_ERR_INVALID_ARG, "pool sizes must be >= 0");
+  if (c->pool_slots > 0 && (c->pool_stride <= 0 || c->pool_stride > PMBS_MAX_BODIES_PER_ENV))
+    return fail(PMBS_ERR_INVALID_ARG, "pool_stride must be in [1, %d]", PMBS_MAX_BODIES_PER_ENV);
+  if (!(c->dt > 0) || !(c->push_speed > 0) || !(c->margin >= 0))
+    return fail(PMBS_ERR_INVALID_ARG, "dt and push_speed must be > 0, margin >= 0");
+  for (int k = 0; k < 3; ++k)
+    if (!(c->pusher_half[k] > 0)) return fail(PMBS_ERR_INVALID_ARG, "pusher half extents must be > 0");
+  return PMBS_OK;
+}
+
+Params params_of(const pmbs_sim_config& c) {
+  Params p;
+  p.dt = c.dt;
+  p.gravity = c.gravity;
+  p.margin = c.margin;
+  p.beta = c.beta;
+  p.slop = c.slop;
+  p.mu_plane = c.mu_plane;
+  p.mu_pusher = c.mu_pusher;
+  p.phx = c.pusher_half[0];
+  p.phy = c.pusher_half[1];
+  p.phz = c.pusher_half[2];
+  p.pusher_z = c.pusher_z;
+  p.push_speed = c.push_speed;
+  p.tau_face = c.tau_face;
+  p.tau_edge = c.tau_edge;
+  p.edge_eps = c.edge_eps;
+  p.iters = c.solver_iters;
+  return p;
+}
+
+// Host pushes are copied into the workspace (the caller may free them on
+// return); device pushes are read in place when the stream reaches the launch.
+static pmbs_status stage_push(pmbs_sim_t* sim, const float* push, int32_t push_is_device, const float4** d_push) {
+  if (!push) {
+    *d_push = nullptr;
+    return PMBS_OK;
+  }
+  if (push_is_device) {
+    *d_push = reinterpret_cast<const float4*>(push);
+    return PMBS_OK;
+  }
+  const size_t bytes = (size_t)sim->n_envs * 4 * sizeof(float);
+  for (int e = 0; e < sim->n_envs * 4; ++e)
+    if (!std::isfinite(push[e])) return fail(PMBS_ERR_INVALID_ARG, "push %d is not finite", e / 4);
+  if (bytes) {
+    hipError_t e = hipMemcpyAsync(sim->d_push, push, bytes, hipMemcpyHostToDevice, sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "push upload");
+    e = hipStreamSynchronize(sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "push upload sync");
+  }
+  *d_push = reinterpret_cast<const float4*>(sim->d_push);
+  return PMBS_OK;
+}
+
+StepArgs step_args(pmbs_sim_t* sim) {
+  StepArgs a{};
+  a.state = sim->d_state;
+  a.bconst = sim->d_bconst;
+  a.env_offset = sim->d_env_offset;
+  a.env_status = sim->d_status;
+  a.n_envs = sim->n_envs;
+  a.env_base = 0;
+  a.stride = sim->cfg.max_bodies;
+  a.stats = sim->d_stats;
+  a.p = params_of(sim->cfg);
+  return a;
+}
+
+}  // namespace pmbs
+
+using namespace pmbs;
+
+extern "C" {
+
+const char* pmbs_status_string(pmbs_status s) {
+  switch (s) {
+    case PMBS_OK: return "ok";
+    case PMBS_ERR_INVALID_ARG: return "invalid argument";
+    case PMBS_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case PMBS_ERR_HIP: return "HIP runtime error";
+    case PMBS_ERR_CAPACITY: return "capacity exceeded";
+    case PMBS_ERR_STATE: return "bad state";
+    default: return "unknown status";
+  }
+}
+
+const char* pmbs_last_error(void) { return g_last_error.c_str(); }
+
+void pmbs_sim_config_default(pmbs_sim_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof *c);
+  c->max_envs = 1024;
+  c->max_bodies = 32768;
+  c->max_contacts = 256;
+  c->solver_iters = 10;
+  c->pool_slots = 0;
+  c->pool_stride = 0;
+  c->dt = 1.0f / 240.0f;
+  c->gravity = 9.81f;
+  c->margin = 0.002f;
+  c->beta = 0.2f;
+  c->slop = 0.0005f;
+  c->mu_plane = 0.5f;
+  c->mu_pusher = 0.5f;
+  c->pusher_half[0] = 0.01f;
+  c->pusher_half[1] = 0.01f;
+  c->pusher_half[2] = 0.02f;
+  c->pusher_z = 0.022f;
+  c->push_speed = 0.1f;
+  c->push_length = 0.05f;
+  c->push_standoff = 0.005f;
+  c->tau_face = 1e-5f;
+  c->tau_edge = 5e-4f;
+  c->edge_eps = 1e-4f;
+}
+
+pmbs_status pmbs_sim_query_workspace(const pmbs_sim_config* cfg, size_t* bytes) {
+  pmbs_status st = check_config(cfg);
+  if (st != PMBS_OK) return st;
+  if (!bytes) return fail(PMBS_ERR_INVALID_ARG, "bytes is null");
+  *bytes = layout_of(*cfg).total;
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_create(const pmbs_sim_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+                            pmbs_sim_t** out) {
+  pmbs_status st = check_config(cfg);
+  if (st != PMBS_OK) return st;
+  if (!out) return fail(PMBS_ERR_INVALID_ARG, "out is null");
+  Layout L = layout_of(*cfg);
+  if (!d_workspace || bytes < L.total)
+    return fail(PMBS_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", L.total, bytes);
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+    return fail(PMBS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  pmbs_sim* s = new (std::nothrow) pmbs_sim();
+  if (!s) return fail(PMBS_ERR_INVALID_ARG, "out of host memory");
+  s->cfg = *cfg;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  char* base = static_cast<char*>(d_workspace);
+  s->d_state = reinterpret_cast<float*>(base + L.state);
+  s->d_bconst = reinterpret_cast<float*>(base + L.bconst);
+  s->d_env_offset = reinterpret_cast<int32_t*>(base + L.env_offset);
+  s->d_push = reinterpret_cast<float*>(base + L.push);
+  s->d_status = reinterpret_cast<uint32_t*>(base + L.status);
+  s->d_target = reinterpret_cast<int32_t*>(base + L.target);
+  s->d_reward = reinterpret_cast<float*>(base + L.reward);
+  s->d_clearance = reinterpret_cast<float*>(base + L.clearance);
+  s->d_slots = reinterpret_cast<int32_t*>(base + L.slots);
+  s->d_stats = reinterpret_cast<long long*>(base + L.stats);
+  s->d_pool = cfg->pool_slots > 0 ? reinterpret_cast<float*>(base + L.pool) : nullptr;
+  s->n_envs = 0;
+  s->n_bodies = 0;
+  hipError_t e = hipMemsetAsync(s->d_status, 0, (size_t)cfg->max_envs * sizeof(uint32_t), s->stream);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "hipMemsetAsync");
+  }
+  *out = s;
+  return PMBS_OK;
+}
+
+void pmbs_sim_destroy(pmbs_sim_t* sim) { delete sim; }
+
+pmbs_status pmbs_sim_set_state(pmbs_sim_t* sim, int32_t n_envs, const int32_t* env_offset, const float* state,
+                               int32_t state_is_device, const float* body) {
+  if (!sim || !env_offset || !state || !body) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (n_envs < 0 || n_envs > sim->cfg.max_envs)
+    return fail(PMBS_ERR_CAPACITY, "n_envs %d exceeds max_envs %d", n_envs, sim->cfg.max_envs);
+  if (env_offset[0] != 0) return fail(PMBS_ERR_INVALID_ARG, "env_offset[0] must be 0");
+  for (int e = 0; e < n_envs; ++e) {
+    int nb = env_offset[e + 1] - env_offset[e];
+    if (nb < 0) return fail(PMBS_ERR_INVALID_ARG, "env_offset must be non-decreasing (env %d)", e);
+    if (nb > PMBS_MAX_BODIES_PER_ENV)
+      return fail(PMBS_ERR_CAPACITY, "env %d has %d bodies (max %d)", e, nb, PMBS_MAX_BODIES_PER_ENV);
+  }
+  const int n = env_offset[n_envs];
+  if (n > sim->cfg.max_bodies) return fail(PMBS_ERR_CAPACITY, "%d bodies exceed max_bodies %d", n, sim->cfg.max_bodies);
+  const int N = sim->cfg.max_bodies;
+  // body constants: half extents, inverse mass, inverse body inertia of a
+  // solid cuboid I = m/12 (e_y^2 + e_z^2, ...), friction
+  std::vector<float> bc((size_t)8 * N, 0.0f);
+  for (int i = 0; i < n; ++i) {
+    double hx = body[0 * n + i], hy = body[1 * n + i], hz = body[2 * n + i], m = body[3 * n + i], mu = body[4 * n + i];
+    if (!(hx > 0 && hy > 0 && hz > 0 && m > 0 && mu >= 0) || !std::isfinite(hx + hy + hz + m + mu))
+      return fail(PMBS_ERR_STATE, "body %d: half extents and mass must be > 0, mu >= 0", i);
+    double ex = 2 * hx, ey = 2 * hy, ez = 2 * hz;
+    bc[0 * (size_t)N + i] = (float)hx;
+    bc[1 * (size_t)N + i] = (float)hy;
+    bc[2 * (size_t)N + i] = (float)hz;
+    bc[3 * (size_t)N + i] = (float)(1.0 / m);
+    bc[4 * (size_t)N + i] = (float)(12.0 / (m * (ey * ey + ez * ez)));
+    bc[5 * (size_t)N + i] = (float)(12.0 / (m * (ex * ex + ez * ez)));
+    bc[6 * (size_t)N + i] = (float)(12.0 / (m * (ex * ex + ey * ey)));
+    bc[7 * (size_t)N + i] = (float)mu;
+  }
+  hipError_t e;
+  if (!state_is_device) {
+    for (int i = 0; i < n; ++i) {
+      double qn = 0;
+      for (int r = 0; r < 13; ++r)
+        if (!std::isfinite(state[(size_t)r * n + i])) return fail(PMBS_ERR_STATE, "body %d: non-finite state", i);
+      for (int r = 3; r < 7; ++r) qn += (double)state[(size_t)r * n + i] * state[(size_t)r * n + i];
+      if (std::fabs(std::sqrt(qn) - 1.0) > 1e-3) return fail(PMBS_ERR_STATE, "body %d: quaternion not unit", i);
+    }
+  }
+  // state rows are strided by max_bodies on the device
+  for (int r = 0; r < 13 && n > 0; ++r) {
+    e = hipMemcpyAsync(sim->d_state + (size_t)r * N, state + (size_t)r * n, (size_t)n * sizeof(float),
+                       state_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "state upload");
+  }
+  e = hipMemcpyAsync(sim->d_bconst, bc.data(), bc.size() * sizeof(float), hipMemcpyHostToDevice, sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "body upload");
+  e = hipMemcpyAsync(sim->d_env_offset, env_offset, (size_t)(n_envs + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                     sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "env_offset upload");
+  // host copies are read by the stream asynchronously: wait so the caller
+  // may free its buffers on return
+  e = hipStreamSynchronize(sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "set_state sync");
+  sim->host_offset.assign(env_offset, env_offset + n_envs + 1);
+  sim->n_envs = n_envs;
+  sim->n_bodies = n;
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_get_state(pmbs_sim_t* sim, float* out, int32_t dst_is_device) {
+  if (!sim || !out) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  const int n = sim->n_bodies, N = sim->cfg.max_bodies;
+  for (int r = 0; r < 13 && n > 0; ++r) {
+    hipError_t e = hipMemcpyAsync(out + (size_t)r * n, sim->d_state + (size_t)r * N, (size_t)n * sizeof(float),
+                                  dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "state download");
+  }
+  if (!dst_is_device) {
+    hipError_t e = hipStreamSynchronize(sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "get_state sync");
+  }
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_device, int32_t n_substeps) {
+  if (!sim || !push) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (n_substeps < 0) return fail(PMBS_ERR_INVALID_ARG, "n_substeps must be >= 0");
+  const float4* d_push;
+  pmbs_status st = stage_push(sim, push, push_is_device, &d_push);
+  if (st != PMBS_OK) return st;
+  StepArgs a = step_args(sim);
+  a.push = d_push;
+  a.n_substeps = n_substeps;
+  hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "step launch");
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_env_status(pmbs_sim_t* sim, uint32_t* out, int32_t dst_is_device) {
+  if (!sim || !out) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (sim->n_envs == 0) return PMBS_OK;
+  hipError_t e = hipMemcpyAsync(out, sim->d_status, (size_t)sim->n_envs * sizeof(uint32_t),
+                                dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "status download");
+  if (!dst_is_device) {
+    e = hipStreamSynchronize(sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "status sync");
+  }
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_collide(pmbs_sim_t* sim, const float* push, int32_t push_is_device, int32_t* d_counts,
+                             float* d_contacts) {
+  if (!sim || !d_counts || !d_contacts) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  const float4* d_push;
+  pmbs_status st = stage_push(sim, push, push_is_device, &d_push);
+  if (st != PMBS_OK) return st;
+  StepArgs a = step_args(sim);
+  a.push = d_push;
+  a.n_substeps = 1;
+  a.collide_only = 1;
+  a.dbg_count = d_counts;
+  a.dbg_contacts = d_contacts;
+  hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "collide launch");
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_eval_reward(pmbs_sim_t* sim, const int32_t* target, int32_t target_is_device, float width,
+                             float* d_reward, float* d_clearance) {
+  if (!sim || !target || !d_reward) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (!(width > 0)) return fail(PMBS_ERR_INVALID_ARG, "width must be > 0");
+  const int n = sim->n_envs;
+  if (!target_is_device) {
+    for (int e = 0; e < n; ++e) {
+      int nb = sim->host_offset[e + 1] - sim->host_offset[e];
+      if (target[e] < 0 || target[e] >= nb) return fail(PMBS_ERR_INVALID_ARG, "env %d: target %d out of range", e, target[e]);
+    }
+  }
+  if (n == 0) return PMBS_OK;
+  hipError_t e = hipSuccess;
+  const int32_t* d_target = target;
+  if (!target_is_device) {
+    e = hipMemcpyAsync(sim->d_target, target, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "target upload");
+    e = hipStreamSynchronize(sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "target upload sync");
+    d_target = sim->d_target;
+  }
+  RewardArgs a{};
+  a.state = sim->d_state;
+  a.bconst = sim->d_bconst;
+  a.env_offset = sim->d_env_offset;
+  a.target = d_target;
+  a.reward = d_reward;
+  a.clearance = d_clearance;
+  a.n_envs = n;
+  a.stride = sim->cfg.max_bodies;
+  a.width = width;
+  e = launch_reward(a, sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "reward launch");
+  return PMBS_OK;
+}
+
+static pmbs_status pool_op(pmbs_sim_t* sim, const int32_t* slots, int32_t slots_is_device, int to_pool) {
+  if (!sim || !slots) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (!sim->d_pool) return fail(PMBS_ERR_CAPACITY, "simulator was created without a state pool");
+  const int n = sim->n_envs;
+  if (!slots_is_device) {
+    for (int e = 0; e < n; ++e) {
+      if (slots[e] >= sim->cfg.pool_slots) return fail(PMBS_ERR_CAPACITY, "env %d: slot %d >= pool_slots", e, slots[e]);
+      int nb = sim->host_offset[e + 1] - sim->host_offset[e];
+      if (slots[e] >= 0 && nb > sim->cfg.pool_stride)
+        return fail(PMBS_ERR_CAPACITY, "env %d has %d bodies > pool_stride %d", e, nb, sim->cfg.pool_stride);
+    }
+  }
+  if (n == 0) return PMBS_OK;
+  hipError_t e = hipSuccess;
+  const int32_t* d_slots = slots;
+  if (!slots_is_device) {
+    e = hipMemcpyAsync(sim->d_slots, slots, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "slot upload");
+    e = hipStreamSynchronize(sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "slot upload sync");
+    d_slots = sim->d_slots;
+  }
+  PoolArgs a{};
+  a.state = sim->d_state;
+  a.pool = sim->d_pool;
+  a.env_offset = sim->d_env_offset;
+  a.slots = d_slots;
+  a.n_envs = n;
+  a.stride = sim->cfg.max_bodies;
+  a.pool_slots = sim->cfg.pool_slots;
+  a.pool_stride = sim->cfg.pool_stride;
+  a.to_pool = to_pool;
+  e = launch_pool(a, sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "pool launch");
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_pool_gather(pmbs_sim_t* sim, const int32_t* slots, int32_t slots_is_device) {
+  return pool_op(sim, slots, slots_is_device, 0);
+}
+
+pmbs_status pmbs_pool_scatter(pmbs_sim_t* sim, const int32_t* slots, int32_t slots_is_device) {
+  return pool_op(sim, slots, slots_is_device, 1);
+}
+
+pmbs_status pmbs_sim_stats(pmbs_sim_t* sim, int64_t* out) {
+  if (!sim || !out) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (sim->n_envs == 0) return PMBS_OK;
+  hipError_t e = hipMemcpyAsync(out, sim->d_stats, (size_t)sim->n_envs * 2 * sizeof(long long), hipMemcpyDeviceToHost,
+                                sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "stats download");
+  e = hipStreamSynchronize(sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "stats sync");
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_sync(pmbs_sim_t* sim) {
+  if (!sim) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  hipError_t e = hipStreamSynchronize(sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "sync");
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_shape(const pmbs_sim_t* sim, int32_t* n_envs, int32_t* n_bodies) {
+  if (!sim) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (n_envs) *n_envs = sim->n_envs;
+  if (n_bodies) *n_bodies = sim->n_bodies;
+  return PMBS_OK;
+}
+
+}  // extern "C"

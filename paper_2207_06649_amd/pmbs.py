@@ -1,0 +1,240 @@
+"""Thin ctypes binding of libpmbs.so (include/pmbs.h).
+
+Argument marshalling only: every step of the push transition, the reward
+and the tree search run inside the library.  PyTorch supplies device memory
+(the workspace and output tensors) and the stream.  There is no fallback:
+if libpmbs.so is missing or no GPU is visible, constructing a simulator
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmbs.so")
+
+PMBS_ENV_CONTACT_OVERFLOW = 1
+PMBS_ENV_NONFINITE = 2
+PMBS_ENV_PUSH_INVALID = 4
+MAX_BODIES_PER_ENV = 31
+
+
+class SimConfig(C.Structure):
+    _fields_ = [("max_envs", C.c_int32), ("max_bodies", C.c_int32), ("max_contacts", C.c_int32),
+                ("solver_iters", C.c_int32), ("pool_slots", C.c_int32), ("pool_stride", C.c_int32),
+                ("dt", C.c_float), ("gravity", C.c_float), ("margin", C.c_float), ("beta", C.c_float),
+                ("slop", C.c_float), ("mu_plane", C.c_float), ("mu_pusher", C.c_float),
+                ("pusher_half", C.c_float * 3), ("pusher_z", C.c_float), ("push_speed", C.c_float),
+                ("push_length", C.c_float), ("push_standoff", C.c_float), ("tau_face", C.c_float),
+                ("tau_edge", C.c_float), ("edge_eps", C.c_float)]
+
+
+class PmbsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Loads libpmbs.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2207_06649_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, fp, up = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_float), C.POINTER(C.c_uint32)
+        cfgp = C.POINTER(SimConfig)
+        L.pmbs_status_string.restype = C.c_char_p
+        L.pmbs_status_string.argtypes = [C.c_int32]
+        L.pmbs_last_error.restype = C.c_char_p
+        L.pmbs_sim_config_default.argtypes = [cfgp]
+        L.pmbs_sim_config_default.restype = None
+        L.pmbs_sim_query_workspace.argtypes = [cfgp, C.POINTER(C.c_size_t)]
+        L.pmbs_sim_create.argtypes = [cfgp, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.pmbs_sim_destroy.argtypes = [vp]
+        L.pmbs_sim_destroy.restype = None
+        L.pmbs_sim_set_state.argtypes = [vp, C.c_int32, ip, vp, C.c_int32, fp]
+        L.pmbs_sim_get_state.argtypes = [vp, vp, C.c_int32]
+        L.pmbs_sim_step.argtypes = [vp, vp, C.c_int32, C.c_int32]
+        L.pmbs_sim_env_status.argtypes = [vp, vp, C.c_int32]
+        L.pmbs_sim_collide.argtypes = [vp, vp, C.c_int32, vp, vp]
+        L.pmbs_eval_reward.argtypes = [vp, vp, C.c_int32, C.c_float, vp, vp]
+        L.pmbs_sim_sync.argtypes = [vp]
+        L.pmbs_sim_stats.argtypes = [vp, vp]
+        L.pmbs_pool_gather.argtypes = [vp, vp, C.c_int32]
+        L.pmbs_pool_scatter.argtypes = [vp, vp, C.c_int32]
+        L.pmbs_sim_shape.argtypes = [vp, ip, ip]
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        L = lib()
+        raise PmbsError(f"{L.pmbs_status_string(st).decode()}: {L.pmbs_last_error().decode()}")
+
+
+def default_config(**over) -> SimConfig:
+    c = SimConfig()
+    lib().pmbs_sim_config_default(C.byref(c))
+    for k, v in over.items():
+        if k == "pusher_half":
+            c.pusher_half = (C.c_float * 3)(*v)
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def soa(a, width: int) -> np.ndarray:
+    """[n, width] rows -> contiguous float32 [width, n]."""
+    a = np.asarray(a, dtype=np.float64).reshape(-1, width)
+    return np.ascontiguousarray(a.T.astype(np.float32))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Sim:
+    """One simulator over a torch-allocated device workspace."""
+
+    def __init__(self, cfg: SimConfig | None = None, device: str = "cuda:0", stream=None, **over):
+        import torch
+        if not torch.cuda.is_available():
+            raise PmbsError("no GPU visible: the simulator runs only on the HIP path")
+        self.torch = torch
+        self.cfg = cfg if cfg is not None else default_config(**over)
+        self.device = torch.device(device)
+        L = lib()
+        nbytes = C.c_size_t(0)
+        _check(L.pmbs_sim_query_workspace(C.byref(self.cfg), C.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        # torch's caching allocator returns 256-byte-or-better aligned blocks
+        self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.pmbs_sim_create(C.byref(self.cfg), _ptr(self.workspace), self.workspace_bytes,
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+        self.n_envs = 0
+        self.n_bodies = 0
+        self.env_offset = np.zeros(1, np.int32)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib().pmbs_sim_destroy(h)
+            self.handle = None
+
+    # ---------------------------------------------------------------- state
+    def set_state(self, env_offset, state, body):
+        """env_offset int [E+1]; state [N,13] (numpy AoS, or a device tensor
+        already SoA [13,N] float32); body [N,5] hx,hy,hz,mass,mu."""
+        off = np.ascontiguousarray(env_offset, dtype=np.int32)
+        bd = soa(body, 5)
+        if hasattr(state, "data_ptr"):
+            st, dev = state, 1
+            sp = _ptr(state)
+        else:
+            st, dev = soa(state, 13), 0
+            sp = st.ctypes.data_as(C.c_void_p)
+        _check(lib().pmbs_sim_set_state(self.handle, off.shape[0] - 1, off.ctypes.data_as(C.POINTER(C.c_int32)),
+                                        sp, dev, bd.ctypes.data_as(C.POINTER(C.c_float))))
+        self.env_offset = off
+        self.n_envs = off.shape[0] - 1
+        self.n_bodies = int(off[-1])
+
+    def load(self, batch):
+        """Loads a scenes.Batch."""
+        self.set_state(batch.env_offset, batch.state, batch.body)
+
+    def get_state(self) -> np.ndarray:
+        """[N,13] float32 (AoS view of the device SoA state)."""
+        out = np.zeros((13, self.n_bodies), np.float32)
+        _check(lib().pmbs_sim_get_state(self.handle, out.ctypes.data_as(C.c_void_p), 0))
+        return out.T.copy()
+
+    def get_state_device(self, out=None):
+        t = self.torch
+        if out is None:
+            out = t.empty((13, self.n_bodies), dtype=t.float32, device=self.device)
+        _check(lib().pmbs_sim_get_state(self.handle, _ptr(out), 1))
+        return out
+
+    # ---------------------------------------------------------------- transition
+    def _push_arg(self, push):
+        if push is None:
+            return None, 0, None
+        if hasattr(push, "data_ptr"):
+            assert push.dtype == self.torch.float32 and push.is_contiguous()
+            return _ptr(push), 1, push
+        p = np.ascontiguousarray(np.asarray(push, np.float32).reshape(self.n_envs, 4))
+        return p.ctypes.data_as(C.c_void_p), 0, p
+
+    def step(self, push, n_substeps: int):
+        ptr, dev, keep = self._push_arg(push)
+        _check(lib().pmbs_sim_step(self.handle, ptr, dev, int(n_substeps)))
+        return keep
+
+    def env_status(self) -> np.ndarray:
+        out = np.zeros(self.n_envs, np.uint32)
+        _check(lib().pmbs_sim_env_status(self.handle, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def collide(self, push=None):
+        """Contact lists at the current poses: (counts [E], contacts [E, C, 9])."""
+        t = self.torch
+        C_ = int(self.cfg.max_contacts)
+        counts = t.zeros(self.n_envs, dtype=t.int32, device=self.device)
+        contacts = t.zeros((self.n_envs, C_, 9), dtype=t.float32, device=self.device)
+        ptr, dev, keep = self._push_arg(push)
+        _check(lib().pmbs_sim_collide(self.handle, ptr, dev, _ptr(counts), _ptr(contacts)))
+        self.sync()
+        return counts.cpu().numpy(), contacts.cpu().numpy()
+
+    def eval_reward(self, target, width: float = 0.08, reward=None, clearance=None, sync: bool = True):
+        """Reward and clearance per env.  target: host ints or a device int32
+        tensor; outputs are device tensors (allocated when not given).  With
+        sync=True returns numpy copies."""
+        t = self.torch
+        if hasattr(target, "data_ptr"):
+            tp, tdev, keep = _ptr(target), 1, target
+        else:
+            keep = np.ascontiguousarray(np.asarray(target, np.int32).reshape(self.n_envs))
+            tp, tdev = keep.ctypes.data_as(C.c_void_p), 0
+        rew = reward if reward is not None else t.empty(self.n_envs, dtype=t.float32, device=self.device)
+        clr = clearance if clearance is not None else t.empty(self.n_envs, dtype=t.float32, device=self.device)
+        _check(lib().pmbs_eval_reward(self.handle, tp, tdev, float(width), _ptr(rew), _ptr(clr)))
+        if not sync:
+            return rew, clr
+        self.sync()
+        return rew.cpu().numpy(), clr.cpu().numpy()
+
+    def stats(self) -> np.ndarray:
+        """[E, 2] int64: contacts and candidate pairs summed over the last step's substeps."""
+        out = np.zeros((self.n_envs, 2), np.int64)
+        _check(lib().pmbs_sim_stats(self.handle, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def _slots(self, slots):
+        if hasattr(slots, "data_ptr"):
+            return _ptr(slots), 1, slots
+        s = np.ascontiguousarray(np.asarray(slots, np.int32).reshape(self.n_envs))
+        return s.ctypes.data_as(C.c_void_p), 0, s
+
+    def pool_gather(self, slots):
+        ptr, dev, keep = self._slots(slots)
+        _check(lib().pmbs_pool_gather(self.handle, ptr, dev))
+        return keep
+
+    def pool_scatter(self, slots):
+        ptr, dev, keep = self._slots(slots)
+        _check(lib().pmbs_pool_scatter(self.handle, ptr, dev))
+        return keep
+
+    def sync(self):
+        _check(lib().pmbs_sim_sync(self.handle))

@@ -1,0 +1,60 @@
+"""The C-ABI library loads, exports every entry point its header declares,
+and rejects bad configurations without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2207_06649_amd import pmbs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(pmbs_[a-z_]+)\s*\(", src))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    L = pmbs.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_defaults_and_workspace_query():
+    cfg = pmbs.default_config()
+    assert cfg.solver_iters == 10 and cfg.max_contacts == 256
+    assert cfg.dt == pytest.approx(1 / 240)
+    n = C.c_size_t(0)
+    assert pmbs.lib().pmbs_sim_query_workspace(C.byref(cfg), C.byref(n)) == 0
+    # 13 + 8 floats per body, per-env regions, 256-byte aligned
+    assert n.value >= 21 * 4 * cfg.max_bodies and n.value % 256 == 0
+    cfg2 = pmbs.default_config(pool_slots=100, pool_stride=21)
+    n2 = C.c_size_t(0)
+    assert pmbs.lib().pmbs_sim_query_workspace(C.byref(cfg2), C.byref(n2)) == 0
+    assert n2.value - n.value >= 100 * 21 * 13 * 4
+
+
+@pytest.mark.parametrize("field,value", [("max_contacts", 100), ("max_envs", 0), ("dt", 0.0),
+                                         ("pool_slots", 5)])
+def test_bad_config_rejected(field, value):
+    cfg = pmbs.default_config(**{field: value})
+    n = C.c_size_t(0)
+    st = pmbs.lib().pmbs_sim_query_workspace(C.byref(cfg), C.byref(n))
+    assert st == -1
+    assert pmbs.lib().pmbs_last_error()
+
+
+def test_create_rejects_small_workspace_without_gpu():
+    cfg = pmbs.default_config()
+    h = C.c_void_p()
+    st = pmbs.lib().pmbs_sim_create(C.byref(cfg), C.c_void_p(256), 16, None, C.byref(h))
+    assert st == -2 and not h.value
