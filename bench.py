@@ -122,6 +122,7 @@ def main() -> int:
     status = sim.env_status()
     stats = sim.stats().astype(np.float64)
     n_valid = int(np.sum((status & pmbs.PMBS_ENV_PUSH_INVALID) == 0))
+    n_overflow = int(np.sum((status & pmbs.PMBS_ENV_CONTACT_OVERFLOW) != 0))
     if np.any(status & (pmbs.PMBS_ENV_NONFINITE | pmbs.PMBS_ENV_CONTACT_OVERFLOW)):
         print("# warning: non-finite or overflowing environments", file=sys.stderr)
     env_substeps = E * args.substeps
@@ -164,6 +165,7 @@ def main() -> int:
                         "step = pool gather + fused push step + reward",
             "envs": E, "bodies_per_env": args.bodies, "substeps": args.substeps,
             "solver_iters": iters, "seed": args.seed, "valid_pushes": n_valid,
+            "max_contacts": int(sim.cfg.max_contacts), "overflow_envs": n_overflow,
         },
         "roofline": {
             "kernel": "step_kernel",

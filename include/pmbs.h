@@ -68,7 +68,7 @@ const char* pmbs_last_error(void);
 typedef struct pmbs_sim_config {
     int32_t max_envs;      /* environment slots */
     int32_t max_bodies;    /* bodies over all environments (packed) */
-    int32_t max_contacts;  /* per environment: 256 or 512 */
+    int32_t max_contacts;  /* per environment: 128, 256 or 512 (sets the VGPR contact slots) */
     int32_t solver_iters;  /* Jacobi iterations per substep (10) */
     int32_t pool_slots;    /* tree-node state slots resident on the device (0: none) */
     int32_t pool_stride;   /* bodies per pool slot (>= bodies of any pooled env) */
@@ -92,7 +92,7 @@ typedef struct pmbs_sim_config {
 typedef struct pmbs_sim pmbs_sim_t;
 
 /* Fills every field with the defaults above (capacities: 1024 envs,
- * 32768 bodies, 256 contacts, no pool). */
+ * 32768 bodies, 128 contacts, no pool). */
 void pmbs_sim_config_default(pmbs_sim_config* cfg);
 
 /* Exact device bytes the configuration needs (256-byte aligned regions). */

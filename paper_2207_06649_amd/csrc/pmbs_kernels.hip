@@ -32,7 +32,7 @@ constexpr int MAXB = 32;             // boxes (<= 31) + the pusher
 constexpr int PLANE = MAXB;          // LDS index of the table
 constexpr int NOBJ = MAXB + 1;
 constexpr int MAX_PAIRS = MAXB * (MAXB - 1) / 2;
-constexpr int CLIP_LANES = 32;       // pair lanes per narrowphase round
+constexpr int CLIP_LANES = 16;       // pair lanes per narrowphase round
 constexpr int POLY = 8;              // clip polygon capacity
 
 // ------------------------------------------------------------------ vectors
@@ -86,6 +86,7 @@ struct Smem {
   float4 vel[NOBJ];                  // solver snapshot: linear
   float4 ang[NOBJ];                  // solver snapshot: angular
   int cnt[NOBJ];                     // contacts touching each body (mass splitting)
+  unsigned short inc[2 * C];         // per-body incidence lists: contact << 1 | side (1 = b)
   float lo[3][MAXB], hi[3][MAXB];    // AABBs
   int sorted[MAXB];
   unsigned mask[MAXB];
@@ -95,7 +96,7 @@ struct Smem {
   float wl[3][C];                    // and their accumulated impulses (n, t1, t2)
   union {
     float4 stage[C][2];              // narrowphase output: (p, sep), (n, -)
-    float imp[9][C];                 // solver exchange: P, ra x P, rb x P
+    float4 imp[3][C];                // solver exchange: P, ra x P, rb x P
   } u;
   float clip[2][POLY][3][CLIP_LANES];
 };
@@ -525,7 +526,6 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
 
   // contact slots
   Contact ct[K];
-  unsigned long long mA[K], mB[K];
 
   const int n_obj = nb + 1;
   const int n_sub = g.collide_only ? 1 : g.n_substeps;
@@ -707,26 +707,50 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
       return;
     }
 
-    // ---- 5. incidence masks per body (contact-index order) and counts
-    if (active) {
+    // ---- 5. per-body incidence lists in contact-index order (CSR) and counts
+    int inc_start = 0, inc_count = 0;
+    {
+      int ca[K], cb[K];
 #pragma unroll
       for (int sl = 0; sl < K; ++sl) {
-        unsigned long long ma = 0, mb = 0;
-        const int c_end = min(nc, 64 * (sl + 1));
-        for (int c = 64 * sl; c < c_end; ++c) {
-          int ab = s.cab[c];
-          unsigned long long bit = 1ull << (c - 64 * sl);
-          if ((ab & 255) == b) ma |= bit;
-          if (((ab >> 8) & 255) == b) mb |= bit;
-        }
-        mA[sl] = ma;
-        mB[sl] = mb;
+        const int c = 64 * sl + lane;
+        const int ab = c < nc ? s.cab[c] : -1;
+        ca[sl] = c < nc ? (ab & 255) : -1;
+        cb[sl] = c < nc ? ((ab >> 8) & 255) : -1;
       }
-      if (part == 0) {
-        int cn = 0;
+      unsigned long long mA[K], mB[K];
 #pragma unroll
-        for (int sl = 0; sl < K; ++sl) cn += __popcll(mA[sl] | mB[sl]);
+      for (int sl = 0; sl < K; ++sl) { mA[sl] = 0ull; mB[sl] = 0ull; }
+      for (int j = 0; j < nb; ++j) {
+#pragma unroll
+        for (int sl = 0; sl < K; ++sl) {
+          if (64 * sl < nc) {
+            const unsigned long long ma = __ballot(ca[sl] == j), mb = __ballot(cb[sl] == j);
+            if (b == j) { mA[sl] = ma; mB[sl] = mb; }
+          }
+        }
+      }
+      int cn = 0;
+#pragma unroll
+      for (int sl = 0; sl < K; ++sl) cn += __popcll(mA[sl] | mB[sl]);
+      if (!active) cn = 0;
+      int tot;
+      int st0 = wave_excl_scan(part == 0 ? cn : 0, &tot);
+      inc_start = __shfl(st0, b, 64);
+      inc_count = cn;
+      if (active && part == 0) {
         s.cnt[b] = cn;
+        int t = inc_start;
+#pragma unroll
+        for (int sl = 0; sl < K; ++sl) {
+          unsigned long long m = mA[sl] | mB[sl];
+          while (m) {
+            const int bit = __builtin_ctzll(m);
+            m &= m - 1;
+            const int side = (int)((mB[sl] >> bit) & 1ull);
+            s.inc[t++] = (unsigned short)(((64 * sl + bit) << 1) | side);
+          }
+        }
       }
     }
     wave_sync();
@@ -784,28 +808,20 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
             q.lt2 = lt2;
             P = q.n * dln + (q.t1 * dl1 + t2 * dl2);
           }
-          f3 Ta = cross(q.ra, P), Tb = cross(q.rb, P);
-          s.u.imp[0][c] = P.x; s.u.imp[1][c] = P.y; s.u.imp[2][c] = P.z;
-          s.u.imp[3][c] = Ta.x; s.u.imp[4][c] = Ta.y; s.u.imp[5][c] = Ta.z;
-          s.u.imp[6][c] = Tb.x; s.u.imp[7][c] = Tb.y; s.u.imp[8][c] = Tb.z;
+          s.u.imp[0][c] = f4(P, 0.0f);
+          s.u.imp[1][c] = f4(cross(q.ra, P), 0.0f);
+          s.u.imp[2][c] = f4(cross(q.rb, P), 0.0f);
         }
       }
       wave_sync();
       if (active) {
         f3 acc = mk(0, 0, 0);
-        const int o = part == 0 ? 0 : 3;
-#pragma unroll
-        for (int sl = 0; sl < K; ++sl) {
-          unsigned long long m = mA[sl] | mB[sl];
-          while (m) {
-            int bit = __builtin_ctzll(m);
-            m &= m - 1;
-            const int c = 64 * sl + bit;
-            const bool side_b = (mB[sl] >> bit) & 1ull;
-            const int oo = (part == 1 && side_b) ? 6 : o;
-            f3 val = mk(s.u.imp[oo][c], s.u.imp[oo + 1][c], s.u.imp[oo + 2][c]);
-            acc = side_b ? acc + val : acc - val;
-          }
+        for (int k = 0; k < inc_count; ++k) {
+          const int en = s.inc[inc_start + k];
+          const int c = en >> 1, side = en & 1;
+          const float4 val = s.u.imp[part == 0 ? 0 : 1 + side][c];
+          const float sg = side ? 1.0f : -1.0f;
+          acc = mk(fmaf(sg, val.x, acc.x), fmaf(sg, val.y, acc.y), fmaf(sg, val.z, acc.z));
         }
         if (part == 0) {
           v = v + acc * invm;
@@ -1003,7 +1019,9 @@ __global__ __launch_bounds__(64) void reward_kernel(RewardArgs g) {
 hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream) {
   const int n = a.n_envs - a.env_base;
   if (n <= 0) return hipSuccess;
-  if (max_contacts <= 256) {
+  if (max_contacts <= 128) {
+    hipLaunchKernelGGL(step_kernel<2>, dim3(n), dim3(64), 0, stream, a);
+  } else if (max_contacts <= 256) {
     hipLaunchKernelGGL(step_kernel<4>, dim3(n), dim3(64), 0, stream, a);
   } else {
     hipLaunchKernelGGL(step_kernel<8>, dim3(n), dim3(64), 0, stream, a);

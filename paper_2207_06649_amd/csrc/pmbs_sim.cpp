@@ -68,8 +68,8 @@ static Layout layout_of(const pmbs_sim_config& c) {
 static pmbs_status check_config(const pmbs_sim_config* c) {
   if (!c) return fail(PMBS_ERR_INVALID_ARG, "config is null");
   if (c->max_envs <= 0 || c->max_bodies <= 0) return fail(PMBS_ERR_INVALID_ARG, "max_envs and max_bodies must be > 0");
-  if (c->max_contacts != 256 && c->max_contacts != 512)
-    return fail(PMBS_ERR_INVALID_ARG, "max_contacts must be 256 or 512 (got %d)", c->max_contacts);
+  if (c->max_contacts != 128 && c->max_contacts != 256 && c->max_contacts != 512)
+    return fail(PMBS_ERR_INVALID_ARG, "max_contacts must be 128, 256 or 512 (got %d)", c->max_contacts);
   if (c->solver_iters < 0 || c->solver_iters > 1000) return fail(PMBS_ERR_INVALID_ARG, "solver_iters out of range");
   if (c->pool_slots < 0 || c->pool_stride < 0) return fail(PMBS_ERR_INVALID_ARG, "pool sizes must be >= 0");
   if (c->pool_slots > 0 && (c->pool_stride <= 0 || c->pool_stride > PMBS_MAX_BODIES_PER_ENV))
@@ -165,7 +165,7 @@ void pmbs_sim_config_default(pmbs_sim_config* c) {
   std::memset(c, 0, sizeof *c);
   c->max_envs = 1024;
   c->max_bodies = 32768;
-  c->max_contacts = 256;
+  c->max_contacts = 128;
   c->solver_iters = 10;
   c->pool_slots = 0;
   c->pool_stride = 0;

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_defaults_and_workspace_query():
     cfg = pmbs.default_config()
-    assert cfg.solver_iters == 10 and cfg.max_contacts == 256
+    assert cfg.solver_iters == 10 and cfg.max_contacts == 128
     assert cfg.dt == pytest.approx(1 / 240)
     n = C.c_size_t(0)
     assert pmbs.lib().pmbs_sim_query_workspace(C.byref(cfg), C.byref(n)) == 0

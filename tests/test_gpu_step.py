@@ -246,6 +246,46 @@ def test_batched_clutter_120_substeps_invariants(pm):
         assert pen <= 1e-3, (e, pen)
 
 
+def test_contact_capacity_classes_agree(pm):
+    """The 128-, 256- and 512-contact kernels give bitwise the same result
+    when no environment overflows."""
+    b = scenes.clutter_batch(12, 64, 15)
+    outs = []
+    for cap in (128, 256, 512):
+        g, gs, _ = run_gpu(pm, b, b.push, 40, max_contacts=cap)
+        assert not np.any(gs & 1)
+        outs.append(g)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def grid_pile(n=31, e=0.04):
+    """n cubes on a touching grid, rows and columns jittered by 2-3 mm so no
+    corners coincide: far more than 128 contacts."""
+    st, bd = [], []
+    for k in range(n):
+        i, j = divmod(k, 6)
+        st.append(srow((i * e + 0.002 * j, j * e + 0.003 * i, e / 2)))
+        bd.append([e / 2, e / 2, e / 2, 0.1, 0.5])
+    return single(st, bd)
+
+
+def test_contact_overflow_flagged_and_isolated(pm):
+    """An env whose contacts exceed the cap is flagged and truncated exactly
+    like the oracle's list; the other envs are bitwise what they are alone."""
+    pile = grid_pile()
+    small = scenes.clutter_batch(14, 3, 6)
+    both = scenes.concat([pile, small])
+    push = np.concatenate([FAR[None], small.push])
+    g, gs, _ = run_gpu(pm, both, push, 1, max_contacts=128)
+    assert gs[0] & 1 and not np.any(gs[1:] & 1)
+    cfg128 = O.make_config(max_contacts=128)
+    o, os_, _ = O.step(cfg128, pile.env_offset, f32(pile.state), f32(pile.body), f32(FAR[None]), 1)
+    assert os_[0] & 1
+    compare(g[:31], o, 1e-5, 1e-5)
+    alone, _, _ = run_gpu(pm, small, small.push, 1, max_contacts=128)
+    assert np.array_equal(g[31:], alone)
+
+
 def test_headline_shape_sampled_parity(pm):
     """4096 envs x 15 cuboids in one launch (the benchmark's shape): sampled
     envs match the oracle after 1 substep; 120 substeps keep the invariants."""
