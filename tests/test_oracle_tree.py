@@ -1,0 +1,232 @@
+"""Pins of the tree oracle (UCT with virtual loss, Alg. 2, batched
+expansion/simulation, max-over-replicas backprop) on toy problems whose
+answers are known independently (no GPU)."""
+import math
+import os
+
+import pytest
+
+from oracle import tree_oracle as T
+from oracle.philox import philox4x32
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_philox_known_answers():
+    n = 0
+    for line in open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(x, 16) for x in line.split()]
+        assert philox4x32(w[0:4], w[4:6]) == tuple(w[6:10])
+        n += 1
+    assert n == 3
+
+
+class ToyEnv:
+    """Deterministic MDP: k actions per state; the state is the action
+    history; reward 1 once the history starts with `lock`, else `base`(history)."""
+
+    def __init__(self, k=3, lock=(2, 0), base=None, valid=None):
+        self.k, self.lock, self.base, self.valid = k, tuple(lock), base, valid
+        self.calls = []
+
+    def n_actions(self, state):
+        return self.k
+
+    def reward(self, hist):
+        if tuple(hist[: len(self.lock)]) == self.lock:
+            return 1.0
+        return self.base(hist) if self.base else 0.0
+
+    def root_reward(self, state):
+        return self.reward(state)
+
+    def run(self, state, actions):
+        self.calls.append((tuple(state), tuple(actions)))
+        if self.valid and not self.valid(state, actions[0]):
+            return False, None, []
+        hist = list(state)
+        rewards = []
+        for a in actions:
+            hist.append(a)
+            rewards.append(self.reward(hist))
+            if rewards[-1] >= 1.0:
+                break
+        return True, tuple(list(state) + [actions[0]]), rewards
+
+
+def all_nodes(n):
+    yield n
+    for ch in n.children:
+        yield from all_nodes(ch)
+
+
+def test_selection_pairs_unique_virtual_counts_reset_and_fill():
+    env = ToyEnv(k=5, lock=(9,))
+    p = T.Planner(env, (), n_envs=8, depth=1, seed=3)
+    pairs, envs = T.select_batch(p.root, 8, 1.4, 1)
+    # depth limit 1: only the root expands; 5 unique actions, then replicas
+    assert [n.id for n, _ in pairs] == [0] * 5
+    assert sorted(a for _, a in pairs) == list(range(5))
+    assert envs == [(0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (0, 1), (1, 1), (2, 1)]
+    assert all(n.Nhat == 0 for n in all_nodes(p.root))
+    assert p.root.untried == []
+    pairs2, envs2 = T.select_batch(p.root, 8, 1.4, 1)
+    assert pairs2 == [] and envs2 == []
+
+
+def test_virtual_loss_diverts_second_selection():
+    """Root children A (Q=0.9, N=1) and B (Q=0.5, N=1), root N=2, c=0.3.
+    By hand: U(A)=0.9+0.3*sqrt(2 ln 2)=1.253 > U(B)=0.853, so A first; then
+    N^(A)=N^(root)=1 and U(A)=0.45+0.3*sqrt(ln 3)=0.764 < U(B)=0.5+0.3*sqrt(2 ln 3)=0.945,
+    so the second pair comes from B (without virtual loss it would be A)."""
+    root = T.Node(0, None, None, 0, (), 0.0, [])
+    A = T.Node(1, root, 0, 1, (0,), 0.9, [10, 11], Q=0.9, N=1)
+    B = T.Node(2, root, 1, 1, (1,), 0.5, [20, 21], Q=0.5, N=1)
+    root.children = [A, B]
+    root.N = 2
+    pairs, _ = T.select_batch(root, 2, 0.3, 2)
+    assert [(n.id, a) for n, a in pairs] == [(1, 10), (2, 20)]
+
+
+def test_discounted_backprop_and_max_over_replicas():
+    """Depth-3 chain: the child's return G is the max over replicas of
+    max_t gamma^t r_t; the j-th ancestor receives gamma^j G."""
+    rewards_by_replica = {0: [0.1, 0.5], 1: [0.3, 0.2], 2: [0.0, 0.9]}
+
+    class Env(ToyEnv):
+        def run(self, state, actions):
+            rep = self.rep
+            self.rep += 1
+            return True, tuple(list(state) + [actions[0]]), rewards_by_replica[rep]
+
+    env = Env(k=1, lock=(7,))
+    env.rep = 0
+    p = T.Planner(env, (), n_envs=3, depth=3, seed=1, gamma=0.8)
+    assert p.iterate()
+    g = max(max(0.8 ** t * r for t, r in enumerate(rw)) for rw in rewards_by_replica.values())
+    assert g == pytest.approx(0.8 * 0.9)
+    child = p.root.children[0]
+    assert child.Q == pytest.approx(g) and child.N == 1
+    assert p.root.Q == pytest.approx(0.8 * g) and p.root.N == 1
+    # the child's own reward is the first replica's first push
+    assert child.reward == 0.1
+
+
+def serial_uct(env, iters, c, gamma, D, seed):
+    """Textbook one-leaf-at-a-time UCT (Eq. 1), written independently of
+    the batch code: returns {history: (Q, N)}."""
+    stats = {(): [0.0, 0]}
+    untried = {(): T.shuffled_actions(env.n_actions(()), 0, seed)}
+    ids = {(): 0}
+    term = {(): env.reward(()) >= 1.0}
+    next_id = 1
+    for _ in range(iters):
+        h = ()
+        path = [h]
+        while True:
+            if term[h]:
+                break
+            if len(h) < D and untried[h]:
+                break
+            kids = [h + (a,) for a in range(env.k) if h + (a,) in stats]
+            live = [k for k in kids if _live(k, stats, untried, term, D)]
+            if not live:
+                break
+            order = sorted(live, key=lambda k: ids[k])
+            best, bu = None, -math.inf
+            for k in order:
+                q, n = stats[k]
+                u = q / n + c * math.sqrt(2 * math.log(stats[h][1]) / n)
+                if best is None or u > bu:
+                    best, bu = k, u
+            h = best
+            path.append(h)
+        if term[h] or not (len(h) < D and untried[h]):
+            break
+        a = untried[h].pop(0)
+        nid = ids[h]
+        acts = [a] + [T.rollout_action(nid, a, 0, t, env.k, seed) for t in range(1, D - len(h))]
+        valid, child, rewards = env.run(h, acts)
+        g = max(gamma ** t * r for t, r in enumerate(rewards))
+        ids[child] = next_id
+        next_id += 1
+        stats[child] = [0.0, 0]
+        untried[child] = T.shuffled_actions(env.k, ids[child], seed)
+        term[child] = rewards[0] >= 1.0
+        path.append(child)
+        for j, node in enumerate(reversed(path)):
+            stats[node][0] += gamma ** j * g
+            stats[node][1] += 1
+    return stats
+
+
+def _live(h, stats, untried, term, D):
+    if term[h]:
+        return False
+    if len(h) < D and untried[h]:
+        return True
+    return any(_live(k, stats, untried, term, D) for k in stats if len(k) == len(h) + 1 and k[:len(h)] == h)
+
+
+def test_single_env_batch_equals_serial_uct():
+    base = lambda hist: 0.05 * (sum(hist) % 4)
+    env = ToyEnv(k=3, lock=(2, 1, 1), base=base)
+    p = T.Planner(env, (), n_envs=1, depth=4, seed=11, c=1.4, gamma=0.8)
+    for _ in range(40):
+        p.iterate()
+    ref = serial_uct(ToyEnv(k=3, lock=(2, 1, 1), base=base), 40, 1.4, 0.8, 4, 11)
+    got = {n.state: (n.Q, n.N) for n in all_nodes(p.root)}
+    assert set(got) == set(ref)
+    for h in ref:
+        assert got[h][1] == ref[h][1]
+        assert got[h][0] == pytest.approx(ref[h][0], abs=1e-12)
+
+
+@pytest.mark.parametrize("n_envs", [1, 4, 16])
+def test_combination_lock_first_action(n_envs):
+    """Only the sequence (2, 0) gives reward 1; everything else 0.  Any
+    number of environments finds 2 as the first action."""
+    env = ToyEnv(k=3, lock=(2, 0))
+    p = T.Planner(env, (), n_envs=n_envs, depth=3, seed=5, c=1.4, gamma=0.8)
+    a, v = p.plan(60 if n_envs == 1 else 20)
+    assert a == 2 and v > 0
+    # no other first action can ever open the lock
+    assert all(ch.Q == 0 for ch in p.root.children if ch.action != 2)
+
+
+def test_invalid_actions_are_discarded():
+    env = ToyEnv(k=4, lock=(9,), valid=lambda s, a: a != 1)
+    p = T.Planner(env, (), n_envs=4, depth=1, seed=2)
+    p.iterate()
+    assert sorted(ch.action for ch in p.root.children) == [0, 2, 3]
+    assert p.root.N == 3
+
+
+def test_shuffle_is_a_permutation_and_seeded():
+    a = T.shuffled_actions(168, 5, 99)
+    assert sorted(a) == list(range(168))
+    assert a == T.shuffled_actions(168, 5, 99)
+    assert a != T.shuffled_actions(168, 6, 99)
+
+
+def test_physics_planner_small_retrieval_scene():
+    """The planner over the FP64 push transition: every child holds the
+    post-push state and its reward; the chosen action is a root child."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2207_06649_amd import scenes
+    b = scenes.retrieval_scene(3, n_others=6, region=0.25)
+    env = T.PhysicsEnv(O.make_config(), b.body, target=0, substeps=60)
+    p = T.Planner(env, b.state, n_envs=12, depth=2, seed=4)
+    a, v = p.plan(2)
+    assert a in {ch.action for ch in p.root.children}
+    for ch in p.root.children:
+        obj, d = divmod(ch.action, 8)
+        push = O.contour_push(O.make_config(), b.state[obj], b.body[obj], d, 8)
+        st, _, valid = O.step(O.make_config(), [0, len(b.body)], b.state, b.body, push[None], 60)
+        assert valid[0] == 1
+        assert np.array_equal(st, ch.state)
+        assert ch.reward == O.reward(st, b.body, 0, 0.08)
