@@ -120,7 +120,7 @@ def main() -> int:
     k_avg_ms = float(np.mean(kernel_ms))
 
     status = sim.env_status()
-    stats = sim.stats().astype(np.float64)
+    stats = sim.stats().astype(np.float64)[:, :2]
     n_valid = int(np.sum((status & pmbs.PMBS_ENV_PUSH_INVALID) == 0))
     n_overflow = int(np.sum((status & pmbs.PMBS_ENV_CONTACT_OVERFLOW) != 0))
     if np.any(status & (pmbs.PMBS_ENV_NONFINITE | pmbs.PMBS_ENV_CONTACT_OVERFLOW)):

@@ -72,6 +72,7 @@ typedef struct pmbs_sim_config {
     int32_t solver_iters;  /* Jacobi iterations per substep (10) */
     int32_t pool_slots;    /* tree-node state slots resident on the device (0: none) */
     int32_t pool_stride;   /* bodies per pool slot (>= bodies of any pooled env) */
+    int32_t max_horizon;   /* pushes per environment in one rollout (8) */
     float dt;              /* substep (1/240 s) */
     float gravity;         /* along -z (9.81) */
     float margin;          /* contact and AABB margin (0.002 m) */
@@ -131,6 +132,29 @@ pmbs_status pmbs_sim_get_state(pmbs_sim_t* sim, float* state_out, int32_t dst_is
 pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_device,
                           int32_t n_substeps);
 
+/* rollout flags */
+#define PMBS_ROLLOUT_WRITE_STATE 1 /* write each env's final state back to its slot */
+#define PMBS_ROLLOUT_QUEUE 2       /* persistent launch pulling envs longest-horizon first */
+
+/* Batch expansion + batch simulation (Sec. IV-C) in one launch: env e runs
+ * the contour pushes actions[act_offset[e] .. act_offset[e+1]) (packed as
+ * obj * 8 + dir: direction dir of 8 around object obj, Sec. IV-B), each
+ * resolved from the current state when it starts, with n_substeps substeps
+ * per push and the retrieval reward (see pmbs_eval_reward, width) after each
+ * push into d_rewards[e * max_h + t]; it stops after the first reward of 1.
+ * A push starting inside a box is discarded: as the first push it ends the
+ * env (PMBS_ENV_PUSH_INVALID, no reward); later it leaves the state and
+ * repeats the previous reward.  src_slot[e] >= 0 loads the env from that
+ * pool slot instead of its own state; child_slot[e] >= 0 stores the state
+ * after the first push there (the expanded tree node).  d_reward_count[e]
+ * (optional, device) receives the number of rewards written.  Integer
+ * inputs are host or device per inputs_on_device (PMBS_ROLLOUT_QUEUE needs
+ * host inputs).  Asynchronous. */
+pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int32_t* act_offset,
+                             const int32_t* src_slot, const int32_t* child_slot, const int32_t* target,
+                             int32_t inputs_on_device, int32_t n_substeps, float width, float* d_rewards,
+                             int32_t max_h, int32_t* d_reward_count, int32_t flags);
+
 /* Status word per environment, cleared by every step.  A host destination
  * synchronises. */
 pmbs_status pmbs_sim_env_status(pmbs_sim_t* sim, uint32_t* status_out, int32_t dst_is_device);
@@ -151,9 +175,10 @@ pmbs_status pmbs_sim_collide(pmbs_sim_t* sim, const float* push, int32_t push_is
 pmbs_status pmbs_eval_reward(pmbs_sim_t* sim, const int32_t* target, int32_t target_is_device,
                              float width, float* d_reward, float* d_clearance);
 
-/* Per environment, summed over the substeps of the last step: contacts
- * solved and candidate pairs from the broadphase (int64 [n_envs][2], host;
- * synchronises).  The benchmark turns these into algorithmic work. */
+/* Per environment, over the last step or rollout: contacts solved and
+ * candidate pairs from the broadphase summed over substeps, and the number
+ * of substeps run (int64 [n_envs][3], host; synchronises).  The benchmark
+ * turns these into algorithmic work. */
 pmbs_status pmbs_sim_stats(pmbs_sim_t* sim, int64_t* out);
 
 /* ------------------------------------------------------------------ */
@@ -174,6 +199,88 @@ pmbs_status pmbs_sim_sync(pmbs_sim_t* sim);
 
 /* Number of environments and bodies of the loaded state. */
 pmbs_status pmbs_sim_shape(const pmbs_sim_t* sim, int32_t* n_envs, int32_t* n_bodies);
+
+/* ------------------------------------------------------------------ */
+/* host UCT tree (Eq. 2, Alg. 2) and the planning loop (Alg. 1)        */
+/* ------------------------------------------------------------------ */
+
+typedef struct pmbs_tree_config {
+    double c;           /* exploration constant of Eq. (2) (1.4) */
+    double gamma;       /* discount of rewards along rollouts and up the tree (0.8) */
+    int32_t max_depth;  /* pushes from the root, tree and rollout together (5) */
+    int32_t n_envs;     /* leaves expanded and simulated per iteration, N_e (256) */
+    int32_t max_nodes;  /* node and pool-slot capacity (65536) */
+    int32_t n_dirs;     /* contour directions per object, N_a (8) */
+    uint64_t seed;      /* Philox key of action orders and random pushes */
+} pmbs_tree_config;
+
+typedef struct pmbs_tree pmbs_tree_t;
+
+typedef struct pmbs_node_info {
+    int32_t parent, action, depth, pool_slot, n_children, terminal;
+    float reward;       /* retrieval reward after the push that made the node */
+    double Q;           /* sum of backed-up returns */
+    int64_t N;          /* visits */
+} pmbs_node_info;
+
+void pmbs_tree_config_default(pmbs_tree_config* cfg);
+
+/* A tree over a scene of n_objects cuboids (actions obj * n_dirs + dir);
+ * the root is node 0 in pool slot 0 with reward root_reward (a root with
+ * reward 1 is terminal and nothing is selected). */
+pmbs_status pmbs_tree_create(const pmbs_tree_config* cfg, int32_t n_objects, float root_reward,
+                             pmbs_tree_t** out);
+void pmbs_tree_destroy(pmbs_tree_t* tree);
+
+/* Selection with virtual loss (Alg. 2, Eq. 2): up to n_envs unique
+ * (node, action) pairs; N^ is incremented on the node and its ancestors
+ * during the phase and reset after it.  The remaining envs replicate the
+ * pairs round-robin (leaf parallelisation).  Outputs, host, n_envs entries
+ * each: act_offset [n_envs+1] and actions (the pair's action followed by
+ * the replica's random pushes down to max_depth, Philox-keyed), src_slot
+ * (the node's pool slot) and child_slot (the new node's slot for the first
+ * replica of a pair, else -1).  n_pairs = 0 when nothing is selectable. */
+pmbs_status pmbs_tree_select(pmbs_tree_t* tree, int32_t* n_pairs, int32_t* actions, int32_t* act_offset,
+                             int32_t* src_slot, int32_t* child_slot, int32_t* n_envs);
+
+/* Expansion and backpropagation from the rollout of the last selection:
+ * rewards [n_envs][max_h], counts [n_envs] and env_status (host).  A pair
+ * whose first push was discarded makes no node; otherwise its child gets
+ * the reward of its push, and every node on the path gets
+ * Q += gamma^j * G, N += 1 with G the maximum over the pair's replicas of
+ * max_t gamma^t r_t (Sec. IV-C, backpropagation). */
+pmbs_status pmbs_tree_update(pmbs_tree_t* tree, const float* rewards, int32_t max_h, const int32_t* counts,
+                             const uint32_t* env_status, int32_t* n_children);
+
+/* The root child with the best average reward Q/N (Sec. III-B); ties to
+ * more visits, then the lower action.  action = -1 without children. */
+pmbs_status pmbs_tree_best(const pmbs_tree_t* tree, int32_t* action, double* value, int64_t* visits);
+pmbs_status pmbs_tree_node(const pmbs_tree_t* tree, int32_t id, pmbs_node_info* out);
+pmbs_status pmbs_tree_size(const pmbs_tree_t* tree, int32_t* n_nodes, int64_t* simulations,
+                           int32_t* pool_slots_used);
+
+typedef struct pmbs_plan_result {
+    int32_t action;        /* best root action, -1 if none */
+    float push[4];         /* that action as a push (x_s, y_s, x_e, y_e) from the root state */
+    double value;          /* its average reward */
+    int64_t visits;
+    int32_t iterations;
+    int32_t nodes;
+    int64_t simulations;   /* rollouts run */
+    int64_t env_substeps;  /* substeps simulated */
+    double seconds;        /* wall time of the call */
+} pmbs_plan_result;
+
+/* Parallel MCTS with batched simulation: iters iterations of select (host)
+ * -> expand + simulate every leaf replica in one device launch -> read back
+ * rewards -> expand + backpropagate (host), then the best root action.
+ * The scene (root_state SoA [13][n_bodies], body [5][n_bodies], host) is
+ * loaded into tree->n_envs environments of sim; sim needs max_envs >=
+ * n_envs, max_bodies >= n_envs * n_bodies, pool_slots >= max_nodes,
+ * pool_stride >= n_bodies, max_horizon >= max_depth.  Synchronous. */
+pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_state, const float* body,
+                      int32_t n_bodies, int32_t target, int32_t iters, int32_t n_substeps, float width,
+                      pmbs_plan_result* out);
 
 #ifdef __cplusplus
 }

@@ -225,5 +225,5 @@ def rollout(cfg, state, body, obj_dir, substeps: int, target: int, width: float 
                           target, width, _d(rew), _i(val), _d(child), C.byref(status))
     if k < 0:
         raise ValueError("orc_rollout failed")
-    return dict(state=st, rewards=rew[:k].copy(), valid=val[:k].copy(), child_state=child,
+    return dict(state=st, rewards=rew[:k].copy(), valid=val[:max(k, 1)].copy(), child_state=child,
                 applied=k, status=status.value)

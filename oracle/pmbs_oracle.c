@@ -893,9 +893,12 @@ int orc_contour_push(const orc_config* cfg, const double* state13, const double*
 
 /* Rollout of one env through a sequence of contour pushes (obj, dir) with a
  * reward after every push (Sec. IV-C, batch simulation); stops after the
- * first push whose reward is 1.  state is updated in place; child_state (if
+ * first push whose reward is 1.  A push whose start pose overlaps a box is
+ * discarded (Sec. IV-B): the first one ends the rollout (the expansion is
+ * not executable, valid[0] = 0); a later one leaves the state as it is and
+ * repeats the previous reward.  state is updated in place; child_state (if
  * given) receives the state after the first push.  Returns the number of
- * pushes applied. */
+ * rewards written. */
 int orc_rollout(const orc_config* cfg, int32_t nb, double* state, const double* body,
                 const int32_t* obj_dir, int32_t n_push, int32_t n_dirs, int32_t substeps,
                 int32_t target, double width, double* rewards, int32_t* valid,
@@ -912,6 +915,12 @@ int orc_rollout(const orc_config* cfg, int32_t nb, double* state, const double* 
         contour_push(cfg, &e.body[obj], dir, n_dirs, push);
         push_begin(&e, cfg, push);
         if (valid) valid[t] = e.valid;
+        if (!e.valid) {
+            if (t == 0) break;
+            rewards[t] = rewards[t - 1];
+            ++applied;
+            continue;
+        }
         for (int k = 0; k < substeps; ++k) substep(&e, cfg, k, 0);
         double r = clearance(&e, target);
         rewards[t] = r > width ? 1.0 : r / width;

@@ -219,4 +219,6 @@ class PhysicsEnv:
     def run(self, state, actions):
         od = [(a // self.n_dirs, a % self.n_dirs) for a in actions]
         r = self.O.rollout(self.cfg, state, self.body, od, self.substeps, self.target, self.width, self.n_dirs)
-        return bool(r["valid"][0]), r["child_state"], list(r["rewards"])
+        if not r["valid"][0]:
+            return False, None, []
+        return True, r["child_state"], list(r["rewards"])

@@ -12,7 +12,8 @@ struct Params {
   float dt, gravity, margin, beta, slop, mu_plane, mu_pusher;
   float phx, phy, phz, pusher_z, push_speed;
   float tau_face, tau_edge, edge_eps;
-  int iters;
+  float push_length, push_standoff;
+  int iters, n_dirs;
 };
 
 struct StepArgs {
@@ -23,8 +24,23 @@ struct StepArgs {
   uint32_t* env_status;     // [n_envs]
   int* dbg_count;           // collide-only outputs
   float* dbg_contacts;
-  long long* stats;         // optional [n_envs][2]: sum over substeps of contacts, candidate pairs
+  long long* stats;         // optional [n_envs][3]: sums over substeps of contacts, candidate pairs; substeps
   int n_envs, env_base, n_substeps, stride, collide_only;
+  // rollout mode: contour pushes per env (actions[act_offset[e]..act_offset[e+1]),
+  // packed obj * n_dirs + dir), reward after each push, child snapshot
+  const int* actions;
+  const int* act_offset;
+  const int* src_slot;      // pool slot each env starts from (null: env state)
+  const int* child_slot;    // pool slot for the state after the first push (-1: none)
+  const int* target;        // target body per env
+  float* pool;
+  float* rewards;           // [n_envs][max_h]
+  int* reward_count;        // [n_envs]
+  int pool_stride, max_h, write_state;
+  float width;
+  // work distribution
+  const int* order;         // work item -> env (null: identity)
+  int* queue;               // device counter (null: one block per work item)
   Params p;
 };
 
@@ -48,7 +64,8 @@ struct PoolArgs {
 };
 
 hipError_t launch_pool(const PoolArgs& a, hipStream_t stream);
-hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream);
+int step_blocks_per_cu(int max_contacts);
+hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream, int grid = 0);
 hipError_t launch_reward(const RewardArgs& a, hipStream_t stream);
 
 }  // namespace pmbs

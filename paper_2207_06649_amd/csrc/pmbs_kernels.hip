@@ -396,37 +396,125 @@ __device__ __forceinline__ void prep_contact(const Smem<K>& s, int c, const Para
   }
 }
 
-// ------------------------------------------------------------------ the step kernel
+// ------------------------------------------------------------------ footprint distance (reward)
+// Footprint of a box = its projection on the table (a zonotope with
+// generators h_k a_k projected).  Overlap: a separating axis among the
+// generators' normals.  Distance when disjoint: minimum over projected
+// vertices of one against the projected box edges of the other (the
+// silhouette edges are among them).
+struct Foot {
+  float cx, cy;
+  float gx[3], gy[3];
+};
+
+__device__ __forceinline__ float seg_dist(float px, float py, float ax, float ay, float bx, float by) {
+  float dx = bx - ax, dy = by - ay;
+  float l2 = dx * dx + dy * dy;
+  float t = l2 > 0.0f ? ((px - ax) * dx + (py - ay) * dy) / l2 : 0.0f;
+  t = fminf(fmaxf(t, 0.0f), 1.0f);
+  float ex = ax + t * dx - px, ey = ay + t * dy - py;
+  return sqrtf(ex * ex + ey * ey);
+}
+
+__device__ __forceinline__ void foot_vertex(const Foot& f, int k, float* x, float* y) {
+  float sx = (k & 1) ? 1.0f : -1.0f, sy = (k & 2) ? 1.0f : -1.0f, sz = (k & 4) ? 1.0f : -1.0f;
+  *x = f.cx + (f.gx[0] * sx + f.gx[1] * sy + f.gx[2] * sz);
+  *y = f.cy + (f.gy[0] * sx + f.gy[1] * sy + f.gy[2] * sz);
+}
+
+__device__ __forceinline__ float foot_point_dist(const Foot& P, const Foot& Q) {
+  // min over vertices of P to the 12 projected edges of Q
+  float best = INFINITY;
+  for (int i = 0; i < 8; ++i) {
+    float px, py;
+    foot_vertex(P, i, &px, &py);
+    for (int a = 0; a < 8; ++a) {
+#pragma unroll
+      for (int bit = 1; bit < 8; bit <<= 1) {
+        if (a & bit) continue;
+        float ax, ay, bx, by;
+        foot_vertex(Q, a, &ax, &ay);
+        foot_vertex(Q, a | bit, &bx, &by);
+        best = fminf(best, seg_dist(px, py, ax, ay, bx, by));
+      }
+    }
+  }
+  return best;
+}
+
+__device__ __forceinline__ bool foot_separated_by(const Foot& F, const Foot& P, const Foot& Q, float dx, float dy) {
+  bool sep = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float lx = -F.gy[k], ly = F.gx[k];
+    float rp = fabsf(P.gx[0] * lx + P.gy[0] * ly) + fabsf(P.gx[1] * lx + P.gy[1] * ly) + fabsf(P.gx[2] * lx + P.gy[2] * ly);
+    float rq = fabsf(Q.gx[0] * lx + Q.gy[0] * ly) + fabsf(Q.gx[1] * lx + Q.gy[1] * ly) + fabsf(Q.gx[2] * lx + Q.gy[2] * ly);
+    if (fabsf(dx * lx + dy * ly) > rp + rq) sep = true;
+  }
+  return sep;
+}
+
+__device__ __forceinline__ float foot_distance(const Foot& P, const Foot& Q) {
+  const float dx = Q.cx - P.cx, dy = Q.cy - P.cy;
+  if (!(foot_separated_by(P, P, Q, dx, dy) || foot_separated_by(Q, P, Q, dx, dy))) return 0.0f;
+  return fminf(foot_point_dist(P, Q), foot_point_dist(Q, P));
+}
+
+// footprint from the body frame: centre, rotation columns, half extents
+__device__ __forceinline__ Foot foot_of(f3 c, f3 a0, f3 a1, f3 a2, f3 h) {
+  Foot f;
+  f.cx = c.x;
+  f.cy = c.y;
+  f.gx[0] = a0.x * h.x; f.gx[1] = a1.x * h.y; f.gx[2] = a2.x * h.z;
+  f.gy[0] = a0.y * h.x; f.gy[1] = a1.y * h.y; f.gy[2] = a2.y * h.z;
+  return f;
+}
+
+// rotation columns of a unit quaternion (body to world)
+__device__ __forceinline__ void quat_cols(float q0, float q1, float q2, float q3, f3* c0, f3* c1, f3* c2) {
+  *c0 = mk(1 - 2 * (q2 * q2 + q3 * q3), 2 * (q1 * q2 + q0 * q3), 2 * (q1 * q3 - q0 * q2));
+  *c1 = mk(2 * (q1 * q2 - q0 * q3), 1 - 2 * (q1 * q1 + q3 * q3), 2 * (q2 * q3 + q0 * q1));
+  *c2 = mk(2 * (q1 * q3 + q0 * q2), 2 * (q2 * q3 - q0 * q1), 1 - 2 * (q1 * q1 + q2 * q2));
+}
+
+// ------------------------------------------------------------------ one environment
+// Runs env e through its pushes: one explicit push (step mode) or a list of
+// contour pushes (rollout mode, with a reward after each push).
 template <int K>
-__global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
-  __shared__ Smem<K> s;
+__device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int e) {
   constexpr int C = Smem<K>::C;
   const Params& p = g.p;
   const int lane = threadIdx.x;
   const int b = lane & 31;
   const int part = lane >> 5;
-  const int e = g.env_base + blockIdx.x;
-  if (e >= g.n_envs) return;
   const int base = g.env_offset[e];
   const int nb = g.env_offset[e + 1] - base;
   const bool active = b < nb;
   const int N = g.stride;
   const float dt = p.dt;
+  const bool rollout = g.actions != nullptr;
+  const int act0 = rollout ? g.act_offset[e] : 0;
+  const int n_push = rollout ? g.act_offset[e + 1] - act0 : 1;
+  const int src = (rollout && g.src_slot) ? g.src_slot[e] : -1;
+  const int PS = g.pool_stride;
 
-  // ---- load (coalesced SoA): part 0 linear, part 1 angular
+  // ---- load (coalesced SoA): part 0 linear, part 1 angular; from the env
+  // arrays or from the state pool slot of the node being expanded
   f3 x = mk(0, 0, 0), v = mk(0, 0, 0), w = mk(0, 0, 0), h = mk(0, 0, 0), invI = mk(0, 0, 0);
   float q0 = 1, q1 = 0, q2 = 0, q3 = 0, invm = 0, mu = 0;
   if (active) {
     const int i = base + b;
-    const float* st = g.state;
+    const float* st = src >= 0 ? g.pool + (size_t)src * 13 * PS : g.state;
+    const int SN = src >= 0 ? PS : N;
+    const int si = src >= 0 ? b : i;
     const float* bc = g.bconst;
     if (part == 0) {
-      x = mk(st[0 * N + i], st[1 * N + i], st[2 * N + i]);
-      v = mk(st[7 * N + i], st[8 * N + i], st[9 * N + i]);
+      x = mk(st[0 * SN + si], st[1 * SN + si], st[2 * SN + si]);
+      v = mk(st[7 * SN + si], st[8 * SN + si], st[9 * SN + si]);
       invm = bc[3 * N + i];
     } else {
-      q0 = st[3 * N + i]; q1 = st[4 * N + i]; q2 = st[5 * N + i]; q3 = st[6 * N + i];
-      w = mk(st[10 * N + i], st[11 * N + i], st[12 * N + i]);
+      q0 = st[3 * SN + si]; q1 = st[4 * SN + si]; q2 = st[5 * SN + si]; q3 = st[6 * SN + si];
+      w = mk(st[10 * SN + si], st[11 * SN + si], st[12 * SN + si]);
       invI = mk(bc[4 * N + i], bc[5 * N + i], bc[6 * N + i]);
     }
     h = mk(bc[0 * N + i], bc[1 * N + i], bc[2 * N + i]);
@@ -444,30 +532,10 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
     s.ang[PLANE] = make_float4(0, 0, 0, 0);
     s.cnt[PLANE] = 1;
   }
-
-  // ---- push begin (uniform across the wave)
-  float4 push = g.push ? g.push[e] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  bool have_push = g.push != nullptr;
-  f3 pdir = mk(1, 0, 0);
-  int n_move = 0;
-  f3 xp = mk(0, 0, 10.0f);
-  f3 pc0 = mk(1, 0, 0), pc1 = mk(0, 1, 0);
-  if (have_push) {
-    float dx = push.z - push.x, dy = push.w - push.y;
-    float len = sqrtf(dx * dx + dy * dy);
-    if (len > 0.0f) pdir = mk(dx / len, dy / len, 0.0f);
-    n_move = (int)roundf(len / (p.push_speed * dt));
-    xp = mk(push.x, push.y, p.pusher_z);
-    float yaw = atan2f(pdir.y, pdir.x);
-    float cy = cosf(0.5f * yaw), sy = sinf(0.5f * yaw);
-    // rotation about z from the half-angle quaternion (cy, 0, 0, sy)
-    pc0 = mk(1.0f - 2.0f * sy * sy, 2.0f * cy * sy, 0.0f);
-    pc1 = mk(-2.0f * cy * sy, 1.0f - 2.0f * sy * sy, 0.0f);
-  }
   const f3 ph = mk(p.phx, p.phy, p.phz);
 
-  // frames of the bodies + the pusher entry (index nb)
-  auto write_frames = [&](f3 vp) {
+  // frames of the bodies (centre, rotation, inverse mass / inertia)
+  auto write_body_frames = [&]() {
     if (active) {
       if (part == 0) {
         s.pos[b] = f4(x, 0.0f);
@@ -490,6 +558,66 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
         s.iwb[b] = make_float4(xz, yz, mu, 0.0f);
       }
     }
+  };
+
+  Contact ct[K];
+  uint32_t status = 0u;
+  float last_r = 0.0f;
+  int n_rewards = 0;
+  long long stat_nc = 0, stat_pairs = 0, stat_sub = 0;
+  const int n_obj = nb + 1;
+
+  for (int t = 0; t < n_push; ++t) {
+  // ---- push begin (uniform across the wave)
+  write_body_frames();
+  wave_sync();
+  bool have_push;
+  float4 push = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (rollout) {
+    // contour push (Sec. IV-B): direction dir of n_dirs around object obj in
+    // its yaw frame, starting beyond the footprint's ray-to-boundary
+    // distance by the pusher half width plus the standoff, moving
+    // push_length toward the object centre
+    const int act = g.actions[act0 + t];
+    const int obj = act / p.n_dirs, dir = act - obj * p.n_dirs;
+    have_push = obj >= 0 && obj < nb;
+    if (have_push) {
+      const f3 oc = xyz(s.pos[obj]), oa0 = xyz(s.col[0][obj]), oh = xyz(s.half[obj]);
+      const float th = 6.283185307179586f * (float)dir / (float)p.n_dirs;
+      const float cth = cosf(th), sth = sinf(th);
+      const float rx = fabsf(cth) > 0.0f ? oh.x / fabsf(cth) : INFINITY;
+      const float ry = fabsf(sth) > 0.0f ? oh.y / fabsf(sth) : INFINITY;
+      const float ray = fminf(rx, ry);
+      const float yaw = atan2f(oa0.y, oa0.x);
+      const float cy = cosf(yaw), sy = sinf(yaw);
+      const float ddx = cy * cth - sy * sth, ddy = sy * cth + cy * sth;
+      const float off = ray + p.phx + p.push_standoff;
+      const float sxp = oc.x + off * ddx, syp = oc.y + off * ddy;
+      push = make_float4(sxp, syp, sxp - p.push_length * ddx, syp - p.push_length * ddy);
+    }
+  } else {
+    have_push = g.push != nullptr;
+    if (have_push) push = g.push[e];
+  }
+  f3 pdir = mk(1, 0, 0);
+  int n_move = 0;
+  f3 xp = mk(0, 0, 10.0f);
+  f3 pc0 = mk(1, 0, 0), pc1 = mk(0, 1, 0);
+  if (have_push) {
+    float dx = push.z - push.x, dy = push.w - push.y;
+    float len = sqrtf(dx * dx + dy * dy);
+    if (len > 0.0f) pdir = mk(dx / len, dy / len, 0.0f);
+    n_move = (int)roundf(len / (p.push_speed * dt));
+    xp = mk(push.x, push.y, p.pusher_z);
+    float yaw = atan2f(pdir.y, pdir.x);
+    float cy = cosf(0.5f * yaw), sy = sinf(0.5f * yaw);
+    // rotation about z from the half-angle quaternion (cy, 0, 0, sy)
+    pc0 = mk(1.0f - 2.0f * sy * sy, 2.0f * cy * sy, 0.0f);
+    pc1 = mk(-2.0f * cy * sy, 1.0f - 2.0f * sy * sy, 0.0f);
+  }
+
+  // the pusher entry (index nb)
+  auto write_pusher = [&](f3 vp) {
     if (lane == 32) {
       s.pos[nb] = f4(xp, 0.0f);
       s.col[0][nb] = f4(pc0, 0.0f);
@@ -503,11 +631,15 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
       s.cnt[nb] = 1;
     }
   };
+  auto write_frames = [&](f3 vp) {
+    write_body_frames();
+    write_pusher(vp);
+  };
 
   // validity of the start pose: SAT separation from every box must be > 0
   bool valid = false;
   if (have_push) {
-    write_frames(mk(0, 0, 0));
+    write_pusher(mk(0, 0, 0));
     wave_sync();
     bool bad = false;
     if (active && part == 0) {
@@ -522,14 +654,17 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
     pc1 = mk(0, 1, 0);
     n_move = 0;
   }
-  uint32_t status = (have_push && !valid) ? PMBS_ENV_PUSH_INVALID : 0u;
+  if (have_push && !valid && (!rollout || t == 0)) status |= PMBS_ENV_PUSH_INVALID;
+  if (rollout && !valid) {
+    // a discarded expansion push ends the rollout; a discarded random push
+    // leaves the state and repeats the previous reward
+    if (t == 0) break;
+    if (lane == 0) g.rewards[(size_t)e * g.max_h + t] = last_r;
+    n_rewards = t + 1;
+    continue;
+  }
 
-  // contact slots
-  Contact ct[K];
-
-  const int n_obj = nb + 1;
   const int n_sub = g.collide_only ? 1 : g.n_substeps;
-  long long stat_nc = 0, stat_pairs = 0;
   int nwarm = 0;  // impulses are carried within one push only
   for (int k = 0; k < n_sub; ++k) {
     // ---- 1. velocity stage
@@ -688,6 +823,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
     const int nc = nc_raw < C ? nc_raw : C;
     stat_nc += nc;
     stat_pairs += n_pairs;
+    stat_sub += 1;
     wave_sync();
 
     if (g.collide_only) {
@@ -864,6 +1000,52 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
     wave_sync();
   }
 
+  if (rollout) {
+    // ---- reward after the push: clearance of the target's footprint
+    write_body_frames();
+    wave_sync();
+    const int tg = g.target[e];
+    float d = INFINITY;
+    if (active && part == 0 && b != tg && tg >= 0 && tg < nb) {
+      const Foot T = foot_of(xyz(s.pos[tg]), xyz(s.col[0][tg]), xyz(s.col[1][tg]), xyz(s.col[2][tg]), xyz(s.half[tg]));
+      const Foot J = foot_of(x, xyz(s.col[0][b]), xyz(s.col[1][b]), xyz(s.col[2][b]), h);
+      d = foot_distance(T, J);
+    }
+    for (int o = 32; o > 0; o >>= 1) d = fminf(d, __shfl_xor(d, o, 64));
+    const float r = d > g.width ? 1.0f : d / g.width;
+    last_r = r;
+    n_rewards = t + 1;
+    if (lane == 0) g.rewards[(size_t)e * g.max_h + t] = r;
+    // the expanded child's state goes to its pool slot
+    const int cs = (t == 0 && g.child_slot) ? g.child_slot[e] : -1;
+    if (cs >= 0 && active) {
+      float* dst = g.pool + (size_t)cs * 13 * PS;
+      if (part == 0) {
+        dst[0 * PS + b] = x.x; dst[1 * PS + b] = x.y; dst[2 * PS + b] = x.z;
+        dst[7 * PS + b] = v.x; dst[8 * PS + b] = v.y; dst[9 * PS + b] = v.z;
+      } else {
+        dst[3 * PS + b] = q0; dst[4 * PS + b] = q1; dst[5 * PS + b] = q2; dst[6 * PS + b] = q3;
+        dst[10 * PS + b] = w.x; dst[11 * PS + b] = w.y; dst[12 * PS + b] = w.z;
+      }
+    }
+    wave_sync();
+    if (r >= 1.0f) break;
+  }
+  }  // pushes
+
+  if (rollout && lane == 0 && g.reward_count) g.reward_count[e] = n_rewards;
+  if (rollout && !g.write_state) {
+    if (lane == 0) {
+      g.env_status[e] = status;
+      if (g.stats) {
+        g.stats[3 * e] = stat_nc;
+        g.stats[3 * e + 1] = stat_pairs;
+        g.stats[3 * e + 2] = stat_sub;
+      }
+    }
+    return;
+  }
+
   // ---- write back
   bool bad = false;
   if (active) {
@@ -884,10 +1066,41 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
   if (lane == 0) {
     g.env_status[e] = status;
     if (g.stats) {
-      g.stats[2 * e] = stat_nc;
-      g.stats[2 * e + 1] = stat_pairs;
+      g.stats[3 * e] = stat_nc;
+      g.stats[3 * e + 1] = stat_pairs;
+      g.stats[3 * e + 2] = stat_sub;
     }
   }
+}
+
+// ------------------------------------------------------------------ the step kernel
+// One wave per environment.  Without a work queue block i runs work item
+// env_base + i; with one, blocks pull work items from the device counter
+// until it passes n_envs (every block reaches that exit).  order[] maps
+// work items to environments (longest horizon first for uneven rollouts).
+template <int K>
+__global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
+  __shared__ Smem<K> s;
+  __shared__ int next;
+  if (g.queue == nullptr) {
+    const int wi = g.env_base + blockIdx.x;
+    if (wi < g.n_envs) run_env<K>(s, g, g.order ? g.order[wi] : wi);
+    return;
+  }
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(g.queue, 1);
+    __syncthreads();
+    const int wi = next;
+    __syncthreads();
+    if (wi >= g.n_envs) break;
+    run_env<K>(s, g, g.order ? g.order[wi] : wi);
+    __syncthreads();
+  }
+}
+
+__global__ void zero_kernel(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 // ------------------------------------------------------------------ state pool
@@ -912,82 +1125,11 @@ __global__ __launch_bounds__(64) void pool_kernel(PoolArgs g) {
 }
 
 // ------------------------------------------------------------------ reward
-// Footprint of a box = projection of the box onto the table plane (a
-// zonotope with generators h_k * a_k projected).  Overlap test: separating
-// axis among the generators' normals.  Distance when disjoint: minimum over
-// projected vertices of one against projected box edges of the other (the
-// silhouette edges are among them).
-struct Foot {
-  float cx, cy;
-  float gx[3], gy[3];
-};
-
-__device__ __forceinline__ float seg_dist(float px, float py, float ax, float ay, float bx, float by) {
-  float dx = bx - ax, dy = by - ay;
-  float l2 = dx * dx + dy * dy;
-  float t = l2 > 0.0f ? ((px - ax) * dx + (py - ay) * dy) / l2 : 0.0f;
-  t = fminf(fmaxf(t, 0.0f), 1.0f);
-  float ex = ax + t * dx - px, ey = ay + t * dy - py;
-  return sqrtf(ex * ex + ey * ey);
-}
-
-__device__ __forceinline__ void foot_vertex(const Foot& f, int k, float* x, float* y) {
-  float sx = (k & 1) ? 1.0f : -1.0f, sy = (k & 2) ? 1.0f : -1.0f, sz = (k & 4) ? 1.0f : -1.0f;
-  *x = f.cx + (f.gx[0] * sx + f.gx[1] * sy + f.gx[2] * sz);
-  *y = f.cy + (f.gy[0] * sx + f.gy[1] * sy + f.gy[2] * sz);
-}
-
-__device__ float foot_point_dist(const Foot& P, const Foot& Q) {
-  // min over vertices of P to the 12 projected edges of Q
-  float best = INFINITY;
-  for (int i = 0; i < 8; ++i) {
-    float px, py;
-    foot_vertex(P, i, &px, &py);
-    for (int a = 0; a < 8; ++a) {
-      for (int bit = 1; bit < 8; bit <<= 1) {
-        if (a & bit) continue;
-        float ax, ay, bx, by;
-        foot_vertex(Q, a, &ax, &ay);
-        foot_vertex(Q, a | bit, &bx, &by);
-        best = fminf(best, seg_dist(px, py, ax, ay, bx, by));
-      }
-    }
-  }
-  return best;
-}
-
-__device__ float foot_distance(const Foot& P, const Foot& Q) {
-  float dx = Q.cx - P.cx, dy = Q.cy - P.cy;
-  bool sep = false;
-  for (int pass = 0; pass < 2; ++pass) {
-    const Foot& F = pass ? Q : P;
-    for (int k = 0; k < 3; ++k) {
-      float lx = -F.gy[k], ly = F.gx[k];
-      float rp = fabsf(P.gx[0] * lx + P.gy[0] * ly) + fabsf(P.gx[1] * lx + P.gy[1] * ly) +
-                 fabsf(P.gx[2] * lx + P.gy[2] * ly);
-      float rq = fabsf(Q.gx[0] * lx + Q.gy[0] * ly) + fabsf(Q.gx[1] * lx + Q.gy[1] * ly) +
-                 fabsf(Q.gx[2] * lx + Q.gy[2] * ly);
-      if (fabsf(dx * lx + dy * ly) > rp + rq) sep = true;
-    }
-  }
-  if (!sep) return 0.0f;
-  return fminf(foot_point_dist(P, Q), foot_point_dist(Q, P));
-}
-
-__device__ Foot make_foot(const float* st, const float* bc, int N, int i) {
-  float q0 = st[3 * N + i], q1 = st[4 * N + i], q2 = st[5 * N + i], q3 = st[6 * N + i];
-  float hx = bc[0 * N + i], hy = bc[1 * N + i], hz = bc[2 * N + i];
-  Foot f;
-  f.cx = st[0 * N + i];
-  f.cy = st[1 * N + i];
-  // first two rows of the rotation matrix, columns scaled by the half extents
-  f.gx[0] = (1 - 2 * (q2 * q2 + q3 * q3)) * hx;
-  f.gx[1] = 2 * (q1 * q2 - q0 * q3) * hy;
-  f.gx[2] = 2 * (q1 * q3 + q0 * q2) * hz;
-  f.gy[0] = 2 * (q1 * q2 + q0 * q3) * hx;
-  f.gy[1] = (1 - 2 * (q1 * q1 + q3 * q3)) * hy;
-  f.gy[2] = 2 * (q2 * q3 - q0 * q1) * hz;
-  return f;
+__device__ __forceinline__ Foot load_foot(const float* st, const float* bc, int N, int i) {
+  f3 c0, c1, c2;
+  quat_cols(st[3 * N + i], st[4 * N + i], st[5 * N + i], st[6 * N + i], &c0, &c1, &c2);
+  return foot_of(mk(st[0 * N + i], st[1 * N + i], st[2 * N + i]), c0, c1, c2,
+                 mk(bc[0 * N + i], bc[1 * N + i], bc[2 * N + i]));
 }
 
 __global__ __launch_bounds__(64) void reward_kernel(RewardArgs g) {
@@ -999,10 +1141,10 @@ __global__ __launch_bounds__(64) void reward_kernel(RewardArgs g) {
   const int t = g.target[e];
   float d = INFINITY;
   if (t >= 0 && t < nb) {
-    Foot T = make_foot(g.state, g.bconst, g.stride, base + t);
+    const Foot T = load_foot(g.state, g.bconst, g.stride, base + t);
     for (int j = lane; j < nb; j += 64) {
       if (j == t) continue;
-      Foot J = make_foot(g.state, g.bconst, g.stride, base + j);
+      const Foot J = load_foot(g.state, g.bconst, g.stride, base + j);
       d = fminf(d, foot_distance(T, J));
     }
   } else {
@@ -1016,9 +1158,22 @@ __global__ __launch_bounds__(64) void reward_kernel(RewardArgs g) {
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream) {
+hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream, int grid) {
   const int n = a.n_envs - a.env_base;
   if (n <= 0) return hipSuccess;
+  if (a.queue) {
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, stream, a.queue, 1);
+  }
+  if (grid > 0 && a.queue && grid < n) {
+    if (max_contacts <= 128) {
+      hipLaunchKernelGGL(step_kernel<2>, dim3(grid), dim3(64), 0, stream, a);
+    } else if (max_contacts <= 256) {
+      hipLaunchKernelGGL(step_kernel<4>, dim3(grid), dim3(64), 0, stream, a);
+    } else {
+      hipLaunchKernelGGL(step_kernel<8>, dim3(grid), dim3(64), 0, stream, a);
+    }
+    return hipGetLastError();
+  }
   if (max_contacts <= 128) {
     hipLaunchKernelGGL(step_kernel<2>, dim3(n), dim3(64), 0, stream, a);
   } else if (max_contacts <= 256) {
@@ -1027,6 +1182,15 @@ hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream) 
     hipLaunchKernelGGL(step_kernel<8>, dim3(n), dim3(64), 0, stream, a);
   }
   return hipGetLastError();
+}
+
+int step_blocks_per_cu(int max_contacts) {
+  int n = 0;
+  hipError_t e;
+  if (max_contacts <= 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2>, 64, 0);
+  else if (max_contacts <= 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<4>, 64, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<8>, 64, 0);
+  return e == hipSuccess ? n : 0;
 }
 
 hipError_t launch_pool(const PoolArgs& a, hipStream_t stream) {

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -38,7 +39,8 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace regions, in order.  Every region starts 256-byte aligned.
 struct Layout {
-  size_t state, bconst, env_offset, push, status, target, reward, clearance, slots, stats, pool, total;
+  size_t state, bconst, env_offset, push, status, target, reward, clearance, slots, stats, pool;
+  size_t actions, act_offset, src_slot, child_slot, order, queue, roll_rewards, roll_counts, total;
 };
 
 static Layout layout_of(const pmbs_sim_config& c) {
@@ -59,8 +61,16 @@ static Layout layout_of(const pmbs_sim_config& c) {
   L.reward = take(ne * sizeof(float));
   L.clearance = take(ne * sizeof(float));
   L.slots = take(ne * sizeof(int32_t));
-  L.stats = take(ne * 2 * sizeof(long long));
+  L.stats = take(ne * 3 * sizeof(long long));
   L.pool = take((size_t)c.pool_slots * (size_t)c.pool_stride * 13 * sizeof(float));
+  L.actions = take(ne * (size_t)c.max_horizon * sizeof(int32_t));
+  L.act_offset = take((ne + 1) * sizeof(int32_t));
+  L.src_slot = take(ne * sizeof(int32_t));
+  L.child_slot = take(ne * sizeof(int32_t));
+  L.order = take(ne * sizeof(int32_t));
+  L.queue = take(64);
+  L.roll_rewards = take(ne * (size_t)c.max_horizon * sizeof(float));
+  L.roll_counts = take(ne * sizeof(int32_t));
   L.total = o;
   return L;
 }
@@ -72,6 +82,7 @@ static pmbs_status check_config(const pmbs_sim_config* c) {
     return fail(PMBS_ERR_INVALID_ARG, "max_contacts must be 128, 256 or 512 (got %d)", c->max_contacts);
   if (c->solver_iters < 0 || c->solver_iters > 1000) return fail(PMBS_ERR_INVALID_ARG, "solver_iters out of range");
   if (c->pool_slots < 0 || c->pool_stride < 0) return fail(PMBS_ERR_INVALID_ARG, "pool sizes must be >= 0");
+  if (c->max_horizon < 1 || c->max_horizon > 64) return fail(PMBS_ERR_INVALID_ARG, "max_horizon must be in [1, 64]");
   if (c->pool_slots > 0 && (c->pool_stride <= 0 || c->pool_stride > PMBS_MAX_BODIES_PER_ENV))
     return fail(PMBS_ERR_INVALID_ARG, "pool_stride must be in [1, %d]", PMBS_MAX_BODIES_PER_ENV);
   if (!(c->dt > 0) || !(c->push_speed > 0) || !(c->margin >= 0))
@@ -98,7 +109,10 @@ Params params_of(const pmbs_sim_config& c) {
   p.tau_face = c.tau_face;
   p.tau_edge = c.tau_edge;
   p.edge_eps = c.edge_eps;
+  p.push_length = c.push_length;
+  p.push_standoff = c.push_standoff;
   p.iters = c.solver_iters;
+  p.n_dirs = 8;
   return p;
 }
 
@@ -124,6 +138,19 @@ static pmbs_status stage_push(pmbs_sim_t* sim, const float* push, int32_t push_i
   }
   *d_push = reinterpret_cast<const float4*>(sim->d_push);
   return PMBS_OK;
+}
+
+// blocks that fit on the device at once for the configured contact class
+int persistent_grid(pmbs_sim_t* sim) {
+  if (sim->grid_cache > 0) return sim->grid_cache;
+  int dev = 0, cus = 256, per_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  }
+  per_cu = step_blocks_per_cu(sim->cfg.max_contacts);
+  sim->grid_cache = cus * (per_cu > 0 ? per_cu : 1);
+  return sim->grid_cache;
 }
 
 StepArgs step_args(pmbs_sim_t* sim) {
@@ -169,6 +196,7 @@ void pmbs_sim_config_default(pmbs_sim_config* c) {
   c->solver_iters = 10;
   c->pool_slots = 0;
   c->pool_stride = 0;
+  c->max_horizon = 8;
   c->dt = 1.0f / 240.0f;
   c->gravity = 9.81f;
   c->margin = 0.002f;
@@ -222,6 +250,14 @@ pmbs_status pmbs_sim_create(const pmbs_sim_config* cfg, void* d_workspace, size_
   s->d_slots = reinterpret_cast<int32_t*>(base + L.slots);
   s->d_stats = reinterpret_cast<long long*>(base + L.stats);
   s->d_pool = cfg->pool_slots > 0 ? reinterpret_cast<float*>(base + L.pool) : nullptr;
+  s->d_actions = reinterpret_cast<int32_t*>(base + L.actions);
+  s->d_act_offset = reinterpret_cast<int32_t*>(base + L.act_offset);
+  s->d_src_slot = reinterpret_cast<int32_t*>(base + L.src_slot);
+  s->d_child_slot = reinterpret_cast<int32_t*>(base + L.child_slot);
+  s->d_order = reinterpret_cast<int32_t*>(base + L.order);
+  s->d_queue = reinterpret_cast<int32_t*>(base + L.queue);
+  s->d_roll_rewards = reinterpret_cast<float*>(base + L.roll_rewards);
+  s->d_roll_counts = reinterpret_cast<int32_t*>(base + L.roll_counts);
   s->n_envs = 0;
   s->n_bodies = 0;
   hipError_t e = hipMemsetAsync(s->d_status, 0, (size_t)cfg->max_envs * sizeof(uint32_t), s->stream);
@@ -324,6 +360,102 @@ pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_de
   a.n_substeps = n_substeps;
   hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream);
   if (e != hipSuccess) return hip_fail(e, "step launch");
+  return PMBS_OK;
+}
+
+// upload a host array into a workspace region (or pass a device array through)
+static pmbs_status stage_ints(pmbs_sim_t* sim, const int32_t* src, size_t n, int32_t on_device, int32_t* region,
+                              const int32_t** out) {
+  if (!src) {
+    *out = nullptr;
+    return PMBS_OK;
+  }
+  if (on_device) {
+    *out = src;
+    return PMBS_OK;
+  }
+  if (n) {
+    hipError_t e = hipMemcpyAsync(region, src, n * sizeof(int32_t), hipMemcpyHostToDevice, sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "input upload");
+  }
+  *out = region;
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int32_t* act_offset, const int32_t* src_slot,
+                             const int32_t* child_slot, const int32_t* target, int32_t inputs_on_device,
+                             int32_t n_substeps, float width, float* d_rewards, int32_t max_h,
+                             int32_t* d_reward_count, int32_t flags) {
+  if (!sim || !actions || !act_offset || !target || !d_rewards) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (n_substeps < 0 || !(width > 0)) return fail(PMBS_ERR_INVALID_ARG, "n_substeps must be >= 0 and width > 0");
+  const int n = sim->n_envs;
+  if ((src_slot || child_slot) && !sim->d_pool) return fail(PMBS_ERR_CAPACITY, "rollout from/to pool slots needs a pool");
+  const bool use_queue = (flags & PMBS_ROLLOUT_QUEUE) != 0;
+  if (use_queue && inputs_on_device) return fail(PMBS_ERR_INVALID_ARG, "the work queue orders host inputs");
+  int total = 0;
+  std::vector<int32_t> order;
+  if (!inputs_on_device) {
+    if (act_offset[0] != 0) return fail(PMBS_ERR_INVALID_ARG, "act_offset[0] must be 0");
+    for (int e = 0; e < n; ++e) {
+      const int h = act_offset[e + 1] - act_offset[e];
+      if (h < 0 || h > max_h || h > sim->cfg.max_horizon)
+        return fail(PMBS_ERR_CAPACITY, "env %d: horizon %d outside [0, min(max_h, max_horizon)]", e, h);
+      const int nb = sim->host_offset[e + 1] - sim->host_offset[e];
+      for (int k = act_offset[e]; k < act_offset[e + 1]; ++k)
+        if (actions[k] < 0 || actions[k] >= nb * 8) return fail(PMBS_ERR_INVALID_ARG, "env %d: action %d out of range", e, actions[k]);
+      if (target[e] < 0 || target[e] >= nb) return fail(PMBS_ERR_INVALID_ARG, "env %d: target out of range", e);
+      if (src_slot && src_slot[e] >= sim->cfg.pool_slots) return fail(PMBS_ERR_CAPACITY, "env %d: source slot", e);
+      if (child_slot && child_slot[e] >= sim->cfg.pool_slots) return fail(PMBS_ERR_CAPACITY, "env %d: child slot", e);
+      if ((src_slot && src_slot[e] >= 0) || (child_slot && child_slot[e] >= 0))
+        if (nb > sim->cfg.pool_stride) return fail(PMBS_ERR_CAPACITY, "env %d: %d bodies > pool_stride", e, nb);
+    }
+    total = act_offset[n];
+    if (use_queue) {
+      // longest horizon first, ties by env index (deterministic schedule)
+      order.resize(n);
+      for (int e = 0; e < n; ++e) order[e] = e;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return act_offset[a + 1] - act_offset[a] > act_offset[b + 1] - act_offset[b];
+      });
+    }
+  } else if (max_h > sim->cfg.max_horizon) {
+    return fail(PMBS_ERR_CAPACITY, "max_h %d > max_horizon %d", max_h, sim->cfg.max_horizon);
+  }
+  if (n == 0) return PMBS_OK;
+  StepArgs a = step_args(sim);
+  const int32_t* p;
+  pmbs_status st;
+  if ((st = stage_ints(sim, actions, (size_t)total, inputs_on_device, sim->d_actions, &p)) != PMBS_OK) return st;
+  a.actions = p;
+  if ((st = stage_ints(sim, act_offset, (size_t)n + 1, inputs_on_device, sim->d_act_offset, &p)) != PMBS_OK) return st;
+  a.act_offset = p;
+  if ((st = stage_ints(sim, src_slot, (size_t)n, inputs_on_device, sim->d_src_slot, &p)) != PMBS_OK) return st;
+  a.src_slot = p;
+  if ((st = stage_ints(sim, child_slot, (size_t)n, inputs_on_device, sim->d_child_slot, &p)) != PMBS_OK) return st;
+  a.child_slot = p;
+  if ((st = stage_ints(sim, target, (size_t)n, inputs_on_device, sim->d_target, &p)) != PMBS_OK) return st;
+  a.target = p;
+  int grid = 0;
+  if (use_queue) {
+    if ((st = stage_ints(sim, order.data(), (size_t)n, 0, sim->d_order, &p)) != PMBS_OK) return st;
+    a.order = p;
+    a.queue = sim->d_queue;
+    grid = persistent_grid(sim);
+  }
+  if (!inputs_on_device) {
+    hipError_t e = hipStreamSynchronize(sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "rollout upload sync");
+  }
+  a.pool = sim->d_pool;
+  a.pool_stride = sim->cfg.pool_stride;
+  a.rewards = d_rewards;
+  a.reward_count = d_reward_count;
+  a.max_h = max_h;
+  a.width = width;
+  a.write_state = (flags & PMBS_ROLLOUT_WRITE_STATE) ? 1 : 0;
+  a.n_substeps = n_substeps;
+  hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream, grid);
+  if (e != hipSuccess) return hip_fail(e, "rollout launch");
   return PMBS_OK;
 }
 
@@ -441,7 +573,7 @@ pmbs_status pmbs_pool_scatter(pmbs_sim_t* sim, const int32_t* slots, int32_t slo
 pmbs_status pmbs_sim_stats(pmbs_sim_t* sim, int64_t* out) {
   if (!sim || !out) return fail(PMBS_ERR_INVALID_ARG, "null argument");
   if (sim->n_envs == 0) return PMBS_OK;
-  hipError_t e = hipMemcpyAsync(out, sim->d_stats, (size_t)sim->n_envs * 2 * sizeof(long long), hipMemcpyDeviceToHost,
+  hipError_t e = hipMemcpyAsync(out, sim->d_stats, (size_t)sim->n_envs * 3 * sizeof(long long), hipMemcpyDeviceToHost,
                                 sim->stream);
   if (e != hipSuccess) return hip_fail(e, "stats download");
   e = hipStreamSynchronize(sim->stream);

@@ -19,12 +19,15 @@ LIB_PATH = os.path.join(HERE, "libpmbs.so")
 PMBS_ENV_CONTACT_OVERFLOW = 1
 PMBS_ENV_NONFINITE = 2
 PMBS_ENV_PUSH_INVALID = 4
+ROLLOUT_WRITE_STATE = 1
+ROLLOUT_QUEUE = 2
 MAX_BODIES_PER_ENV = 31
 
 
 class SimConfig(C.Structure):
     _fields_ = [("max_envs", C.c_int32), ("max_bodies", C.c_int32), ("max_contacts", C.c_int32),
                 ("solver_iters", C.c_int32), ("pool_slots", C.c_int32), ("pool_stride", C.c_int32),
+                ("max_horizon", C.c_int32),
                 ("dt", C.c_float), ("gravity", C.c_float), ("margin", C.c_float), ("beta", C.c_float),
                 ("slop", C.c_float), ("mu_plane", C.c_float), ("mu_pusher", C.c_float),
                 ("pusher_half", C.c_float * 3), ("pusher_z", C.c_float), ("push_speed", C.c_float),
@@ -67,6 +70,8 @@ def lib():
         L.pmbs_sim_stats.argtypes = [vp, vp]
         L.pmbs_pool_gather.argtypes = [vp, vp, C.c_int32]
         L.pmbs_pool_scatter.argtypes = [vp, vp, C.c_int32]
+        L.pmbs_sim_rollout.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_float, vp, C.c_int32,
+                                       vp, C.c_int32]
         L.pmbs_sim_shape.argtypes = [vp, ip, ip]
         _lib = L
     return _lib
@@ -215,8 +220,9 @@ class Sim:
         return rew.cpu().numpy(), clr.cpu().numpy()
 
     def stats(self) -> np.ndarray:
-        """[E, 2] int64: contacts and candidate pairs summed over the last step's substeps."""
-        out = np.zeros((self.n_envs, 2), np.int64)
+        """[E, 3] int64: contacts and candidate pairs summed over the last
+        step's substeps, and the substeps run."""
+        out = np.zeros((self.n_envs, 3), np.int64)
         _check(lib().pmbs_sim_stats(self.handle, out.ctypes.data_as(C.c_void_p)))
         return out
 
@@ -236,5 +242,150 @@ class Sim:
         _check(lib().pmbs_pool_scatter(self.handle, ptr, dev))
         return keep
 
+    def rollout(self, actions, act_offset, target, n_substeps=120, width=0.08, src_slot=None, child_slot=None,
+                max_h=None, flags=ROLLOUT_WRITE_STATE, sync=True):
+        """Contour-push rollouts (host int inputs).  Returns (rewards [E, max_h],
+        counts [E]) as numpy when sync, else the device tensors."""
+        t = self.torch
+        off = np.ascontiguousarray(act_offset, np.int32)
+        acts = np.ascontiguousarray(actions, np.int32) if len(actions) else np.zeros(1, np.int32)
+        tg = np.ascontiguousarray(target, np.int32)
+        mh = int(max_h if max_h is not None else max(1, int(np.diff(off).max()) if len(off) > 1 else 1))
+        rew = t.full((self.n_envs, mh), -1.0, dtype=t.float32, device=self.device)
+        cnt = t.zeros(self.n_envs, dtype=t.int32, device=self.device)
+        keep = [off, acts, tg]
+        ss = cs = None
+        if src_slot is not None:
+            ss = np.ascontiguousarray(src_slot, np.int32)
+            keep.append(ss)
+        if child_slot is not None:
+            cs = np.ascontiguousarray(child_slot, np.int32)
+            keep.append(cs)
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
+        _check(lib().pmbs_sim_rollout(self.handle, ptr(acts), ptr(off), ptr(ss), ptr(cs), ptr(tg), 0, int(n_substeps),
+                                      float(width), _ptr(rew), mh, _ptr(cnt), int(flags)))
+        if not sync:
+            return rew, cnt
+        self.sync()
+        return rew.cpu().numpy(), cnt.cpu().numpy()
+
     def sync(self):
         _check(lib().pmbs_sim_sync(self.handle))
+
+
+# ---------------------------------------------------------------- tree / plan
+class TreeConfig(C.Structure):
+    _fields_ = [("c", C.c_double), ("gamma", C.c_double), ("max_depth", C.c_int32), ("n_envs", C.c_int32),
+                ("max_nodes", C.c_int32), ("n_dirs", C.c_int32), ("seed", C.c_uint64)]
+
+
+class NodeInfo(C.Structure):
+    _fields_ = [("parent", C.c_int32), ("action", C.c_int32), ("depth", C.c_int32), ("pool_slot", C.c_int32),
+                ("n_children", C.c_int32), ("terminal", C.c_int32), ("reward", C.c_float), ("Q", C.c_double),
+                ("N", C.c_int64)]
+
+
+class PlanResult(C.Structure):
+    _fields_ = [("action", C.c_int32), ("push", C.c_float * 4), ("value", C.c_double), ("visits", C.c_int64),
+                ("iterations", C.c_int32), ("nodes", C.c_int32), ("simulations", C.c_int64),
+                ("env_substeps", C.c_int64), ("seconds", C.c_double)]
+
+
+def _tree_lib():
+    L = lib()
+    if not getattr(L, "_tree_ready", False):
+        vp = C.c_void_p
+        L.pmbs_tree_config_default.argtypes = [C.POINTER(TreeConfig)]
+        L.pmbs_tree_config_default.restype = None
+        L.pmbs_tree_create.argtypes = [C.POINTER(TreeConfig), C.c_int32, C.c_float, C.POINTER(vp)]
+        L.pmbs_tree_destroy.argtypes = [vp]
+        L.pmbs_tree_destroy.restype = None
+        L.pmbs_tree_select.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.pmbs_tree_update.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
+        L.pmbs_tree_best.argtypes = [vp, vp, vp, vp]
+        L.pmbs_tree_node.argtypes = [vp, C.c_int32, C.POINTER(NodeInfo)]
+        L.pmbs_tree_size.argtypes = [vp, vp, vp, vp]
+        L.pmbs_plan.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_float,
+                                C.POINTER(PlanResult)]
+        L._tree_ready = True
+    return L
+
+
+def tree_config(**over) -> TreeConfig:
+    c = TreeConfig()
+    _tree_lib().pmbs_tree_config_default(C.byref(c))
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Tree:
+    """Host UCT tree of the library (no GPU needed)."""
+
+    def __init__(self, n_objects: int, root_reward: float = 0.0, cfg: TreeConfig | None = None, **over):
+        L = _tree_lib()
+        self.cfg = cfg if cfg is not None else tree_config(**over)
+        h = C.c_void_p()
+        _check(L.pmbs_tree_create(C.byref(self.cfg), int(n_objects), float(root_reward), C.byref(h)))
+        self.handle = h
+        E, D = self.cfg.n_envs, self.cfg.max_depth
+        self._acts = np.zeros(E * D, np.int32)
+        self._off = np.zeros(E + 1, np.int32)
+        self._src = np.zeros(E, np.int32)
+        self._child = np.zeros(E, np.int32)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib().pmbs_tree_destroy(h)
+            self.handle = None
+
+    def select(self):
+        npairs, nenvs = C.c_int32(0), C.c_int32(0)
+        _check(_tree_lib().pmbs_tree_select(self.handle, C.byref(npairs), _np_ptr(self._acts), _np_ptr(self._off),
+                                            _np_ptr(self._src), _np_ptr(self._child), C.byref(nenvs)))
+        E = nenvs.value
+        return dict(n_pairs=npairs.value, n_envs=E, act_offset=self._off[:E + 1].copy(),
+                    actions=self._acts[:self._off[E]].copy() if E else np.zeros(0, np.int32),
+                    src_slot=self._src[:E].copy(), child_slot=self._child[:E].copy())
+
+    def update(self, rewards, counts, status):
+        rw = np.ascontiguousarray(rewards, np.float32)
+        ct = np.ascontiguousarray(counts, np.int32)
+        stt = np.ascontiguousarray(status, np.uint32)
+        made = C.c_int32(0)
+        _check(_tree_lib().pmbs_tree_update(self.handle, _np_ptr(rw), rw.shape[1], _np_ptr(ct), _np_ptr(stt),
+                                            C.byref(made)))
+        return made.value
+
+    def best(self):
+        a, v, n = C.c_int32(0), C.c_double(0), C.c_int64(0)
+        _check(_tree_lib().pmbs_tree_best(self.handle, C.byref(a), C.byref(v), C.byref(n)))
+        return a.value, v.value, n.value
+
+    def node(self, i: int) -> dict:
+        info = NodeInfo()
+        _check(_tree_lib().pmbs_tree_node(self.handle, int(i), C.byref(info)))
+        return {k: getattr(info, k) for k, _ in NodeInfo._fields_}
+
+    def size(self):
+        n, s, p = C.c_int32(0), C.c_int64(0), C.c_int32(0)
+        _check(_tree_lib().pmbs_tree_size(self.handle, C.byref(n), C.byref(s), C.byref(p)))
+        return n.value, s.value, p.value
+
+
+def plan(sim: "Sim", tree: Tree, state, body, target: int, iters: int, n_substeps: int = 120,
+         width: float = 0.08) -> dict:
+    """Runs pmbs_plan on a host scene (state [n,13], body [n,5])."""
+    st = soa(state, 13)
+    bd = soa(body, 5)
+    res = PlanResult()
+    _check(_tree_lib().pmbs_plan(sim.handle, tree.handle, _np_ptr(st), _np_ptr(bd), st.shape[1], int(target),
+                                 int(iters), int(n_substeps), float(width), C.byref(res)))
+    out = {k: getattr(res, k) for k, _ in PlanResult._fields_}
+    out["push"] = list(res.push)
+    return out

@@ -1,0 +1,72 @@
+"""pmbs_plan (host tree + device rollouts) against the tree oracle over the
+FP64 transition on small retrieval scenes: same tree shape and actions,
+child rewards and values within the rollout tolerance, same best action."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import tree_oracle as T
+from paper_2207_06649_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_06649_amd import pmbs
+    return pmbs
+
+
+def f32(a):
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def make_sim(pm, n_envs, n_bodies, max_nodes, depth):
+    return pm.Sim(max_envs=n_envs, max_bodies=n_envs * n_bodies, pool_slots=max_nodes, pool_stride=n_bodies,
+                  max_horizon=max(depth, 1))
+
+
+@pytest.mark.parametrize("seed,n_envs,depth,iters", [(3, 12, 2, 2), (5, 24, 3, 3)])
+def test_plan_matches_oracle_planner(pm, seed, n_envs, depth, iters):
+    b = scenes.retrieval_scene(seed, n_others=6, region=0.25)
+    n = len(b.body)
+    st, bd = f32(b.state), f32(b.body)
+    sim = make_sim(pm, n_envs, n, 4096, depth)
+    tree = pm.Tree(n, O.reward(st, bd, 0, 0.08), n_envs=n_envs, max_depth=depth, seed=seed, max_nodes=4096)
+    res = pm.plan(sim, tree, st, bd, 0, iters, n_substeps=60)
+    env = T.PhysicsEnv(O.make_config(), bd, target=0, substeps=60)
+    p = T.Planner(env, st, n_envs=n_envs, depth=depth, seed=seed)
+    a_ref, v_ref = p.plan(iters)
+    nodes = []
+    stack = [p.root]
+    while stack:
+        nd = stack.pop()
+        nodes.append(nd)
+        stack.extend(nd.children)
+    assert tree.size()[0] == len(nodes) == res["nodes"]
+    for nd in nodes:
+        info = tree.node(nd.id)
+        assert info["action"] == (-1 if nd.action is None else nd.action)
+        assert info["parent"] == (-1 if nd.parent is None else nd.parent.id)
+        assert info["N"] == nd.N
+        assert abs(info["reward"] - nd.reward) < 1e-4
+        assert abs(info["Q"] - nd.Q) < 1e-4 * max(1, nd.N)
+    assert res["action"] == a_ref
+    assert abs(res["value"] - v_ref) < 1e-4
+    assert res["iterations"] == iters and res["simulations"] == n_envs * iters
+    # the returned push is the contour push of the chosen action from the root state
+    want = O.contour_push(O.make_config(), st[a_ref // 8], bd[a_ref // 8], a_ref % 8, 8)
+    assert np.abs(np.array(res["push"]) - want).max() < 1e-5
+
+
+def test_serial_plan_runs(pm):
+    b = scenes.retrieval_scene(1, n_others=8, region=0.3)
+    n = len(b.body)
+    sim = make_sim(pm, 1, n, 256, 3)
+    tree = pm.Tree(n, 0.0, n_envs=1, max_depth=3, seed=2, max_nodes=256)
+    res = pm.plan(sim, tree, f32(b.state), f32(b.body), 0, 10, n_substeps=60)
+    assert res["iterations"] == 10 and res["simulations"] == 10
+    assert res["action"] >= 0 and res["nodes"] >= 2

@@ -1,0 +1,125 @@
+"""GPU parity of batched contour-push rollouts (batch expansion + batch
+simulation) against the FP64 oracle's rollout: rewards after every push,
+the expanded child's state in its pool slot, discarded pushes, early stop
+at reward 1, pool-slot sources and the persistent work queue."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2207_06649_amd import scenes
+
+pytestmark = pytest.mark.gpu
+CFG = O.make_config()
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_06649_amd import pmbs
+    return pmbs
+
+
+def f32(a):
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def rollout_case(seed, n_envs, n_bodies, horizons, substeps=40, region=0.3):
+    rng = np.random.default_rng(seed)
+    b = scenes.clutter_batch(seed, n_envs, n_bodies, region=region)
+    acts, off = [], [0]
+    for e in range(n_envs):
+        nb = int(b.counts()[e])
+        h = int(horizons[e % len(horizons)])
+        acts += [int(rng.integers(0, nb)) * 8 + int(rng.integers(0, 8)) for _ in range(h)]
+        off.append(len(acts))
+    tgt = np.array([int(rng.integers(0, int(n))) for n in b.counts()], np.int32)
+    return b, np.array(acts, np.int32), np.array(off, np.int32), tgt
+
+
+def oracle_rollouts(b, acts, off, tgt, substeps, width=0.08):
+    out = []
+    for e in range(b.n_envs):
+        lo, hi = b.env_offset[e], b.env_offset[e + 1]
+        od = [(a // 8, a % 8) for a in acts[off[e]:off[e + 1]]]
+        out.append(O.rollout(CFG, f32(b.state[lo:hi]), f32(b.body[lo:hi]), od, substeps, int(tgt[e]), width))
+    return out
+
+
+def check(b, rew, cnt, ref, tol=2e-5):
+    for e, r in enumerate(ref):
+        k = r["applied"]
+        assert cnt[e] == k, (e, cnt[e], k)
+        assert np.abs(rew[e, :k] - r["rewards"]).max(initial=0) <= tol, (e, rew[e, :k], r["rewards"])
+
+
+def test_rollout_rewards_and_final_state(pm):
+    b, acts, off, tgt = rollout_case(1, 48, (4, 12), [1, 2, 3], substeps=30)
+    sim = pm.Sim(max_envs=b.n_envs, max_bodies=b.n_bodies)
+    sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+    rew, cnt = sim.rollout(acts, off, tgt, n_substeps=30)
+    ref = oracle_rollouts(b, acts, off, tgt, 30)
+    check(b, rew, cnt, ref)
+    st = sim.get_state().astype(np.float64)
+    status = sim.env_status()
+    for e, r in enumerate(ref):
+        lo, hi = b.env_offset[e], b.env_offset[e + 1]
+        assert bool(status[e] & 4) == (r["valid"][0] == 0)
+        if r["valid"][0]:
+            # rollouts here run up to 3 pushes: invariant-level agreement
+            assert np.abs(st[lo:hi, :3] - r["state"][:, :3]).max() < 2e-3
+
+
+def test_rollout_single_push_exact_and_child_snapshot(pm):
+    """One push per env: reward and child state match the oracle within the
+    one-push tolerance; pool sources and child slots round-trip."""
+    b, acts, off, tgt = rollout_case(2, 32, 8, [1], substeps=20)
+    sim = pm.Sim(max_envs=b.n_envs, max_bodies=b.n_bodies, pool_slots=80, pool_stride=8)
+    sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+    src = np.arange(b.n_envs, dtype=np.int32) + 40
+    sim.pool_scatter(src)
+    # scramble the env states: the rollout must read the pool slots
+    sim.set_state(b.env_offset, f32(b.state + np.r_[0.3, 0.3, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0]), f32(b.body))
+    child = np.arange(b.n_envs, dtype=np.int32)
+    rew, cnt = sim.rollout(acts, off, tgt, n_substeps=20, src_slot=src, child_slot=child, flags=0)
+    ref = oracle_rollouts(b, acts, off, tgt, 20)
+    check(b, rew, cnt, ref)
+    sim.pool_gather(child)
+    st = sim.get_state().astype(np.float64)
+    for e, r in enumerate(ref):
+        lo, hi = b.env_offset[e], b.env_offset[e + 1]
+        if r["valid"][0]:
+            assert np.abs(st[lo:hi, :3] - r["child_state"][:, :3]).max() < 1e-4
+
+
+def test_rollout_work_queue_matches_plain_launch(pm):
+    """Uneven horizons 1-5: the persistent longest-first launch gives bitwise
+    the plain launch's rewards and states."""
+    b, acts, off, tgt = rollout_case(3, 96, (5, 20), [1, 5, 3, 2, 4], substeps=15)
+    outs = []
+    for flags in (pm.ROLLOUT_WRITE_STATE, pm.ROLLOUT_WRITE_STATE | pm.ROLLOUT_QUEUE):
+        sim = pm.Sim(max_envs=b.n_envs, max_bodies=b.n_bodies, max_contacts=256)
+        sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+        rew, cnt = sim.rollout(acts, off, tgt, n_substeps=15, flags=flags, max_h=5)
+        outs.append((rew, cnt, sim.get_state()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_rollout_early_stop_at_reward_one(pm):
+    """A target already far from everything scores 1 after the first push and
+    the env stops there."""
+    st = np.zeros((3, 13))
+    st[:, 3] = 1
+    st[0, :3] = (0, 0, 0.02)
+    st[1, :3] = (0.3, 0, 0.02)
+    st[2, :3] = (0.3, 0.2, 0.02)
+    bd = np.array([[0.02, 0.02, 0.02, 0.1, 0.5]] * 3)
+    b = scenes.Batch(np.array([0, 3], np.int32), st, bd, np.zeros((1, 4)), np.zeros(1, np.int32))
+    sim = pm.Sim(max_envs=1, max_bodies=3)
+    sim.set_state(b.env_offset, f32(st), f32(bd))
+    acts = np.array([1 * 8 + 0, 2 * 8 + 3, 1 * 8 + 4], np.int32)
+    rew, cnt = sim.rollout(acts, [0, 3], [0], n_substeps=20)
+    ref = O.rollout(CFG, f32(st), f32(bd), [(1, 0), (2, 3), (1, 4)], 20, 0)
+    assert cnt[0] == 1 == ref["applied"] and rew[0, 0] == 1.0

@@ -1,0 +1,121 @@
+"""The library's host tree (C++) against the tree oracle (Python) on toy
+MDPs with identical rewards: selections, node statistics and the final
+action agree exactly (both use float64 and the same Philox draws).  CPU."""
+import numpy as np
+import pytest
+
+from oracle import tree_oracle as T
+from paper_2207_06649_amd import pmbs
+
+
+class Toy:
+    def __init__(self, k, lock, base=None, invalid=()):
+        self.k, self.lock, self.base, self.invalid = k, tuple(lock), base, set(invalid)
+
+    def n_actions(self, state):
+        return self.k
+
+    def reward(self, hist):
+        if tuple(hist[:len(self.lock)]) == self.lock:
+            return 1.0
+        return float(np.float32(self.base(hist))) if self.base else 0.0
+
+    def root_reward(self, state):
+        return self.reward(state)
+
+    def run(self, state, actions):
+        if (tuple(state), actions[0]) in self.invalid or actions[0] in self.invalid:
+            return False, None, []
+        hist, rewards = list(state), []
+        for a in actions:
+            hist.append(a)
+            rewards.append(self.reward(hist))
+            if rewards[-1] >= 1.0:
+                break
+        return True, tuple(list(state) + [actions[0]]), rewards
+
+
+def run_library_tree(env, n_objects, n_dirs, iters, **cfg):
+    tree = pmbs.Tree(n_objects, env.root_reward(()), n_dirs=n_dirs, **cfg)
+    hist = {0: ()}
+    trace = []
+    for _ in range(iters):
+        sel = tree.select()
+        if sel["n_pairs"] == 0:
+            break
+        E, D = sel["n_envs"], cfg["max_depth"]
+        rewards = np.zeros((E, D), np.float32)
+        counts = np.zeros(E, np.int32)
+        status = np.zeros(E, np.uint32)
+        off, acts = sel["act_offset"], sel["actions"]
+        trace.append([(int(sel["src_slot"][e]), tuple(acts[off[e]:off[e + 1]])) for e in range(E)])
+        for e in range(E):
+            h = hist[int(sel["src_slot"][e])]
+            valid, child, rw = env.run(h, list(acts[off[e]:off[e + 1]]))
+            if not valid:
+                status[e] = pmbs.PMBS_ENV_PUSH_INVALID
+                continue
+            counts[e] = len(rw)
+            rewards[e, :len(rw)] = rw
+            if sel["child_slot"][e] >= 0:
+                hist[int(sel["child_slot"][e])] = child
+        tree.update(rewards, counts, status)
+    return tree, hist, trace
+
+
+def run_oracle_tree(env, iters, **cfg):
+    p = T.Planner(env, (), n_envs=cfg["n_envs"], c=cfg["c"], gamma=cfg["gamma"], depth=cfg["max_depth"],
+                  seed=cfg["seed"])
+    for _ in range(iters):
+        if not p.iterate():
+            break
+    return p
+
+
+def oracle_nodes(p):
+    out, stack = [], [p.root]
+    while stack:
+        n = stack.pop()
+        out.append(n)
+        stack.extend(n.children)
+    return sorted(out, key=lambda n: n.id)
+
+
+@pytest.mark.parametrize("n_envs,depth,iters,seed", [(1, 4, 30, 7), (4, 3, 12, 1), (16, 4, 8, 3), (64, 5, 5, 9)])
+def test_library_tree_matches_oracle(n_envs, depth, iters, seed):
+    base = lambda h: 0.03 * ((sum(h) * 7 + len(h)) % 9)
+    env = Toy(k=6, lock=(5, 0, 3), base=base, invalid={2})
+    cfg = dict(n_envs=n_envs, max_depth=depth, c=1.4, gamma=0.8, seed=seed, max_nodes=100000)
+    tree, hist, _ = run_library_tree(env, 3, 2, iters, **cfg)     # 3 objects x 2 dirs = 6 actions
+    p = run_oracle_tree(env, iters, **cfg)
+    nodes = oracle_nodes(p)
+    n_lib = tree.size()[0]
+    assert n_lib == len(nodes)
+    for n in nodes:
+        info = tree.node(n.id)
+        assert info["action"] == (-1 if n.action is None else n.action)
+        assert info["parent"] == (-1 if n.parent is None else n.parent.id)
+        assert info["N"] == n.N
+        assert info["Q"] == n.Q                       # bitwise: same float64 operations
+        assert info["terminal"] == int(n.terminal)
+        assert hist[info["pool_slot"]] == n.state
+    a, v, visits = tree.best()
+    b = T.best_action(p.root)
+    assert a == b.action and v == b.Q / b.N and visits == b.N
+
+
+def test_library_selection_unique_pairs_and_fill():
+    tree = pmbs.Tree(2, 0.0, n_envs=8, max_depth=1, n_dirs=2, seed=0, max_nodes=100)
+    sel = tree.select()
+    assert sel["n_pairs"] == 4 and sel["n_envs"] == 8
+    firsts = [sel["actions"][sel["act_offset"][e]] for e in range(8)]
+    assert sorted(firsts[:4]) == [0, 1, 2, 3] and firsts[4:] == firsts[:4]
+    assert list(sel["child_slot"]) == [1, 2, 3, 4, -1, -1, -1, -1]
+    tree.update(np.zeros((8, 1), np.float32), np.ones(8, np.int32), np.zeros(8, np.uint32))
+    assert tree.select()["n_pairs"] == 0
+
+
+def test_library_tree_rejects_update_without_selection():
+    tree = pmbs.Tree(2, 0.0, n_envs=2, max_depth=2, n_dirs=2)
+    with pytest.raises(pmbs.PmbsError):
+        tree.update(np.zeros((2, 2), np.float32), np.ones(2, np.int32), np.zeros(2, np.uint32))
