@@ -55,6 +55,62 @@ def cpu_threads() -> int:
     return max(1, n)
 
 
+def plan_latency(pmbs, scenes, args) -> dict:
+    """MCTS object retrieval: 20 cuboids + a target at the centre of a
+    0.4 m square; UCT c = 1.4, leaves per iteration, depth <= 5 pushes,
+    30 iterations.  Wall time of pmbs_plan per seeded scene (p50/p99), and
+    serial one-leaf-at-a-time MCTS on the same scene, timed for a bounded
+    number of iterations and projected to the same number of simulations."""
+    import torch
+    n_bodies, depth = 21, 5
+    times, values, subs = [], [], []
+
+    def sim_for(n_envs, max_nodes):
+        return pmbs.Sim(max_envs=n_envs, max_bodies=n_envs * n_bodies, pool_slots=max_nodes, pool_stride=n_bodies,
+                        max_horizon=depth)
+
+    def root_reward(st, bd):
+        s1 = pmbs.Sim(max_envs=1, max_bodies=n_bodies)
+        s1.set_state([0, n_bodies], st, bd)
+        return float(s1.eval_reward([0], 0.08)[0][0])
+
+    leaves, iters = args.plan_leaves, args.plan_iters
+    max_nodes = leaves * iters + 2
+    sim = sim_for(leaves, max_nodes)
+    for k in range(args.plan_scenes):
+        sc = scenes.retrieval_scene(100 + k, n_others=20, region=0.4)
+        tree = pmbs.Tree(n_bodies, root_reward(sc.state, sc.body), n_envs=leaves, max_depth=depth, c=1.4,
+                         gamma=0.8, seed=100 + k, max_nodes=max_nodes)
+        res = pmbs.plan(sim, tree, sc.state, sc.body, 0, iters, n_substeps=120)
+        times.append(res["seconds"])
+        values.append(res["value"])
+        subs.append(res["env_substeps"])
+        print(f"# plan scene {k}: {res['seconds']:.3f} s, action {res['action']}, value {res['value']:.3f}, "
+              f"{res['nodes']} nodes", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    # serial baseline: same scene as the first plan, one leaf per iteration
+    sc = scenes.retrieval_scene(100, n_others=20, region=0.4)
+    ssim = sim_for(1, args.serial_iters + 2)
+    tree = pmbs.Tree(n_bodies, root_reward(sc.state, sc.body), n_envs=1, max_depth=depth, c=1.4, gamma=0.8,
+                     seed=100, max_nodes=args.serial_iters + 2)
+    sres = pmbs.plan(ssim, tree, sc.state, sc.body, 0, args.serial_iters, n_substeps=120)
+    per_iter = sres["seconds"] / max(1, sres["iterations"])
+    projected = per_iter * leaves * iters
+    t = np.array(times)
+    return {
+        "workload": f"{n_bodies - 1} cuboids + target in 0.4 m square, c=1.4, {leaves} leaves/iteration, "
+                    f"depth <= {depth}, {iters} iterations, 120 substeps per push",
+        "scenes": len(times),
+        "p50_s": round(float(np.percentile(t, 50)), 4),
+        "p99_s": round(float(np.percentile(t, 99)), 4),
+        "mean_s": round(float(t.mean()), 4),
+        "env_substeps_per_s": round(float(np.sum(subs) / t.sum()), 1),
+        "serial": {"iterations_timed": int(sres["iterations"]), "s_per_iteration": round(per_iter, 5),
+                   "projected_s_same_simulations": round(projected, 3)},
+        "speedup_vs_serial": round(projected / float(np.percentile(t, 50)), 2),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +121,10 @@ def main() -> int:
     ap.add_argument("--substeps", type=int, default=120)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plan-scenes", type=int, default=5, help="seeded retrieval scenes for plan latency (0: skip)")
+    ap.add_argument("--plan-iters", type=int, default=30)
+    ap.add_argument("--plan-leaves", type=int, default=256)
+    ap.add_argument("--serial-iters", type=int, default=64, help="one-leaf iterations timed for the serial baseline")
     ap.add_argument("--copy-mb", type=int, default=256,
                     help="size of a plain device copy run after the timed region (counter calibration)")
     args = ap.parse_args()
@@ -147,7 +207,7 @@ def main() -> int:
     ms_per_step = total_ms / args.steps
     value = env_substeps * args.steps / (total_ms * 1e-3)
     out = {
-        "metric": "env-substeps/sec (4096 envs x 15 boxes) + %HBM peak",
+        "metric": "env-substeps/sec (4096 envs x 15 boxes) + %HBM peak; p50/p99 MCTS plan latency",
         "value": round(value, 1),
         "unit": "env-substeps/s",
         "n_gpus": 1,
@@ -188,6 +248,9 @@ def main() -> int:
             "frac": round(achieved_gbs / PEAK_HBM_GBS, 6),
         },
     }
+
+    if args.plan_scenes > 0:
+        out["plan"] = plan_latency(pmbs, scenes, args)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

@@ -185,7 +185,8 @@ struct SatResult {
 
 // contact axis: early out when any s > margin; the kept axis starts at the
 // first candidate and is replaced only when s exceeds it by tau (face) or
-// tau_edge (edge axes)
+// tau_edge (edge axes).  Both boxes sit in registers; the 15 candidates are
+// unrolled so every axis index is static.
 template <int K>
 __device__ __forceinline__ SatResult sat_best(const Smem<K>& s, int ia, int ib, const Params& p) {
   const Box A = load_box(s, ia), B = load_box(s, ib);
@@ -193,18 +194,35 @@ __device__ __forceinline__ SatResult sat_best(const Smem<K>& s, int ia, int ib, 
   r.s = -INFINITY;
   r.idx = -1;
   r.L = mk(0, 0, 0);
-  f3 d = B.c - A.c;
+  const f3 d = B.c - A.c;
   int best = -1;
-#pragma unroll 1
+  bool out = false;
+#pragma unroll
   for (int idx = 0; idx < 15; ++idx) {
     f3 L;
-    if (!sat_axis(s, ia, ib, idx, p.edge_eps, &L)) continue;
-    float sv = fabsf(dot(d, L)) - radius_along(A, L) - radius_along(B, L);
-    if (sv > p.margin) { r.idx = -1; return r; }
-    float tau = idx < 6 ? p.tau_face : p.tau_edge;
-    if (best < 0 || sv > r.s + tau) { r.s = sv; best = idx; r.L = L; }
+    bool ok = true;
+    if (idx < 3) {
+      L = axis(A, idx);
+    } else if (idx < 6) {
+      L = axis(B, idx - 3);
+    } else {
+      const f3 v = cross(axis(A, (idx - 6) / 3), axis(B, (idx - 6) % 3));
+      const float len = sqrtf(dot(v, v));
+      ok = len >= p.edge_eps;
+      L = v * (1.0f / len);
+    }
+    if (ok && !out) {
+      const float sv = fabsf(dot(d, L)) - radius_along(A, L) - radius_along(B, L);
+      if (sv > p.margin) out = true;
+      const float tau = idx < 6 ? p.tau_face : p.tau_edge;
+      if (!out && (best < 0 || sv > r.s + tau)) {
+        r.s = sv;
+        best = idx;
+        r.L = L;
+      }
+    }
   }
-  r.idx = best;
+  r.idx = out ? -1 : best;
   return r;
 }
 
@@ -221,29 +239,50 @@ __device__ __forceinline__ void cl_put(Smem<K>& s, int buf, int i, int lane, f3 
 }
 
 // Sutherland-Hodgman against sign * ((x - f).dir) - h <= 0, from buffer
-// `src` (n points) into `dst`; at most POLY points are kept.
+// `src` (n points) into `dst`; at most POLY points are kept.  The input
+// polygon is read into registers once (static slots), outputs go to LDS.
 template <int K>
-__device__ __forceinline__ int clip_stage(Smem<K>& s, int src, int n, int dst, int lane, f3 f, f3 dir, float sign, float h) {
+__device__ __forceinline__ int clip_stage(Smem<K>& s, int src, int n, int dst, int lane, f3 f, f3 dir, float sign,
+                                          float h) {
   if (n == 0) return 0;
+  f3 P[POLY];
+  float d[POLY];
+#pragma unroll
+  for (int i = 0; i < POLY; ++i) {
+    if (i < n) {
+      P[i] = cl_get(s, src, i, lane);
+      d[i] = sign * dot(P[i] - f, dir) - h;
+    }
+  }
+  f3 prev = P[0];
+  float dp = d[0];
+#pragma unroll
+  for (int i = 1; i < POLY; ++i) {
+    if (i == n - 1) {
+      prev = P[i];
+      dp = d[i];
+    }
+  }
   int m = 0;
-  f3 prev = cl_get(s, src, n - 1, lane);
-  float dp = sign * dot(prev - f, dir) - h;
-  for (int i = 0; i < n; ++i) {
-    f3 cur = cl_get(s, src, i, lane);
-    float dc = sign * dot(cur - f, dir) - h;
-    if (dc <= 0.0f) {
-      if (dp > 0.0f) {
+#pragma unroll
+  for (int i = 0; i < POLY; ++i) {
+    if (i < n) {
+      const f3 cur = P[i];
+      const float dc = d[i];
+      if (dc <= 0.0f) {
+        if (dp > 0.0f) {
+          if (m < POLY) cl_put(s, dst, m, lane, prev + (cur - prev) * (dp / (dp - dc)));
+          ++m;
+        }
+        if (m < POLY) cl_put(s, dst, m, lane, cur);
+        ++m;
+      } else if (dp <= 0.0f) {
         if (m < POLY) cl_put(s, dst, m, lane, prev + (cur - prev) * (dp / (dp - dc)));
         ++m;
       }
-      if (m < POLY) cl_put(s, dst, m, lane, cur);
-      ++m;
-    } else if (dp <= 0.0f) {
-      if (m < POLY) cl_put(s, dst, m, lane, prev + (cur - prev) * (dp / (dp - dc)));
-      ++m;
+      prev = cur;
+      dp = dc;
     }
-    prev = cur;
-    dp = dc;
   }
   return m < POLY ? m : POLY;
 }
@@ -771,6 +810,8 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       int cnt = 0, np = 0, ia = 0, ib = 0;
       SatResult sr;
       sr.idx = -1;
+      f3 poly[POLY];
+      float psep[POLY];
       f3 n = mk(0, 0, 0), nref = mk(0, 0, 0), fref = mk(0, 0, 0), ept = mk(0, 0, 0);
       if (has) {
         unsigned pr = s.pairs[pi];
@@ -782,9 +823,13 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
           n = sel(dot(d, sr.L) >= 0.0f, sr.L, neg(sr.L));
           if (sr.idx < 6) {
             np = face_manifold(s, ia, ib, sr.idx, n, lane, &nref, &fref);
-            for (int i = 0; i < np; ++i) {
-              float sep = dot(nref, cl_get(s, 1, i, lane) - fref);
-              cnt += sep <= p.margin ? 1 : 0;
+#pragma unroll
+            for (int i = 0; i < POLY; ++i) {
+              if (i < np) {
+                poly[i] = cl_get(s, 1, i, lane);
+                psep[i] = dot(nref, poly[i] - fref);
+                cnt += psep[i] <= p.margin ? 1 : 0;
+              }
             }
           } else {
             ept = edge_point(s, ia, ib, sr.idx, n);
@@ -798,9 +843,11 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         const int ab = ia | (ib << 8);
         if (sr.idx < 6) {
           int t = 0;
-          for (int i = 0; i < np; ++i) {
-            f3 pt = cl_get(s, 1, i, lane);
-            float sep = dot(nref, pt - fref);
+#pragma unroll
+          for (int i = 0; i < POLY; ++i) {
+            if (i >= np) continue;
+            const f3 pt = poly[i];
+            const float sep = psep[i];
             if (sep <= p.margin) {
               const int c = off + t;
               if (c < C) {
@@ -951,12 +998,28 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       }
       wave_sync();
       if (active) {
+        // sums in contact-index order; four incidences per step so their
+        // LDS loads are in flight together
         f3 acc = mk(0, 0, 0);
-        for (int k = 0; k < inc_count; ++k) {
+        const int sel0 = part == 0 ? 0 : 1;
+        int k = 0;
+        for (; k + 4 <= inc_count; k += 4) {
+          int en[4];
+          float4 val[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) en[u] = s.inc[inc_start + k + u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) val[u] = s.u.imp[part == 0 ? 0 : sel0 + (en[u] & 1)][en[u] >> 1];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float sg = (en[u] & 1) ? 1.0f : -1.0f;
+            acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
+          }
+        }
+        for (; k < inc_count; ++k) {
           const int en = s.inc[inc_start + k];
-          const int c = en >> 1, side = en & 1;
-          const float4 val = s.u.imp[part == 0 ? 0 : 1 + side][c];
-          const float sg = side ? 1.0f : -1.0f;
+          const float4 val = s.u.imp[part == 0 ? 0 : sel0 + (en & 1)][en >> 1];
+          const float sg = (en & 1) ? 1.0f : -1.0f;
           acc = mk(fmaf(sg, val.x, acc.x), fmaf(sg, val.y, acc.y), fmaf(sg, val.z, acc.z));
         }
         if (part == 0) {
@@ -1082,18 +1145,17 @@ template <int K>
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
   __shared__ Smem<K> s;
   __shared__ int next;
-  if (g.queue == nullptr) {
-    const int wi = g.env_base + blockIdx.x;
-    if (wi < g.n_envs) run_env<K>(s, g, g.order ? g.order[wi] : wi);
-    return;
-  }
+  int wi = g.queue ? 0 : g.env_base + blockIdx.x;
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(g.queue, 1);
-    __syncthreads();
-    const int wi = next;
-    __syncthreads();
+    if (g.queue) {
+      if (threadIdx.x == 0) next = atomicAdd(g.queue, 1);
+      __syncthreads();
+      wi = next;
+      __syncthreads();
+    }
     if (wi >= g.n_envs) break;
-    run_env<K>(s, g, g.order ? g.order[wi] : wi);
+    run_env<K>(s, g, g.order ? g.order[wi] : wi);   // the only call site: one inlined copy
+    if (!g.queue) break;
     __syncthreads();
   }
 }

@@ -52,10 +52,12 @@ def test_plan_matches_oracle_planner(pm, seed, n_envs, depth, iters):
         assert info["action"] == (-1 if nd.action is None else nd.action)
         assert info["parent"] == (-1 if nd.parent is None else nd.parent.id)
         assert info["N"] == nd.N
-        assert abs(info["reward"] - nd.reward) < 1e-4
-        assert abs(info["Q"] - nd.Q) < 1e-4 * max(1, nd.N)
+        # a reward is clearance / 0.08 m after a pushed (multi-substep) transition:
+        # 1e-3 is 80 um of clearance, inside the 1e-3 m multi-substep state bar
+        assert abs(info["reward"] - nd.reward) < 1e-3
+        assert abs(info["Q"] - nd.Q) < 1e-3 * max(1, nd.N)
     assert res["action"] == a_ref
-    assert abs(res["value"] - v_ref) < 1e-4
+    assert abs(res["value"] - v_ref) < 1e-3
     assert res["iterations"] == iters and res["simulations"] == n_envs * iters
     # the returned push is the contour push of the chosen action from the root state
     want = O.contour_push(O.make_config(), st[a_ref // 8], bd[a_ref // 8], a_ref % 8, 8)
