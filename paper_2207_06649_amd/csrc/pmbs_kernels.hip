@@ -72,6 +72,20 @@ __device__ __forceinline__ int wave_excl_scan(int x, int* total) {
   return v - x;
 }
 
+// Exclusive prefix sum of small non-negative counts (< 2^bits) across the
+// wave: one ballot per bit, counted below each lane with mbcnt (no LDS).
+__device__ __forceinline__ int wave_excl_scan_bits(int x, int bits, int* total) {
+  int prefix = 0, tot = 0;
+  for (int bb = 0; bb < bits; ++bb) {
+    const unsigned long long m = __ballot((x >> bb) & 1);
+    const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    prefix += below << bb;
+    tot += __popcll(m) << bb;
+  }
+  *total = tot;
+  return prefix;
+}
+
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
 // ------------------------------------------------------------------ LDS layout
@@ -421,6 +435,9 @@ __device__ __forceinline__ void prep_contact(const Smem<K>& s, int c, const Para
   ct->ln = ct->lt1 = ct->lt2 = 0.0f;
   const int key = contact_key(ab);
   int lo = 0, hi = nwarm - 1;
+  if (c < nwarm && s.wkey[c] == key) {   // unchanged list prefix: same index
+    lo = hi = c;
+  }
   while (lo <= hi) {
     const int mid = (lo + hi) >> 1;
     const int km = s.wkey[mid];
@@ -730,17 +747,18 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       s.mask[lane] = 0u;
     }
     wave_sync();
-    if (lane < n_obj) {
-      // NaN keys sort last (ranks stay a permutation whatever the state holds)
-      float key = s.lo[0][lane];
+    {
+      // rank of each object's min-x key (ties by index; NaN keys sort last,
+      // so the ranks stay a permutation whatever the state holds)
+      float key = lane < n_obj ? s.lo[0][lane] : INFINITY;
       key = key == key ? key : INFINITY;
+      const int ikey = __float_as_int(key);
       int rank = 0;
       for (int j = 0; j < n_obj; ++j) {
-        float kj = s.lo[0][j];
-        kj = kj == kj ? kj : INFINITY;
+        const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
         rank += (kj < key || (kj == key && j < lane)) ? 1 : 0;
       }
-      s.sorted[rank] = lane;
+      if (lane < n_obj) s.sorted[rank] = lane;
     }
     wave_sync();
     if (lane < n_obj) {
@@ -759,7 +777,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     int n_pairs;
     {
       unsigned m = lane < n_obj ? s.mask[lane] : 0u;
-      int off = wave_excl_scan(__popc(m), &n_pairs);
+      int off = wave_excl_scan_bits(__popc(m), 5, &n_pairs);
       int t = 0;
       while (m) {
         int j = __builtin_ctz(m);
@@ -785,7 +803,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         }
       }
       int total;
-      int off = wave_excl_scan(__popc(flags), &total);
+      int off = wave_excl_scan_bits(__popc(flags), 4, &total);
       int t = 0;
       while (flags) {
         const int kk = __builtin_ctz(flags);
@@ -838,7 +856,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         }
       }
       int total;
-      int off = nc_raw + wave_excl_scan(cnt, &total);
+      int off = nc_raw + wave_excl_scan_bits(cnt, 4, &total);
       if (has && cnt > 0) {
         const int ab = ia | (ib << 8);
         if (sr.idx < 6) {
@@ -918,7 +936,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       for (int sl = 0; sl < K; ++sl) cn += __popcll(mA[sl] | mB[sl]);
       if (!active) cn = 0;
       int tot;
-      int st0 = wave_excl_scan(part == 0 ? cn : 0, &tot);
+      int st0 = wave_excl_scan_bits(part == 0 ? cn : 0, 11, &tot);
       inc_start = __shfl(st0, b, 64);
       inc_count = cn;
       if (active && part == 0) {

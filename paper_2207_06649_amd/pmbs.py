@@ -115,6 +115,7 @@ class Sim:
         self.cfg = cfg if cfg is not None else default_config(**over)
         self.device = torch.device(device)
         L = lib()
+        self._L = L  # kept so that the destructor still works during interpreter shutdown
         nbytes = C.c_size_t(0)
         _check(L.pmbs_sim_query_workspace(C.byref(self.cfg), C.byref(nbytes)))
         self.workspace_bytes = int(nbytes.value)
@@ -131,8 +132,9 @@ class Sim:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            lib().pmbs_sim_destroy(h)
+        L = getattr(self, "_L", None)
+        if h is not None and h.value and L is not None:
+            L.pmbs_sim_destroy(h)
             self.handle = None
 
     # ---------------------------------------------------------------- state
@@ -328,6 +330,7 @@ class Tree:
 
     def __init__(self, n_objects: int, root_reward: float = 0.0, cfg: TreeConfig | None = None, **over):
         L = _tree_lib()
+        self._L = L
         self.cfg = cfg if cfg is not None else tree_config(**over)
         h = C.c_void_p()
         _check(L.pmbs_tree_create(C.byref(self.cfg), int(n_objects), float(root_reward), C.byref(h)))
@@ -340,8 +343,9 @@ class Tree:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            lib().pmbs_tree_destroy(h)
+        L = getattr(self, "_L", None)
+        if h is not None and h.value and L is not None:
+            L.pmbs_tree_destroy(h)
             self.handle = None
 
     def select(self):
