@@ -47,6 +47,44 @@ def hbm_bytes_per_call(n_bodies: int, n_envs: int) -> float:
     return 136.0 * n_bodies + 28.0 * n_envs
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_4096x15_traffic.md")
+KERNEL_SOURCES = ("paper_2207_06649_amd/csrc/pmbs_kernels.hip", "paper_2207_06649_amd/csrc/pmbs_kernels.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n_envs: int, n_bodies: int, substeps: int):
+    """HBM bytes per step-kernel launch from the recorded FETCH_SIZE and
+    WRITE_SIZE counter runs (each scaled by the same counter's reading for a
+    plain device copy of known size; the record is written by
+    bench_traffic.py), or None when the counters were taken on other kernel
+    sources or another workload."""
+    rec = {}
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.startswith("- ") and ":" in line:
+                    k, v = line[2:].split(":", 1)
+                    rec[k.strip()] = v.strip()
+    except OSError:
+        return None
+    try:
+        if rec.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        if (int(rec["envs"]), int(rec["bodies_per_env"]), int(rec["substeps"])) != (n_envs, n_bodies, substeps):
+            return None
+        return float(rec["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_threads() -> int:
     n = len(os.sched_getaffinity(0))
     omp = os.environ.get("OMP_NUM_THREADS")
@@ -234,7 +272,7 @@ def main() -> int:
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 5),
-            "traffic": None,
+            "traffic": measured_traffic(E, args.bodies, args.substeps),
             "kernel_ms": round(k_avg_ms, 4),
             "flop_per_env_substep": round(f_unit, 1),
             "contacts_per_env_substep": round(nc, 3),
