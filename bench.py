@@ -149,6 +149,182 @@ def plan_latency(pmbs, scenes, args) -> dict:
     }
 
 
+def plain_per_push(sim, acts, off, tgt, n_substeps, width=0.08, rewards=None, counts=None):
+    """The plain form of uneven rollouts: one launch per push index over a
+    fixed-shape batch (the caller pads every env to the same body count),
+    one workgroup per env, the state kept in the env slots, and a
+    synchronous read-back after every launch to apply the rollout rules on
+    the host (a discarded expansion push ends the env, a later discarded
+    push repeats the previous reward, a reward of 1 ends the env).
+    Returns (rewards [E, H], counts [E], status [E])."""
+    from paper_2207_06649_amd import pmbs
+    off = np.asarray(off)
+    h = np.diff(off)
+    E, H = len(h), int(h.max()) if len(h) else 0
+    rew = np.zeros((E, max(H, 1)), np.float32)
+    cnt = np.zeros(E, np.int32)
+    status = np.zeros(E, np.uint32)
+    last = np.zeros(E, np.float32)
+    ended = np.zeros(E, bool)
+    for t in range(H):
+        go = (~ended) & (t < h)
+        a1 = acts[off[:-1] + t][go] if go.any() else np.zeros(0, np.int32)
+        o1 = np.zeros(E + 1, np.int32)
+        o1[1:] = np.cumsum(go)
+        r1, c1 = sim.rollout(a1, o1, tgt, n_substeps=n_substeps, width=width, max_h=1,
+                             flags=pmbs.ROLLOUT_WRITE_STATE, rewards=rewards, counts=counts)
+        st = sim.env_status()
+        took = go & (c1 > 0)
+        dropped = go & (c1 == 0)
+        rew[took, t] = r1[took, 0]
+        last[took] = r1[took, 0]
+        cnt[took] = t + 1
+        if t == 0:
+            ended |= dropped
+            status[dropped] |= pmbs.PMBS_ENV_PUSH_INVALID
+        else:
+            rew[dropped, t] = last[dropped]
+            cnt[dropped] = t + 1
+        status[go] |= st[go] & ~np.uint32(pmbs.PMBS_ENV_PUSH_INVALID)
+        ended |= took & (r1[:, 0] >= 1.0)
+    return rew, cnt, status
+
+
+def uneven_batching(pmbs, scenes, args) -> dict:
+    """Uneven batch: envs of 5-30 cuboids, 1-5 contour pushes each, 120
+    substeps per push.  Packed form: one graph-captured launch of persistent
+    work-queue kernels per contact class, envs loaded from pool slots,
+    launch plan chosen by the autotuner.  Plain form: every env padded to 30
+    bodies, one launch per push index with a host round trip between
+    launches.  Both report useful env-substeps (real bodies, pushes actually
+    simulated) per second of wall time."""
+    import torch
+    E, sub, H = args.uneven_envs, args.substeps, 5
+    t0 = time.time()
+    b = scenes.clutter_batch(3, E, (5, 30))
+    hz = scenes.horizons(3, E)
+    acts, off = scenes.contour_actions(3, b.counts(), hz)
+    tgt = np.zeros(E, np.int32)
+    print(f"# uneven workload ready: {E} envs, {b.n_bodies} bodies, {int(off[-1])} pushes "
+          f"({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    sim = pmbs.Sim(max_envs=E, max_bodies=b.n_bodies, max_contacts=256, pool_slots=2 * E, pool_stride=31,
+                   max_horizon=H)
+    sim.set_state(b.env_offset, b.state, b.body)
+    src = np.arange(E, dtype=np.int32)
+    child = src + E
+    sim.pool_scatter(src)
+    rew = torch.empty((E, H), dtype=torch.float32, device=dev)
+    cnt = torch.empty(E, dtype=torch.int32, device=dev)
+    t1 = time.perf_counter()
+    plan, tune_ms, _ = sim.autotune(acts, off, tgt, n_substeps=sub, src_slot=src, child_slot=child, max_h=H,
+                                    reps=1, rewards=rew, counts=cnt)
+    tune_s = time.perf_counter() - t1
+    print(f"# autotuned plan {plan} ({tune_ms:.1f} ms per launch, {tune_s:.1f} s of tuning)",
+          file=sys.stderr, flush=True)
+    flags = pmbs.ROLLOUT_QUEUE | pmbs.ROLLOUT_GRAPH
+    sim.rollout(acts, off, tgt, n_substeps=sub, src_slot=src, child_slot=child, max_h=H, flags=flags,
+                rewards=rew, counts=cnt, sync=True)   # capture
+    useful = int(sim.stats()[:, 2].sum())
+    reps = args.uneven_reps
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    for _ in range(reps):
+        sim.rollout(acts, off, tgt, n_substeps=sub, src_slot=src, child_slot=child, max_h=H, flags=flags,
+                    rewards=rew, counts=cnt, sync=True)
+    packed_s = (time.perf_counter() - tw) / reps
+    packed_rew, packed_cnt = rew.cpu().numpy(), cnt.cpu().numpy()
+    del sim
+    # plain form
+    pb = scenes.pad_batch(b, 30)
+    psim = pmbs.Sim(max_envs=E, max_bodies=pb.n_bodies, max_contacts=256, max_horizon=H)
+    prew = torch.empty((E, 1), dtype=torch.float32, device=dev)
+    pcnt = torch.empty(E, dtype=torch.int32, device=dev)
+    plain = []
+    for _ in range(max(1, reps // 2)):
+        psim.set_state(pb.env_offset, pb.state, pb.body)
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        r_p, c_p, _ = plain_per_push(psim, acts, off, tgt, sub, rewards=prew, counts=pcnt)
+        plain.append(time.perf_counter() - tw)
+    plain_s = float(np.median(plain))
+    same_counts = float(np.mean(c_p == packed_cnt))
+    return {
+        "workload": f"{E} envs x U{{5..30}} cuboids, U{{1..5}} contour pushes, {sub} substeps each",
+        "useful_env_substeps": useful,
+        "packed": {"env_substeps_per_s": round(useful / packed_s, 1), "s_per_batch": round(packed_s, 4),
+                   "plan": plan, "autotune_s": round(tune_s, 2), "graph": True},
+        "plain_padded_per_push": {"env_substeps_per_s": round(useful / plain_s, 1), "s_per_batch": round(plain_s, 4),
+                                  "padded_to": 30},
+        "speedup": round(plain_s / packed_s, 2),
+        "envs_with_equal_reward_counts": round(same_counts, 4),
+    }
+
+
+def serving(pmbs, scenes, args) -> dict:
+    """Planning requests arriving as a Poisson stream: scenes of 5-30 cuboids
+    (a target at the centre), leaf batches of 64, 256 or 1024, 10-30
+    iterations, depth <= 5, 120 substeps per push.  Continuous batching
+    (every request in flight advances one iteration per packed,
+    graph-replayed launch; admission by free env slots, request slots and
+    node-pool bytes) against the plain form: one request at a time in
+    arrival order, each with its own batched launches.  Capacity comes from
+    a saturated run (all requests at t = 0); latency from a Poisson run at
+    0.7x the plain form's capacity (or the nominal 50/s if that is lower)."""
+    rng = np.random.default_rng([4, 2024])
+    n = args.serve_requests
+    reqs = []
+    for k in range(n):
+        nb = int(rng.integers(5, 31))
+        sc = scenes.retrieval_scene(500 + k, n_others=nb - 1, region=0.4)
+        reqs.append(dict(state=sc.state, body=sc.body, target=0, leaves=int(rng.choice([64, 256, 1024])),
+                         iterations=int(rng.integers(10, 31)), seed=1000 + k))
+    gaps = rng.exponential(1.0, size=n)
+
+    def run(continuous: bool, rate: float | None) -> dict:
+        srv = pmbs.Server(max_envs=4096, max_requests=16 if continuous else 1, pool_slots=262144,
+                          n_substeps=args.substeps, graph=1 if continuous else 0)
+        t0 = time.perf_counter()
+        arrivals = np.cumsum(gaps / rate) - gaps[0] / rate if rate else np.zeros(n)
+        ids = []
+        for k, q in enumerate(reqs):
+            delay = t0 + arrivals[k] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit(**q))
+        res = [srv.wait(i) for i in ids]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.array([r["latency_seconds"] for r in res])
+        useful = sum(r["env_substeps"] for r in res)
+        return {"requests": n, "wall_s": round(wall, 3), "env_substeps_per_s": round(useful / wall, 1),
+                "requests_per_s": round(n / wall, 3), "p50_s": round(float(np.percentile(lat, 50)), 4),
+                "p99_s": round(float(np.percentile(lat, 99)), 4), "launches": st["launches"],
+                "peak_in_flight": st["peak_in_flight"], "peak_held_mb": round(st["peak_held_bytes"] / 2**20, 1),
+                "failed": int(sum(r["status"] != 0 for r in res)),
+                "results": [(r["action"], round(r["value"], 6)) for r in res]}
+
+    plain_sat = run(False, None)
+    print(f"# serving plain saturated: {plain_sat['requests_per_s']} req/s", file=sys.stderr, flush=True)
+    cont_sat = run(True, None)
+    print(f"# serving continuous saturated: {cont_sat['requests_per_s']} req/s", file=sys.stderr, flush=True)
+    rate = min(50.0, 0.7 * plain_sat["requests_per_s"])
+    plain = run(False, rate)
+    cont = run(True, rate)
+    same = all(a == b for a, b in zip(plain.pop("results"), cont.pop("results")))
+    for d in (plain_sat, cont_sat):
+        d.pop("results")
+    return {
+        "workload": f"{n} requests: 5-30 cuboids (target at the centre, 0.4 m square), leaves U{{64,256,1024}}, "
+                    f"10-30 iterations, depth <= 5, {args.substeps} substeps per push",
+        "offered_rate_per_s": round(rate, 3),
+        "continuous": cont, "plain_per_request": plain,
+        "capacity": {"continuous": cont_sat, "plain_per_request": plain_sat},
+        "same_results_alone_and_mixed": same,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +339,9 @@ def main() -> int:
     ap.add_argument("--plan-iters", type=int, default=30)
     ap.add_argument("--plan-leaves", type=int, default=256)
     ap.add_argument("--serial-iters", type=int, default=64, help="one-leaf iterations timed for the serial baseline")
+    ap.add_argument("--uneven-envs", type=int, default=4096, help="envs of the uneven batch (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=24, help="requests of the serving runs (0: skip)")
+    ap.add_argument("--uneven-reps", type=int, default=4)
     ap.add_argument("--copy-mb", type=int, default=256,
                     help="size of a plain device copy run after the timed region (counter calibration)")
     args = ap.parse_args()
@@ -289,6 +468,10 @@ def main() -> int:
 
     if args.plan_scenes > 0:
         out["plan"] = plan_latency(pmbs, scenes, args)
+    if args.uneven_envs > 0:
+        out["uneven"] = uneven_batching(pmbs, scenes, args)
+    if args.serve_requests > 0:
+        out["serving"] = serving(pmbs, scenes, args)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

@@ -134,7 +134,11 @@ pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_de
 
 /* rollout flags */
 #define PMBS_ROLLOUT_WRITE_STATE 1 /* write each env's final state back to its slot */
-#define PMBS_ROLLOUT_QUEUE 2       /* persistent launch pulling envs longest-horizon first */
+#define PMBS_ROLLOUT_QUEUE 2       /* persistent launches pulling envs from device work queues
+                                      (order and contact classes per the launch plan) */
+#define PMBS_ROLLOUT_GRAPH 4       /* with PMBS_ROLLOUT_QUEUE: replay the launches as one captured
+                                      hipGraph (captured on first use and again whenever the
+                                      launch arguments or the plan change) */
 
 /* Batch expansion + batch simulation (Sec. IV-C) in one launch: env e runs
  * the contour pushes actions[act_offset[e] .. act_offset[e+1]) (packed as
@@ -154,6 +158,45 @@ pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int3
                              const int32_t* src_slot, const int32_t* child_slot, const int32_t* target,
                              int32_t inputs_on_device, int32_t n_substeps, float width, float* d_rewards,
                              int32_t max_h, int32_t* d_reward_count, int32_t flags);
+
+/* Launch plan of queued rollouts (packing of uneven envs and horizons).
+ * Every env is a work item; items are sorted by estimated work, largest
+ * first, and pulled from a device counter by persistent workgroups (one
+ * wave per env).  Envs with at most small_max_bodies bodies run in the
+ * 128-contact kernel and the rest in the 256-contact kernel; an env whose
+ * contacts overflow its kernel stops before writing anything and is re-run
+ * by the next larger kernel that max_contacts allows, so results do not
+ * depend on the plan beyond FP32 contraction differences between the
+ * kernels.  With max_contacts 128 every env runs in the 128-contact kernel
+ * and an overflow only sets PMBS_ENV_CONTACT_OVERFLOW. */
+typedef struct pmbs_launch_plan {
+  int32_t small_max_bodies;    /* -1: no env in the 128-contact kernel */
+  int32_t small_blocks_per_cu; /* persistent workgroups per CU, 0: as many as fit */
+  int32_t large_blocks_per_cu;
+  int32_t order;               /* 0: horizon first; 1: horizon x (bodies + 4) first */
+} pmbs_launch_plan;
+
+/* Defaults: small_max_bodies 16, blocks per CU 0, order 1. */
+pmbs_status pmbs_sim_set_launch_plan(pmbs_sim_t* sim, const pmbs_launch_plan* plan);
+pmbs_status pmbs_sim_get_launch_plan(const pmbs_sim_t* sim, pmbs_launch_plan* plan);
+
+/* Autotuner of the launch plan for one rollout workload (same arguments as
+ * pmbs_sim_rollout; PMBS_ROLLOUT_WRITE_STATE is refused because every
+ * candidate re-runs the rollout from the same inputs).  Candidates are timed
+ * with HIP events on the simulator's stream, reps runs each, by coordinate
+ * descent over small_max_bodies, blocks per CU and order; the fastest plan
+ * (median time) is installed and returned with its time in milliseconds.
+ * cache_path (optional) names a text file of earlier results keyed by the
+ * device, the library build, the configuration and a histogram of the
+ * workload's body counts and horizons: a hit installs the cached plan
+ * without timing (*cached = 1), a miss appends the new result.  The
+ * rollout's outputs afterwards are those of one pmbs_sim_rollout call.
+ * Synchronises. */
+pmbs_status pmbs_sim_autotune(pmbs_sim_t* sim, const int32_t* actions, const int32_t* act_offset,
+                              const int32_t* src_slot, const int32_t* child_slot, const int32_t* target,
+                              int32_t n_substeps, float width, float* d_rewards, int32_t max_h,
+                              int32_t* d_reward_count, int32_t flags, int32_t reps, const char* cache_path,
+                              pmbs_launch_plan* best, float* best_ms, int32_t* cached);
 
 /* Status word per environment, cleared by every step.  A host destination
  * synchronises. */
@@ -215,6 +258,7 @@ typedef struct pmbs_tree_config {
 } pmbs_tree_config;
 
 typedef struct pmbs_tree pmbs_tree_t;
+typedef struct pmbs_server pmbs_server_t;
 
 typedef struct pmbs_node_info {
     int32_t parent, action, depth, pool_slot, n_children, terminal;
@@ -281,6 +325,86 @@ typedef struct pmbs_plan_result {
 pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_state, const float* body,
                       int32_t n_bodies, int32_t target, int32_t iters, int32_t n_substeps, float width,
                       pmbs_plan_result* out);
+
+/* ------------------------------------------------------------------ */
+/* serving: planning requests with continuous batching                 */
+/* Requests (a scene, a target, a leaf batch size and an iteration
+ * count) arrive at any time.  A worker thread owned by the server admits
+ * them in arrival order while env slots, request slots and node-pool
+ * memory allow (admission by device-memory footprint), keeps each admitted
+ * request's tree-node states resident in the pool, and runs one iteration
+ * of every request in flight per batched launch (Sec. IV-C iterations of
+ * several trees packed into one rollout launch).  Requests that arrive
+ * while others run join at the next iteration boundary; a finished
+ * request frees its slots at once.  A request's result does not depend on
+ * which other requests shared its launches. */
+typedef struct pmbs_server_config {
+  pmbs_sim_config sim;    /* physics and contact class (max_contacts, solver_iters, ...); its sizes are
+                             derived from the fields below */
+  int32_t max_envs;       /* env slots per launch: the leaf batches of all requests in flight */
+  int32_t max_requests;   /* requests in flight at once */
+  int32_t pool_slots;     /* tree-node state slots shared by the requests in flight */
+  int32_t max_depth;      /* D, pushes per simulation counting tree and rollout */
+  int32_t n_substeps;     /* substeps per push */
+  float width;            /* gripper width of the reward */
+  double c, gamma;        /* Eq. 2 exploration constant, discount */
+  int64_t hbm_budget;     /* bytes of node-pool footprint the requests in flight may hold; 0: the pool */
+  int32_t graph;          /* replay the batched launch as a captured graph */
+} pmbs_server_config;
+
+typedef struct pmbs_request {
+  const float* state;     /* host SoA [13][n_bodies], copied at submission */
+  const float* body;      /* host SoA [5][n_bodies] (half extents, mass, mu) */
+  int32_t n_bodies;       /* 1..PMBS_MAX_BODIES_PER_ENV */
+  int32_t target;
+  int32_t leaves;         /* N_e of this request */
+  int32_t iterations;
+  uint64_t seed;
+} pmbs_request;
+
+typedef struct pmbs_request_result {
+  pmbs_plan_result plan;    /* plan.seconds: admission to completion */
+  double queued_seconds;    /* submission to admission */
+  double latency_seconds;   /* submission to completion */
+  int64_t footprint_bytes;  /* node-pool bytes the request held */
+  int32_t status;           /* PMBS_OK, PMBS_ERR_CANCELLED, or the error that ended it */
+} pmbs_request_result;
+
+typedef struct pmbs_server_stats {
+  int64_t submitted, completed, launches, env_substeps;
+  double busy_seconds;      /* wall time with at least one request in flight */
+  int32_t in_flight, waiting, peak_in_flight;
+  int64_t held_bytes, peak_held_bytes;
+} pmbs_server_stats;
+
+#define PMBS_ERR_CANCELLED (-6)
+
+/* Defaults: 4096 envs, 16 requests, 262144 pool slots, D = 5, 120
+ * substeps, width 0.08, c = 1.4, gamma = 0.8, budget 0, graph on, and the
+ * simulator defaults with max_contacts 256. */
+void pmbs_server_config_default(pmbs_server_config* cfg);
+/* Device bytes of the server's workspace (node pool of pool_slots x 31
+ * bodies x 52 B plus the simulator's buffers). */
+pmbs_status pmbs_server_query_workspace(const pmbs_server_config* cfg, size_t* bytes);
+/* Starts the worker thread on the calling thread's current device; the
+ * workspace (device, 256-byte aligned) and stream are the caller's until
+ * pmbs_server_destroy returns. */
+pmbs_status pmbs_server_create(const pmbs_server_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+                               pmbs_server_t** out);
+/* Queues a request; never blocks on the device.  PMBS_ERR_CAPACITY if it
+ * could never be admitted (too many leaves, bodies or nodes). */
+pmbs_status pmbs_server_submit(pmbs_server_t* srv, const pmbs_request* req, uint64_t* request_id);
+/* *done = 1 and *out filled once the request has finished (the id is then
+ * forgotten); *done = 0 otherwise. */
+pmbs_status pmbs_server_poll(pmbs_server_t* srv, uint64_t request_id, pmbs_request_result* out, int32_t* done);
+/* Blocks until the request has finished, then as pmbs_server_poll. */
+pmbs_status pmbs_server_wait(pmbs_server_t* srv, uint64_t request_id, pmbs_request_result* out);
+/* A waiting request finishes at once, one in flight at its next iteration
+ * boundary, with status PMBS_ERR_CANCELLED and the best action so far. */
+pmbs_status pmbs_server_cancel(pmbs_server_t* srv, uint64_t request_id);
+pmbs_status pmbs_server_get_stats(pmbs_server_t* srv, pmbs_server_stats* out);
+/* Cancels what is left, stops the worker and frees the handle. */
+void pmbs_server_destroy(pmbs_server_t* srv);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmbs.so")
 
-SOURCES = ["pmbs_kernels.hip", "pmbs_sim.cpp", "pmbs_tree.cpp", "pmbs_plan.cpp"]
+SOURCES = ["pmbs_kernels.hip", "pmbs_sim.cpp", "pmbs_tree.cpp", "pmbs_plan.cpp", "pmbs_tune.cpp", "pmbs_server.cpp"]
 
 # No packed FP32 (v_pk_*_f32) code generation anywhere in the device code.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -21,14 +21,30 @@ def sources() -> list[str]:
     return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
 
+def build_id() -> str:
+    """Hash of the sources and headers (keys the autotuner's cache)."""
+    import hashlib
+    h = hashlib.sha256()
+    names = sorted(os.listdir(CSRC))
+    for n in names:
+        if n.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(CSRC, n), "rb") as f:
+                h.update(n.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "include", "pmbs.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     """Compiles every source (always, also when a library exists)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    bid = build_id()
     objs = []
     for src in sources():
         obj = os.path.join(CSRC, os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *lang, "-c", src, "-o", obj]
+        cmd = [hipcc, *HIP_FLAGS, f'-DPMBS_BUILD_ID="{bid}"', "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+               *lang, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

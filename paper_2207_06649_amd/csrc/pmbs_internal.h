@@ -23,12 +23,29 @@ struct pmbs_sim {
   int32_t* d_slots;     // [max_envs] pool slots of the current gather/scatter
   long long* d_stats;   // [max_envs][2]
   float* d_pool;        // [pool_slots][13][pool_stride]
-  int32_t *d_actions, *d_act_offset, *d_src_slot, *d_child_slot, *d_order, *d_queue;
+  int32_t *d_actions, *d_act_offset, *d_src_slot, *d_child_slot, *d_order;
   float* d_roll_rewards;   // [max_envs][max_horizon] rollout rewards of the planner
   int32_t* d_roll_counts;
-  int grid_cache = 0;
+  // queued rollouts: d_order holds the small-class list at [0, max_envs) and
+  // the large-class list at [max_envs, 2 max_envs); d_ctl holds the queue
+  // counters [0..3] (small, large, fallback 256, fallback 512), the
+  // overflow counts [4..5] and the list lengths [8..9]; d_ovf4 / d_ovf8 are
+  // the overflow lists feeding the 256- and 512-contact fallbacks
+  int32_t *d_ctl, *d_ovf4, *d_ovf8;
+  int32_t *d_bc_base;      // [max_envs] optional body-constant rows per env
+  int cus = 0, occ[3] = {0, 0, 0};   // CUs; resident blocks per CU of the 128/256/512 kernels
+  pmbs_launch_plan plan;
+  // internal streams and events for the concurrent class launches and graph capture
+  hipStream_t side = nullptr, cap = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  pmbs::StepArgs graph_args;
+  pmbs_launch_plan graph_plan;
   int32_t n_envs, n_bodies;
   std::vector<int32_t> host_offset;
+  bool pool_layout = false;   // envs live only in pool slots, body constants at d_bc_base rows
+  ~pmbs_sim();
 };
 
 namespace pmbs {
@@ -63,5 +80,23 @@ pmbs_status fail(pmbs_status s, const char* fmt, ...);
 pmbs_status hip_fail(hipError_t e, const char* what);
 Params params_of(const pmbs_sim_config& c);
 StepArgs step_args(pmbs_sim_t* sim);
-int persistent_grid(pmbs_sim_t* sim);
+pmbs_status body_constants(const float* body, int n, int i, float* out, size_t stride);
+// body constants of a host SoA [5][n] scene into rows row0.. (synchronous)
+pmbs_status upload_bodies(pmbs_sim_t* sim, int row0, int n, const float* body);
+// a host SoA [13][n] state into one pool slot (synchronous)
+pmbs_status upload_pool_slot(pmbs_sim_t* sim, int slot, int n, const float* state);
+// pool-only env layout: env e has env_offset[e+1] - env_offset[e] bodies
+// whose constants start at row bc_base[e]; rollouts must then load every
+// env from a pool slot and may not write state back
+pmbs_status set_layout(pmbs_sim_t* sim, int n_envs, const int32_t* env_offset, const int32_t* bc_base);
+// retrieval reward of env e's state in pool slot slots[e] (pool layout; synchronous, host out)
+pmbs_status rewards_from_pool(pmbs_sim_t* sim, const int32_t* slots, const int32_t* target, float width, float* out);
+// the contour push of an action from a host SoA state (double precision)
+void contour_push_host(const pmbs_sim_config& cfg, const float* st, const float* bd, int n, int obj, int dir,
+                       int n_dirs, float out[4]);
+// workgroups of a persistent launch of the given contact class
+int class_grid(pmbs_sim_t* sim, int max_contacts, int blocks_per_cu);
+// the queued rollout launches (all contact classes and fallbacks) on `stream`
+hipError_t enqueue_queued(pmbs_sim_t* sim, const StepArgs& a, hipStream_t stream, bool skip_empty, int n_small,
+                          int n_large);
 }  // namespace pmbs

@@ -38,9 +38,19 @@ struct StepArgs {
   int* reward_count;        // [n_envs]
   int pool_stride, max_h, write_state;
   float width;
+  // body constants of env e start at row bc_base[e] of bconst with row
+  // stride bc_stride (null: row env_offset[e], stride `stride`)
+  const int* bc_base;
+  int bc_stride;
   // work distribution
   const int* order;         // work item -> env (null: identity)
   int* queue;               // device counter (null: one block per work item)
+  const int* work_count;    // device count of work items (null: n_envs)
+  // an env whose contacts overflow this instantiation's capacity stops
+  // before writing anything and appends itself here, for a re-run in a
+  // larger class (null: it finishes with the overflow status bit)
+  int* overflow_list;
+  int* overflow_count;
   Params p;
 };
 
@@ -53,6 +63,13 @@ struct RewardArgs {
   float* clearance;
   int n_envs, stride;
   float width;
+  // optional: env e's state from pool slot slots[e] ([13][pool_stride]) and
+  // its body constants from rows bc_base[e] (row stride bc_stride)
+  const float* pool;
+  const int* slots;
+  int pool_stride;
+  const int* bc_base;
+  int bc_stride;
 };
 
 struct PoolArgs {
@@ -65,7 +82,12 @@ struct PoolArgs {
 
 hipError_t launch_pool(const PoolArgs& a, hipStream_t stream);
 int step_blocks_per_cu(int max_contacts);
-hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream, int grid = 0);
+// one workgroup per env (no queue)
+hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream);
+// persistent queue launch of one contact class without resetting the queue
+// counter (the caller clears it, e.g. with launch_zero)
+hipError_t launch_step_class(const StepArgs& a, int max_contacts, hipStream_t stream, int grid);
+hipError_t launch_zero(int* p, int n, hipStream_t stream);
 hipError_t launch_reward(const RewardArgs& a, hipStream_t stream);
 
 }  // namespace pmbs

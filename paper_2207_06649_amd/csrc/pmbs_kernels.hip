@@ -564,17 +564,19 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     const int SN = src >= 0 ? PS : N;
     const int si = src >= 0 ? b : i;
     const float* bc = g.bconst;
+    const int BN = g.bc_base ? g.bc_stride : N;
+    const int bi = g.bc_base ? g.bc_base[e] + b : i;
     if (part == 0) {
       x = mk(st[0 * SN + si], st[1 * SN + si], st[2 * SN + si]);
       v = mk(st[7 * SN + si], st[8 * SN + si], st[9 * SN + si]);
-      invm = bc[3 * N + i];
+      invm = bc[3 * BN + bi];
     } else {
       q0 = st[3 * SN + si]; q1 = st[4 * SN + si]; q2 = st[5 * SN + si]; q3 = st[6 * SN + si];
       w = mk(st[10 * SN + si], st[11 * SN + si], st[12 * SN + si]);
-      invI = mk(bc[4 * N + i], bc[5 * N + i], bc[6 * N + i]);
+      invI = mk(bc[4 * BN + bi], bc[5 * BN + bi], bc[6 * BN + bi]);
     }
-    h = mk(bc[0 * N + i], bc[1 * N + i], bc[2 * N + i]);
-    mu = bc[7 * N + i];
+    h = mk(bc[0 * BN + bi], bc[1 * BN + bi], bc[2 * BN + bi]);
+    mu = bc[7 * BN + bi];
   }
   if (lane == 0) {
     s.pos[PLANE] = make_float4(0, 0, 0, 0);
@@ -617,6 +619,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   };
 
   Contact ct[K];
+  bool deferred = false;
   uint32_t status = 0u;
   float last_r = 0.0f;
   int n_rewards = 0;
@@ -884,7 +887,14 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       }
       nc_raw += total;
     }
-    if (nc_raw > C) status |= PMBS_ENV_CONTACT_OVERFLOW;
+    if (nc_raw > C) {
+      status |= PMBS_ENV_CONTACT_OVERFLOW;
+      if (g.overflow_list) {
+        // nothing of this env has been written yet: hand it to a larger class
+        deferred = true;
+        break;
+      }
+    }
     const int nc = nc_raw < C ? nc_raw : C;
     stat_nc += nc;
     stat_pairs += n_pairs;
@@ -1080,6 +1090,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     xp = xp + vp * dt;
     wave_sync();
   }
+  if (deferred) break;
 
   if (rollout) {
     // ---- reward after the push: clearance of the target's footprint
@@ -1114,6 +1125,10 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   }
   }  // pushes
 
+  if (deferred) {
+    if (lane == 0) g.overflow_list[atomicAdd(g.overflow_count, 1)] = e;
+    return;
+  }
   if (rollout && lane == 0 && g.reward_count) g.reward_count[e] = n_rewards;
   if (rollout && !g.write_state) {
     if (lane == 0) {
@@ -1163,6 +1178,7 @@ template <int K>
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
   __shared__ Smem<K> s;
   __shared__ int next;
+  const int n_work = g.work_count ? *g.work_count : g.n_envs;
   int wi = g.queue ? 0 : g.env_base + blockIdx.x;
   for (;;) {
     if (g.queue) {
@@ -1171,7 +1187,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
       wi = next;
       __syncthreads();
     }
-    if (wi >= g.n_envs) break;
+    if (wi >= n_work) break;
     run_env<K>(s, g, g.order ? g.order[wi] : wi);   // the only call site: one inlined copy
     if (!g.queue) break;
     __syncthreads();
@@ -1205,11 +1221,11 @@ __global__ __launch_bounds__(64) void pool_kernel(PoolArgs g) {
 }
 
 // ------------------------------------------------------------------ reward
-__device__ __forceinline__ Foot load_foot(const float* st, const float* bc, int N, int i) {
+__device__ __forceinline__ Foot load_foot(const float* st, int SN, int si, const float* bc, int BN, int bi) {
   f3 c0, c1, c2;
-  quat_cols(st[3 * N + i], st[4 * N + i], st[5 * N + i], st[6 * N + i], &c0, &c1, &c2);
-  return foot_of(mk(st[0 * N + i], st[1 * N + i], st[2 * N + i]), c0, c1, c2,
-                 mk(bc[0 * N + i], bc[1 * N + i], bc[2 * N + i]));
+  quat_cols(st[3 * SN + si], st[4 * SN + si], st[5 * SN + si], st[6 * SN + si], &c0, &c1, &c2);
+  return foot_of(mk(st[0 * SN + si], st[1 * SN + si], st[2 * SN + si]), c0, c1, c2,
+                 mk(bc[0 * BN + bi], bc[1 * BN + bi], bc[2 * BN + bi]));
 }
 
 __global__ __launch_bounds__(64) void reward_kernel(RewardArgs g) {
@@ -1219,12 +1235,18 @@ __global__ __launch_bounds__(64) void reward_kernel(RewardArgs g) {
   const int base = g.env_offset[e];
   const int nb = g.env_offset[e + 1] - base;
   const int t = g.target[e];
+  const bool from_pool = g.pool != nullptr;
+  const float* st = from_pool ? g.pool + (size_t)g.slots[e] * 13 * g.pool_stride : g.state;
+  const int SN = from_pool ? g.pool_stride : g.stride;
+  const int s0 = from_pool ? 0 : base;
+  const int BN = g.bc_base ? g.bc_stride : g.stride;
+  const int b0 = g.bc_base ? g.bc_base[e] : base;
   float d = INFINITY;
   if (t >= 0 && t < nb) {
-    const Foot T = load_foot(g.state, g.bconst, g.stride, base + t);
+    const Foot T = load_foot(st, SN, s0 + t, g.bconst, BN, b0 + t);
     for (int j = lane; j < nb; j += 64) {
       if (j == t) continue;
-      const Foot J = load_foot(g.state, g.bconst, g.stride, base + j);
+      const Foot J = load_foot(st, SN, s0 + j, g.bconst, BN, b0 + j);
       d = fminf(d, foot_distance(T, J));
     }
   } else {
@@ -1238,22 +1260,9 @@ __global__ __launch_bounds__(64) void reward_kernel(RewardArgs g) {
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream, int grid) {
+hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream) {
   const int n = a.n_envs - a.env_base;
   if (n <= 0) return hipSuccess;
-  if (a.queue) {
-    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, stream, a.queue, 1);
-  }
-  if (grid > 0 && a.queue && grid < n) {
-    if (max_contacts <= 128) {
-      hipLaunchKernelGGL(step_kernel<2>, dim3(grid), dim3(64), 0, stream, a);
-    } else if (max_contacts <= 256) {
-      hipLaunchKernelGGL(step_kernel<4>, dim3(grid), dim3(64), 0, stream, a);
-    } else {
-      hipLaunchKernelGGL(step_kernel<8>, dim3(grid), dim3(64), 0, stream, a);
-    }
-    return hipGetLastError();
-  }
   if (max_contacts <= 128) {
     hipLaunchKernelGGL(step_kernel<2>, dim3(n), dim3(64), 0, stream, a);
   } else if (max_contacts <= 256) {
@@ -1261,6 +1270,24 @@ hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream, 
   } else {
     hipLaunchKernelGGL(step_kernel<8>, dim3(n), dim3(64), 0, stream, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_step_class(const StepArgs& a, int max_contacts, hipStream_t stream, int grid) {
+  if (grid <= 0 || !a.queue) return hipErrorInvalidValue;
+  if (max_contacts <= 128) {
+    hipLaunchKernelGGL(step_kernel<2>, dim3(grid), dim3(64), 0, stream, a);
+  } else if (max_contacts <= 256) {
+    hipLaunchKernelGGL(step_kernel<4>, dim3(grid), dim3(64), 0, stream, a);
+  } else {
+    hipLaunchKernelGGL(step_kernel<8>, dim3(grid), dim3(64), 0, stream, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(int* p, int n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, p, n);
   return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@
 
 using namespace pmbs;
 
-namespace {
+namespace pmbs {
 
 // The contour push of an action from the root state, in double precision
 // (Sec. IV-B sampling: direction dir of n_dirs around object obj in its yaw
@@ -39,7 +39,7 @@ void contour_push_host(const pmbs_sim_config& cfg, const float* st, const float*
   out[3] = (float)(cy + off * dy - cfg.push_length * dy);
 }
 
-}  // namespace
+}  // namespace pmbs
 
 extern "C" {
 

@@ -1,0 +1,565 @@
+// pmbs_server.cpp -- planning requests served with continuous batching.
+//
+// A worker thread owns the simulator.  Each pass of its loop admits waiting
+// requests in arrival order while env slots, request slots and node-pool
+// memory allow, then runs one MCTS iteration (Sec. IV-C: selection with
+// virtual loss, batch expansion and simulation, backpropagation) of every
+// request in flight: their leaf batches are packed into one rollout launch
+// (uneven scenes and horizons in the persistent work queues), the rewards
+// come back once, and each tree is updated from its own slice.  Node
+// states stay in the device pool for the request's lifetime; scene
+// constants sit in per-request rows of the simulator's body table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "pmbs.h"
+#include "pmbs_internal.h"
+
+using namespace pmbs;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr int kStride = PMBS_MAX_BODIES_PER_ENV;  // pool rows per slot and body-table rows per request slot
+
+struct Request {
+  uint64_t id = 0;
+  std::vector<float> state, body;  // host SoA copies
+  int32_t nb = 0, target = 0, leaves = 0, iterations = 0;
+  uint64_t seed = 0;
+  enum Phase { kWaiting, kActive, kDone } phase = kWaiting;
+  bool cancel = false;
+  int32_t req_slot = -1, slot_base = -1, max_nodes = 0;
+  int64_t footprint = 0;
+  pmbs_tree_t* tree = nullptr;
+  int32_t iter = 0;
+  int64_t env_substeps = 0;
+  Clock::time_point t_submit, t_admit, t_done;
+  pmbs_request_result result{};
+  int32_t env_begin = 0, n_envs = 0;  // this pass's envs in the packed launch
+  ~Request() {
+    if (tree) pmbs_tree_destroy(tree);
+  }
+};
+
+// first-fit allocator of contiguous pool-slot ranges
+struct RangeAlloc {
+  std::map<int32_t, int32_t> free_;  // start -> length
+  explicit RangeAlloc(int32_t n = 0) {
+    if (n > 0) free_[0] = n;
+  }
+  int32_t take(int32_t n) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      const int32_t at = it->first, len = it->second;
+      free_.erase(it);
+      if (len > n) free_[at + n] = len - n;
+      return at;
+    }
+    return -1;
+  }
+  void give(int32_t at, int32_t n) {
+    auto it = free_.emplace(at, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+pmbs_sim_config sim_config_of(const pmbs_server_config& c) {
+  pmbs_sim_config s = c.sim;
+  s.max_envs = c.max_envs;
+  s.max_bodies = c.max_requests * kStride;
+  s.pool_slots = c.pool_slots;
+  s.pool_stride = kStride;
+  s.max_horizon = c.max_depth;
+  return s;
+}
+
+pmbs_status check_server_config(const pmbs_server_config* c) {
+  if (!c) return fail(PMBS_ERR_INVALID_ARG, "config is null");
+  if (c->max_envs < 1 || c->max_requests < 1 || c->pool_slots < 2 || c->max_depth < 1 || c->max_depth > 32 ||
+      c->n_substeps < 0 || !(c->width > 0) || !(c->c >= 0) || !(c->gamma >= 0) || c->hbm_budget < 0)
+    return fail(PMBS_ERR_INVALID_ARG, "bad server config");
+  if ((int64_t)c->max_requests * kStride > (1 << 28)) return fail(PMBS_ERR_INVALID_ARG, "max_requests too large");
+  return PMBS_OK;
+}
+
+double secs(Clock::duration d) { return std::chrono::duration<double>(d).count(); }
+
+}  // namespace
+
+struct pmbs_server {
+  pmbs_server_config cfg;
+  pmbs_sim_t* sim = nullptr;
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<uint64_t> waiting;
+  std::map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::vector<Request*> active;  // worker-owned
+  std::vector<char> slot_used;
+  RangeAlloc pool;
+  int64_t held = 0, peak_held = 0;
+  int32_t env_used = 0, peak_in_flight = 0;
+  int64_t submitted = 0, completed = 0, launches = 0, env_substeps = 0;
+  double busy = 0.0;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::thread worker;
+  // packed launch buffers (worker only)
+  std::vector<int32_t> actions, act_off, src, child, target, env_off, bc_base, counts, t_actions, t_off, t_src,
+      t_child;
+  std::vector<float> rewards;
+  std::vector<uint32_t> status;
+  std::vector<int64_t> stats;
+
+  int64_t footprint_of(int32_t max_nodes) const { return (int64_t)max_nodes * 13 * kStride * (int64_t)sizeof(float); }
+  int64_t budget() const {
+    const int64_t pool_bytes = footprint_of(cfg.pool_slots);
+    return cfg.hbm_budget > 0 ? std::min(cfg.hbm_budget, pool_bytes) : pool_bytes;
+  }
+  void run();
+  bool admit_locked(Request* r);
+  void release_locked(Request* r);
+  void finish(Request* r, pmbs_status st);
+  pmbs_status start_requests(const std::vector<Request*>& fresh);
+  pmbs_status pass();
+};
+
+bool pmbs_server::admit_locked(Request* r) {
+  if ((int)active.size() >= cfg.max_requests) return false;
+  if (env_used + r->leaves > cfg.max_envs) return false;
+  if (held + r->footprint > budget()) return false;
+  const int32_t at = pool.take(r->max_nodes);
+  if (at < 0) return false;
+  int k = 0;
+  while (slot_used[k]) ++k;  // a free request slot exists: active.size() < max_requests
+  slot_used[k] = 1;
+  r->req_slot = k;
+  r->slot_base = at;
+  held += r->footprint;
+  peak_held = std::max(peak_held, held);
+  env_used += r->leaves;
+  r->phase = Request::kActive;
+  r->t_admit = Clock::now();
+  active.push_back(r);
+  peak_in_flight = std::max(peak_in_flight, (int32_t)active.size());
+  return true;
+}
+
+void pmbs_server::release_locked(Request* r) {
+  pool.give(r->slot_base, r->max_nodes);
+  slot_used[r->req_slot] = 0;
+  held -= r->footprint;
+  env_used -= r->leaves;
+  active.erase(std::find(active.begin(), active.end(), r));
+}
+
+// best action so far (or none) into the result; the caller holds no lock
+void pmbs_server::finish(Request* r, pmbs_status st) {
+  pmbs_request_result& res = r->result;
+  res.status = st;
+  pmbs_plan_result& pr = res.plan;
+  pr.action = -1;
+  std::memset(pr.push, 0, sizeof pr.push);
+  pr.value = 0.0;
+  pr.visits = 0;
+  if (r->tree) {
+    int32_t a = -1;
+    double v = 0.0;
+    int64_t n = 0;
+    if (pmbs_tree_best(r->tree, &a, &v, &n) == PMBS_OK && a >= 0) {
+      pr.action = a;
+      pr.value = v;
+      pr.visits = n;
+      contour_push_host(sim->cfg, r->state.data(), r->body.data(), r->nb, a / 8, a % 8, 8, pr.push);
+    }
+    int32_t nodes = 0;
+    int64_t sims = 0;
+    pmbs_tree_size(r->tree, &nodes, &sims, nullptr);
+    pr.nodes = nodes;
+    pr.simulations = sims;
+  }
+  pr.iterations = r->iter;
+  pr.env_substeps = r->env_substeps;
+  r->t_done = Clock::now();
+  const bool admitted = r->slot_base >= 0;
+  pr.seconds = admitted ? secs(r->t_done - r->t_admit) : 0.0;
+  res.queued_seconds = secs((admitted ? r->t_admit : r->t_done) - r->t_submit);
+  res.latency_seconds = secs(r->t_done - r->t_submit);
+  res.footprint_bytes = r->footprint;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (r->phase == Request::kActive) release_locked(r);
+    r->phase = Request::kDone;
+    ++completed;
+    if (r->tree) {
+      pmbs_tree_destroy(r->tree);
+      r->tree = nullptr;
+    }
+  }
+  cv_done.notify_all();
+}
+
+// root states into the pool, scene constants into the request's body rows,
+// root rewards on the device, then the trees
+pmbs_status pmbs_server::start_requests(const std::vector<Request*>& fresh) {
+  std::vector<int32_t> off(1, 0), base, slots, tg;
+  for (Request* r : fresh) {
+    pmbs_status s = upload_bodies(sim, r->req_slot * kStride, r->nb, r->body.data());
+    if (s == PMBS_OK) s = upload_pool_slot(sim, r->slot_base, r->nb, r->state.data());
+    if (s != PMBS_OK) return s;
+    off.push_back(off.back() + r->nb);
+    base.push_back(r->req_slot * kStride);
+    slots.push_back(r->slot_base);
+    tg.push_back(r->target);
+  }
+  pmbs_status s = set_layout(sim, (int)fresh.size(), off.data(), base.data());
+  if (s != PMBS_OK) return s;
+  std::vector<float> root_r(fresh.size());
+  if ((s = rewards_from_pool(sim, slots.data(), tg.data(), cfg.width, root_r.data())) != PMBS_OK) return s;
+  for (size_t i = 0; i < fresh.size(); ++i) {
+    Request* r = fresh[i];
+    pmbs_tree_config tc;
+    pmbs_tree_config_default(&tc);
+    tc.c = cfg.c;
+    tc.gamma = cfg.gamma;
+    tc.max_depth = cfg.max_depth;
+    tc.n_envs = r->leaves;
+    tc.max_nodes = r->max_nodes;
+    tc.n_dirs = 8;
+    tc.seed = r->seed;
+    if ((s = pmbs_tree_create(&tc, r->nb, root_r[i], &r->tree)) != PMBS_OK) return s;
+  }
+  return PMBS_OK;
+}
+
+// one iteration of every request in flight, in one packed launch
+pmbs_status pmbs_server::pass() {
+  const int D = cfg.max_depth;
+  env_off.assign(1, 0);
+  bc_base.clear();
+  src.clear();
+  child.clear();
+  target.clear();
+  actions.clear();
+  act_off.assign(1, 0);
+  std::vector<Request*> done_now, in_launch;
+  for (Request* r : active) {
+    bool cancel;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      cancel = r->cancel;
+    }
+    if (cancel || r->iter >= r->iterations) {
+      done_now.push_back(r);
+      continue;
+    }
+    t_actions.resize((size_t)r->leaves * D);
+    t_off.resize(r->leaves + 1);
+    t_src.resize(r->leaves);
+    t_child.resize(r->leaves);
+    int32_t n_pairs = 0, n_envs = 0;
+    pmbs_status s = pmbs_tree_select(r->tree, &n_pairs, t_actions.data(), t_off.data(), t_src.data(), t_child.data(),
+                                     &n_envs);
+    if (s != PMBS_OK) return s;
+    if (n_pairs == 0) {
+      done_now.push_back(r);
+      continue;
+    }
+    r->env_begin = (int32_t)src.size();
+    r->n_envs = n_envs;
+    for (int e = 0; e < n_envs; ++e) {
+      env_off.push_back(env_off.back() + r->nb);
+      bc_base.push_back(r->req_slot * kStride);
+      src.push_back(r->slot_base + t_src[e]);
+      child.push_back(t_child[e] >= 0 ? r->slot_base + t_child[e] : -1);
+      target.push_back(r->target);
+      for (int k = t_off[e]; k < t_off[e + 1]; ++k) actions.push_back(t_actions[k]);
+      act_off.push_back((int32_t)actions.size());
+    }
+    in_launch.push_back(r);
+  }
+  for (Request* r : done_now) finish(r, r->cancel ? PMBS_ERR_CANCELLED : PMBS_OK);
+  const int E = (int)src.size();
+  if (E == 0) return PMBS_OK;
+  pmbs_status s = set_layout(sim, E, env_off.data(), bc_base.data());
+  if (s != PMBS_OK) return s;
+  int32_t flags = PMBS_ROLLOUT_QUEUE | (cfg.graph ? PMBS_ROLLOUT_GRAPH : 0);
+  s = pmbs_sim_rollout(sim, actions.data(), act_off.data(), src.data(), child.data(), target.data(), 0,
+                       cfg.n_substeps, cfg.width, sim->d_roll_rewards, D, sim->d_roll_counts, flags);
+  if (s != PMBS_OK) return s;
+  rewards.resize((size_t)E * D);
+  counts.resize(E);
+  status.resize(E);
+  stats.resize((size_t)E * 3);
+  hipError_t e = hipMemcpyAsync(rewards.data(), sim->d_roll_rewards, rewards.size() * sizeof(float),
+                                hipMemcpyDeviceToHost, sim->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(counts.data(), sim->d_roll_counts, (size_t)E * sizeof(int32_t), hipMemcpyDeviceToHost,
+                       sim->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(status.data(), sim->d_status, (size_t)E * sizeof(uint32_t), hipMemcpyDeviceToHost, sim->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(stats.data(), sim->d_stats, (size_t)E * 3 * sizeof(int64_t), hipMemcpyDeviceToHost, sim->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "server read-back");
+  int64_t total = 0;
+  for (Request* r : in_launch) {
+    const int b0 = r->env_begin;
+    s = pmbs_tree_update(r->tree, rewards.data() + (size_t)b0 * D, D, counts.data() + b0, status.data() + b0, nullptr);
+    if (s != PMBS_OK) return s;
+    int64_t sub = 0;
+    for (int k = b0; k < b0 + r->n_envs; ++k) sub += stats[(size_t)3 * k + 2];
+    r->env_substeps += sub;
+    total += sub;
+    r->iter += 1;
+  }
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    ++launches;
+    env_substeps += total;
+  }
+  // finished requests free their slots before the next admission
+  for (Request* r : in_launch)
+    if (r->iter >= r->iterations) finish(r, PMBS_OK);
+  return PMBS_OK;
+}
+
+void pmbs_server::run() {
+  (void)hipSetDevice(device);
+  for (;;) {
+    std::vector<Request*> fresh;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stop || !waiting.empty() || !active.empty(); });
+      if (stop) break;
+      while (!waiting.empty()) {
+        Request* r = reqs[waiting.front()].get();
+        if (!admit_locked(r)) break;
+        waiting.pop_front();
+        fresh.push_back(r);
+      }
+    }
+    const auto t0 = Clock::now();
+    pmbs_status s = fresh.empty() ? PMBS_OK : start_requests(fresh);
+    if (s != PMBS_OK) {
+      for (Request* r : fresh) finish(r, s);
+      continue;
+    }
+    s = pass();
+    if (s != PMBS_OK) {
+      // a failed launch ends every request in flight with its error
+      std::vector<Request*> all;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        all = active;
+      }
+      for (Request* r : all) finish(r, s);
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    busy += secs(Clock::now() - t0);
+  }
+}
+
+extern "C" {
+
+void pmbs_server_config_default(pmbs_server_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof *c);
+  pmbs_sim_config_default(&c->sim);
+  c->sim.max_contacts = 256;
+  c->max_envs = 4096;
+  c->max_requests = 16;
+  c->pool_slots = 262144;
+  c->max_depth = 5;
+  c->n_substeps = 120;
+  c->width = 0.08f;
+  c->c = 1.4;
+  c->gamma = 0.8;
+  c->hbm_budget = 0;
+  c->graph = 1;
+}
+
+pmbs_status pmbs_server_query_workspace(const pmbs_server_config* cfg, size_t* bytes) {
+  pmbs_status s = check_server_config(cfg);
+  if (s != PMBS_OK) return s;
+  const pmbs_sim_config sc = sim_config_of(*cfg);
+  return pmbs_sim_query_workspace(&sc, bytes);
+}
+
+pmbs_status pmbs_server_create(const pmbs_server_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+                               pmbs_server_t** out) {
+  pmbs_status s = check_server_config(cfg);
+  if (s != PMBS_OK) return s;
+  if (!out) return fail(PMBS_ERR_INVALID_ARG, "out is null");
+  const pmbs_sim_config sc = sim_config_of(*cfg);
+  pmbs_server* srv = new (std::nothrow) pmbs_server();
+  if (!srv) return fail(PMBS_ERR_INVALID_ARG, "out of host memory");
+  srv->cfg = *cfg;
+  if ((s = pmbs_sim_create(&sc, d_workspace, bytes, hip_stream, &srv->sim)) != PMBS_OK) {
+    delete srv;
+    return s;
+  }
+  hipError_t e = hipGetDevice(&srv->device);
+  if (e != hipSuccess) {
+    pmbs_sim_destroy(srv->sim);
+    delete srv;
+    return hip_fail(e, "hipGetDevice");
+  }
+  srv->slot_used.assign(cfg->max_requests, 0);
+  srv->pool = RangeAlloc(cfg->pool_slots);
+  try {
+    srv->worker = std::thread([srv] { srv->run(); });
+  } catch (...) {
+    pmbs_sim_destroy(srv->sim);
+    delete srv;
+    return fail(PMBS_ERR_INVALID_ARG, "cannot start the worker thread");
+  }
+  *out = srv;
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_server_submit(pmbs_server_t* srv, const pmbs_request* q, uint64_t* id) {
+  if (!srv || !q || !q->state || !q->body || !id) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (q->n_bodies < 1 || q->n_bodies > PMBS_MAX_BODIES_PER_ENV || q->target < 0 || q->target >= q->n_bodies)
+    return fail(PMBS_ERR_INVALID_ARG, "bad scene size or target");
+  if (q->leaves < 1 || q->iterations < 1) return fail(PMBS_ERR_INVALID_ARG, "leaves and iterations must be >= 1");
+  auto r = std::make_unique<Request>();
+  r->nb = q->n_bodies;
+  r->target = q->target;
+  r->leaves = q->leaves;
+  r->iterations = q->iterations;
+  r->seed = q->seed;
+  const int64_t nodes = (int64_t)q->leaves * q->iterations + 1;
+  if (q->leaves > srv->cfg.max_envs || nodes > srv->cfg.pool_slots)
+    return fail(PMBS_ERR_CAPACITY, "request needs %d env slots and %lld pool slots (server: %d, %d)", q->leaves,
+                (long long)nodes, srv->cfg.max_envs, srv->cfg.pool_slots);
+  r->max_nodes = (int32_t)nodes;
+  r->footprint = srv->footprint_of(r->max_nodes);
+  if (r->footprint > srv->budget())
+    return fail(PMBS_ERR_CAPACITY, "request footprint %lld B exceeds the budget %lld B", (long long)r->footprint,
+                (long long)srv->budget());
+  r->state.assign(q->state, q->state + (size_t)13 * q->n_bodies);
+  r->body.assign(q->body, q->body + (size_t)5 * q->n_bodies);
+  for (int i = 0; i < q->n_bodies; ++i) {
+    float tmp[8];
+    pmbs_status s = body_constants(q->body, q->n_bodies, i, tmp, 1);
+    if (s != PMBS_OK) return s;
+  }
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) return fail(PMBS_ERR_INVALID_ARG, "server is stopping");
+    r->id = srv->next_id++;
+    *id = r->id;
+    srv->waiting.push_back(r->id);
+    srv->reqs.emplace(r->id, std::move(r));
+    ++srv->submitted;
+  }
+  srv->cv_work.notify_all();
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_server_poll(pmbs_server_t* srv, uint64_t id, pmbs_request_result* out, int32_t* done) {
+  if (!srv || !out || !done) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(id);
+  if (it == srv->reqs.end()) return fail(PMBS_ERR_INVALID_ARG, "unknown request %llu", (unsigned long long)id);
+  if (it->second->phase != Request::kDone) {
+    *done = 0;
+    return PMBS_OK;
+  }
+  *out = it->second->result;
+  *done = 1;
+  srv->reqs.erase(it);
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_server_wait(pmbs_server_t* srv, uint64_t id, pmbs_request_result* out) {
+  if (!srv || !out) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(id);
+  if (it == srv->reqs.end()) return fail(PMBS_ERR_INVALID_ARG, "unknown request %llu", (unsigned long long)id);
+  Request* r = it->second.get();
+  srv->cv_done.wait(lk, [&] { return r->phase == Request::kDone; });
+  *out = r->result;
+  srv->reqs.erase(id);
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_server_cancel(pmbs_server_t* srv, uint64_t id) {
+  if (!srv) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  Request* waiting_req = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(id);
+    if (it == srv->reqs.end()) return fail(PMBS_ERR_INVALID_ARG, "unknown request %llu", (unsigned long long)id);
+    Request* r = it->second.get();
+    r->cancel = true;
+    if (r->phase == Request::kWaiting) {
+      srv->waiting.erase(std::find(srv->waiting.begin(), srv->waiting.end(), id));
+      waiting_req = r;
+    }
+  }
+  if (waiting_req) srv->finish(waiting_req, PMBS_ERR_CANCELLED);
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_server_get_stats(pmbs_server_t* srv, pmbs_server_stats* out) {
+  if (!srv || !out) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  out->submitted = srv->submitted;
+  out->completed = srv->completed;
+  out->launches = srv->launches;
+  out->env_substeps = srv->env_substeps;
+  out->busy_seconds = srv->busy;
+  out->in_flight = (int32_t)srv->active.size();
+  out->waiting = (int32_t)srv->waiting.size();
+  out->peak_in_flight = srv->peak_in_flight;
+  out->held_bytes = srv->held;
+  out->peak_held_bytes = srv->peak_held;
+  return PMBS_OK;
+}
+
+void pmbs_server_destroy(pmbs_server_t* srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+  }
+  srv->cv_work.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  (void)hipStreamSynchronize(srv->sim->stream);
+  // what is left ends cancelled (its trees are freed with the requests)
+  std::vector<Request*> left;
+  for (auto& kv : srv->reqs)
+    if (kv.second->phase != Request::kDone) left.push_back(kv.second.get());
+  for (Request* r : left) srv->finish(r, PMBS_ERR_CANCELLED);
+  pmbs_sim_destroy(srv->sim);
+  delete srv;
+}
+
+}  // extern "C"

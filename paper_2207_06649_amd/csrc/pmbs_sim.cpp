@@ -40,7 +40,8 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // Workspace regions, in order.  Every region starts 256-byte aligned.
 struct Layout {
   size_t state, bconst, env_offset, push, status, target, reward, clearance, slots, stats, pool;
-  size_t actions, act_offset, src_slot, child_slot, order, queue, roll_rewards, roll_counts, total;
+  size_t actions, act_offset, src_slot, child_slot, order, roll_rewards, roll_counts;
+  size_t ctl, ovf4, ovf8, bc_base, total;
 };
 
 static Layout layout_of(const pmbs_sim_config& c) {
@@ -67,10 +68,13 @@ static Layout layout_of(const pmbs_sim_config& c) {
   L.act_offset = take((ne + 1) * sizeof(int32_t));
   L.src_slot = take(ne * sizeof(int32_t));
   L.child_slot = take(ne * sizeof(int32_t));
-  L.order = take(ne * sizeof(int32_t));
-  L.queue = take(64);
+  L.order = take(2 * ne * sizeof(int32_t));
   L.roll_rewards = take(ne * (size_t)c.max_horizon * sizeof(float));
   L.roll_counts = take(ne * sizeof(int32_t));
+  L.ctl = take(64 * sizeof(int32_t));
+  L.ovf4 = take(ne * sizeof(int32_t));
+  L.ovf8 = take(ne * sizeof(int32_t));
+  L.bc_base = take(ne * sizeof(int32_t));
   L.total = o;
   return L;
 }
@@ -140,21 +144,207 @@ static pmbs_status stage_push(pmbs_sim_t* sim, const float* push, int32_t push_i
   return PMBS_OK;
 }
 
-// blocks that fit on the device at once for the configured contact class
-int persistent_grid(pmbs_sim_t* sim) {
-  if (sim->grid_cache > 0) return sim->grid_cache;
-  int dev = 0, cus = 256, per_cu = 0;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+// Body constants of body i of a host SoA [5][n] (hx, hy, hz, mass, mu):
+// half extents, inverse mass, inverse body inertia of a solid cuboid
+// I = m/12 (e_y^2 + e_z^2, ...), friction; written to out[k * stride].
+pmbs_status body_constants(const float* body, int n, int i, float* out, size_t stride) {
+  double hx = body[0 * n + i], hy = body[1 * n + i], hz = body[2 * n + i], m = body[3 * n + i], mu = body[4 * n + i];
+  if (!(hx > 0 && hy > 0 && hz > 0 && m > 0 && mu >= 0) || !std::isfinite(hx + hy + hz + m + mu))
+    return fail(PMBS_ERR_STATE, "body %d: half extents and mass must be > 0, mu >= 0", i);
+  double ex = 2 * hx, ey = 2 * hy, ez = 2 * hz;
+  out[0 * stride] = (float)hx;
+  out[1 * stride] = (float)hy;
+  out[2 * stride] = (float)hz;
+  out[3 * stride] = (float)(1.0 / m);
+  out[4 * stride] = (float)(12.0 / (m * (ey * ey + ez * ez)));
+  out[5 * stride] = (float)(12.0 / (m * (ex * ex + ez * ez)));
+  out[6 * stride] = (float)(12.0 / (m * (ex * ex + ey * ey)));
+  out[7 * stride] = (float)mu;
+  return PMBS_OK;
+}
+
+static pmbs_status check_state(const float* state, int n) {
+  for (int i = 0; i < n; ++i) {
+    double qn = 0;
+    for (int r = 0; r < 13; ++r)
+      if (!std::isfinite(state[(size_t)r * n + i])) return fail(PMBS_ERR_STATE, "body %d: non-finite state", i);
+    for (int r = 3; r < 7; ++r) qn += (double)state[(size_t)r * n + i] * state[(size_t)r * n + i];
+    if (std::fabs(std::sqrt(qn) - 1.0) > 1e-3) return fail(PMBS_ERR_STATE, "body %d: quaternion not unit", i);
   }
-  per_cu = step_blocks_per_cu(sim->cfg.max_contacts);
-  sim->grid_cache = cus * (per_cu > 0 ? per_cu : 1);
-  return sim->grid_cache;
+  return PMBS_OK;
+}
+
+pmbs_status upload_bodies(pmbs_sim_t* sim, int row0, int n, const float* body) {
+  const int N = sim->cfg.max_bodies;
+  if (row0 < 0 || n < 0 || row0 + n > N) return fail(PMBS_ERR_CAPACITY, "body rows [%d, %d) outside %d", row0, row0 + n, N);
+  std::vector<float> bc((size_t)8 * n);
+  for (int i = 0; i < n; ++i) {
+    pmbs_status bs = body_constants(body, n, i, bc.data() + i, (size_t)n);
+    if (bs != PMBS_OK) return bs;
+  }
+  for (int r = 0; r < 8 && n > 0; ++r) {
+    hipError_t e = hipMemcpyAsync(sim->d_bconst + (size_t)r * N + row0, bc.data() + (size_t)r * n, (size_t)n * sizeof(float),
+                                  hipMemcpyHostToDevice, sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "body upload");
+  }
+  hipError_t e = hipStreamSynchronize(sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "body upload sync");
+  return PMBS_OK;
+}
+
+pmbs_status upload_pool_slot(pmbs_sim_t* sim, int slot, int n, const float* state) {
+  if (!sim->d_pool || slot < 0 || slot >= sim->cfg.pool_slots || n > sim->cfg.pool_stride)
+    return fail(PMBS_ERR_CAPACITY, "pool slot %d with %d bodies does not fit", slot, n);
+  pmbs_status st = check_state(state, n);
+  if (st != PMBS_OK) return st;
+  const int PS = sim->cfg.pool_stride;
+  for (int r = 0; r < 13 && n > 0; ++r) {
+    hipError_t e = hipMemcpyAsync(sim->d_pool + ((size_t)slot * 13 + r) * PS, state + (size_t)r * n,
+                                  (size_t)n * sizeof(float), hipMemcpyHostToDevice, sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "pool upload");
+  }
+  hipError_t e = hipStreamSynchronize(sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "pool upload sync");
+  return PMBS_OK;
+}
+
+pmbs_status set_layout(pmbs_sim_t* sim, int n_envs, const int32_t* env_offset, const int32_t* bc_base) {
+  if (n_envs < 0 || n_envs > sim->cfg.max_envs) return fail(PMBS_ERR_CAPACITY, "n_envs %d > max_envs", n_envs);
+  if (env_offset[0] != 0) return fail(PMBS_ERR_INVALID_ARG, "env_offset[0] must be 0");
+  for (int e = 0; e < n_envs; ++e) {
+    const int nb = env_offset[e + 1] - env_offset[e];
+    if (nb < 1 || nb > PMBS_MAX_BODIES_PER_ENV) return fail(PMBS_ERR_CAPACITY, "env %d: %d bodies", e, nb);
+    if (bc_base[e] < 0 || bc_base[e] + nb > sim->cfg.max_bodies)
+      return fail(PMBS_ERR_CAPACITY, "env %d: body rows outside max_bodies", e);
+  }
+  hipError_t e = hipMemcpyAsync(sim->d_env_offset, env_offset, (size_t)(n_envs + 1) * sizeof(int32_t),
+                                hipMemcpyHostToDevice, sim->stream);
+  if (e == hipSuccess && n_envs > 0)
+    e = hipMemcpyAsync(sim->d_bc_base, bc_base, (size_t)n_envs * sizeof(int32_t), hipMemcpyHostToDevice, sim->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "layout upload");
+  sim->host_offset.assign(env_offset, env_offset + n_envs + 1);
+  sim->n_envs = n_envs;
+  sim->n_bodies = 0;
+  sim->pool_layout = true;
+  return PMBS_OK;
+}
+
+pmbs_status rewards_from_pool(pmbs_sim_t* sim, const int32_t* slots, const int32_t* target, float width, float* out) {
+  const int n = sim->n_envs;
+  if (!sim->pool_layout) return fail(PMBS_ERR_INVALID_ARG, "no pool layout set");
+  if (n == 0) return PMBS_OK;
+  hipError_t e = hipMemcpyAsync(sim->d_slots, slots, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, sim->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sim->d_target, target, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "reward input upload");
+  RewardArgs a{};
+  a.state = sim->d_state;
+  a.bconst = sim->d_bconst;
+  a.env_offset = sim->d_env_offset;
+  a.target = sim->d_target;
+  a.reward = sim->d_reward;
+  a.n_envs = n;
+  a.stride = sim->cfg.max_bodies;
+  a.width = width;
+  a.pool = sim->d_pool;
+  a.slots = sim->d_slots;
+  a.pool_stride = sim->cfg.pool_stride;
+  a.bc_base = sim->d_bc_base;
+  a.bc_stride = sim->cfg.max_bodies;
+  if ((e = launch_reward(a, sim->stream)) != hipSuccess) return hip_fail(e, "reward launch");
+  e = hipMemcpyAsync(out, sim->d_reward, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, sim->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "reward download");
+  return PMBS_OK;
+}
+
+static int class_index(int max_contacts) { return max_contacts <= 128 ? 0 : max_contacts <= 256 ? 1 : 2; }
+
+int class_grid(pmbs_sim_t* sim, int max_contacts, int blocks_per_cu) {
+  if (sim->cus <= 0) {
+    int dev = 0;
+    sim->cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      sim->cus = prop.multiProcessorCount;
+  }
+  const int k = class_index(max_contacts);
+  if (sim->occ[k] <= 0) {
+    const int o = step_blocks_per_cu(max_contacts);
+    sim->occ[k] = o > 0 ? o : 1;
+  }
+  const int per_cu = blocks_per_cu > 0 && blocks_per_cu < sim->occ[k] ? blocks_per_cu : sim->occ[k];
+  return sim->cus * per_cu;
+}
+
+static hipError_t ensure_streams(pmbs_sim_t* sim) {
+  hipError_t e = hipSuccess;
+  if (!sim->side) e = hipStreamCreateWithFlags(&sim->side, hipStreamNonBlocking);
+  if (e == hipSuccess && !sim->cap) e = hipStreamCreateWithFlags(&sim->cap, hipStreamNonBlocking);
+  if (e == hipSuccess && !sim->ev_fork) e = hipEventCreateWithFlags(&sim->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess && !sim->ev_join) e = hipEventCreateWithFlags(&sim->ev_join, hipEventDisableTiming);
+  return e;
+}
+
+// Queued rollout launches.  With max_contacts 128 one 128-contact kernel
+// takes every env.  Otherwise the large-class kernel (256 contacts) runs on
+// the side stream while the 128-contact kernel runs on `stream`; envs that
+// overflow the 128-contact kernel are re-run by a 256-contact fallback, and
+// with max_contacts 512 overflows of either 256-contact kernel by a
+// 512-contact fallback after both.  skip_empty leaves out kernels whose
+// host-known lists are empty (never inside a captured graph, whose launches
+// must not depend on the counts).
+hipError_t enqueue_queued(pmbs_sim_t* sim, const StepArgs& a, hipStream_t stream, bool skip_empty, int n_small,
+                          int n_large) {
+  const int mc = sim->cfg.max_contacts;
+  int* ctl = sim->d_ctl;
+  const pmbs_launch_plan& pl = sim->plan;
+  hipError_t e = launch_zero(ctl, 6, stream);
+  if (e != hipSuccess) return e;
+  StepArgs sm = a, lg = a, f4 = a, f8 = a;
+  sm.order = sim->d_order;
+  sm.work_count = ctl + 8;
+  sm.queue = ctl + 0;
+  if (mc == 128) {
+    if (skip_empty && n_small == 0) return hipSuccess;
+    return launch_step_class(sm, 128, stream, class_grid(sim, 128, pl.small_blocks_per_cu));
+  }
+  sm.overflow_list = sim->d_ovf4;
+  sm.overflow_count = ctl + 4;
+  lg.order = sim->d_order + sim->cfg.max_envs;
+  lg.work_count = ctl + 9;
+  lg.queue = ctl + 1;
+  f4.order = sim->d_ovf4;
+  f4.work_count = ctl + 4;
+  f4.queue = ctl + 2;
+  if (mc > 256) {
+    lg.overflow_list = f4.overflow_list = sim->d_ovf8;
+    lg.overflow_count = f4.overflow_count = ctl + 5;
+  }
+  f8.order = sim->d_ovf8;
+  f8.work_count = ctl + 5;
+  f8.queue = ctl + 3;
+  const bool run_large = !skip_empty || n_large > 0, run_small = !skip_empty || n_small > 0;
+  if (run_large) {
+    if ((e = hipEventRecord(sim->ev_fork, stream)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(sim->side, sim->ev_fork, 0)) != hipSuccess) return e;
+    if ((e = launch_step_class(lg, 256, sim->side, class_grid(sim, 256, pl.large_blocks_per_cu))) != hipSuccess)
+      return e;
+    if ((e = hipEventRecord(sim->ev_join, sim->side)) != hipSuccess) return e;
+  }
+  if (run_small) {
+    if ((e = launch_step_class(sm, 128, stream, class_grid(sim, 128, pl.small_blocks_per_cu))) != hipSuccess) return e;
+    if ((e = launch_step_class(f4, 256, stream, class_grid(sim, 256, pl.large_blocks_per_cu))) != hipSuccess) return e;
+  }
+  if (run_large && (e = hipStreamWaitEvent(stream, sim->ev_join, 0)) != hipSuccess) return e;
+  if (mc > 256) e = launch_step_class(f8, 512, stream, class_grid(sim, 512, 0));
+  return e;
 }
 
 StepArgs step_args(pmbs_sim_t* sim) {
-  StepArgs a{};
+  StepArgs a;
+  std::memset(&a, 0, sizeof a);  // padding too: launch arguments are compared bytewise
   a.state = sim->d_state;
   a.bconst = sim->d_bconst;
   a.env_offset = sim->d_env_offset;
@@ -169,6 +359,15 @@ StepArgs step_args(pmbs_sim_t* sim) {
 
 }  // namespace pmbs
 
+pmbs_sim::~pmbs_sim() {
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (side) (void)hipStreamDestroy(side);
+  if (cap) (void)hipStreamDestroy(cap);
+}
+
 using namespace pmbs;
 
 extern "C" {
@@ -181,6 +380,7 @@ const char* pmbs_status_string(pmbs_status s) {
     case PMBS_ERR_HIP: return "HIP runtime error";
     case PMBS_ERR_CAPACITY: return "capacity exceeded";
     case PMBS_ERR_STATE: return "bad state";
+    case PMBS_ERR_CANCELLED: return "cancelled";
     default: return "unknown status";
   }
 }
@@ -255,9 +455,16 @@ pmbs_status pmbs_sim_create(const pmbs_sim_config* cfg, void* d_workspace, size_
   s->d_src_slot = reinterpret_cast<int32_t*>(base + L.src_slot);
   s->d_child_slot = reinterpret_cast<int32_t*>(base + L.child_slot);
   s->d_order = reinterpret_cast<int32_t*>(base + L.order);
-  s->d_queue = reinterpret_cast<int32_t*>(base + L.queue);
   s->d_roll_rewards = reinterpret_cast<float*>(base + L.roll_rewards);
   s->d_roll_counts = reinterpret_cast<int32_t*>(base + L.roll_counts);
+  s->d_ctl = reinterpret_cast<int32_t*>(base + L.ctl);
+  s->d_ovf4 = reinterpret_cast<int32_t*>(base + L.ovf4);
+  s->d_ovf8 = reinterpret_cast<int32_t*>(base + L.ovf8);
+  s->d_bc_base = reinterpret_cast<int32_t*>(base + L.bc_base);
+  s->plan.small_max_bodies = 16;
+  s->plan.small_blocks_per_cu = 0;
+  s->plan.large_blocks_per_cu = 0;
+  s->plan.order = 1;
   s->n_envs = 0;
   s->n_bodies = 0;
   hipError_t e = hipMemsetAsync(s->d_status, 0, (size_t)cfg->max_envs * sizeof(uint32_t), s->stream);
@@ -270,6 +477,23 @@ pmbs_status pmbs_sim_create(const pmbs_sim_config* cfg, void* d_workspace, size_
 }
 
 void pmbs_sim_destroy(pmbs_sim_t* sim) { delete sim; }
+
+pmbs_status pmbs_sim_set_launch_plan(pmbs_sim_t* sim, const pmbs_launch_plan* plan) {
+  if (!sim || !plan) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (plan->small_max_bodies < -1 || plan->small_max_bodies > PMBS_MAX_BODIES_PER_ENV)
+    return fail(PMBS_ERR_INVALID_ARG, "small_max_bodies must be in [-1, %d]", PMBS_MAX_BODIES_PER_ENV);
+  if (plan->small_blocks_per_cu < 0 || plan->large_blocks_per_cu < 0)
+    return fail(PMBS_ERR_INVALID_ARG, "blocks per CU must be >= 0");
+  if (plan->order != 0 && plan->order != 1) return fail(PMBS_ERR_INVALID_ARG, "order must be 0 or 1");
+  sim->plan = *plan;
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_get_launch_plan(const pmbs_sim_t* sim, pmbs_launch_plan* plan) {
+  if (!sim || !plan) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  *plan = sim->plan;
+  return PMBS_OK;
+}
 
 pmbs_status pmbs_sim_set_state(pmbs_sim_t* sim, int32_t n_envs, const int32_t* env_offset, const float* state,
                                int32_t state_is_device, const float* body) {
@@ -286,32 +510,15 @@ pmbs_status pmbs_sim_set_state(pmbs_sim_t* sim, int32_t n_envs, const int32_t* e
   const int n = env_offset[n_envs];
   if (n > sim->cfg.max_bodies) return fail(PMBS_ERR_CAPACITY, "%d bodies exceed max_bodies %d", n, sim->cfg.max_bodies);
   const int N = sim->cfg.max_bodies;
-  // body constants: half extents, inverse mass, inverse body inertia of a
-  // solid cuboid I = m/12 (e_y^2 + e_z^2, ...), friction
   std::vector<float> bc((size_t)8 * N, 0.0f);
   for (int i = 0; i < n; ++i) {
-    double hx = body[0 * n + i], hy = body[1 * n + i], hz = body[2 * n + i], m = body[3 * n + i], mu = body[4 * n + i];
-    if (!(hx > 0 && hy > 0 && hz > 0 && m > 0 && mu >= 0) || !std::isfinite(hx + hy + hz + m + mu))
-      return fail(PMBS_ERR_STATE, "body %d: half extents and mass must be > 0, mu >= 0", i);
-    double ex = 2 * hx, ey = 2 * hy, ez = 2 * hz;
-    bc[0 * (size_t)N + i] = (float)hx;
-    bc[1 * (size_t)N + i] = (float)hy;
-    bc[2 * (size_t)N + i] = (float)hz;
-    bc[3 * (size_t)N + i] = (float)(1.0 / m);
-    bc[4 * (size_t)N + i] = (float)(12.0 / (m * (ey * ey + ez * ez)));
-    bc[5 * (size_t)N + i] = (float)(12.0 / (m * (ex * ex + ez * ez)));
-    bc[6 * (size_t)N + i] = (float)(12.0 / (m * (ex * ex + ey * ey)));
-    bc[7 * (size_t)N + i] = (float)mu;
+    pmbs_status bs = body_constants(body, n, i, bc.data() + i, N);
+    if (bs != PMBS_OK) return bs;
   }
   hipError_t e;
   if (!state_is_device) {
-    for (int i = 0; i < n; ++i) {
-      double qn = 0;
-      for (int r = 0; r < 13; ++r)
-        if (!std::isfinite(state[(size_t)r * n + i])) return fail(PMBS_ERR_STATE, "body %d: non-finite state", i);
-      for (int r = 3; r < 7; ++r) qn += (double)state[(size_t)r * n + i] * state[(size_t)r * n + i];
-      if (std::fabs(std::sqrt(qn) - 1.0) > 1e-3) return fail(PMBS_ERR_STATE, "body %d: quaternion not unit", i);
-    }
+    pmbs_status cs = check_state(state, n);
+    if (cs != PMBS_OK) return cs;
   }
   // state rows are strided by max_bodies on the device
   for (int r = 0; r < 13 && n > 0; ++r) {
@@ -331,11 +538,13 @@ pmbs_status pmbs_sim_set_state(pmbs_sim_t* sim, int32_t n_envs, const int32_t* e
   sim->host_offset.assign(env_offset, env_offset + n_envs + 1);
   sim->n_envs = n_envs;
   sim->n_bodies = n;
+  sim->pool_layout = false;
   return PMBS_OK;
 }
 
 pmbs_status pmbs_sim_get_state(pmbs_sim_t* sim, float* out, int32_t dst_is_device) {
   if (!sim || !out) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (sim->pool_layout) return fail(PMBS_ERR_INVALID_ARG, "the env layout holds pool-only rollouts: load a state first");
   const int n = sim->n_bodies, N = sim->cfg.max_bodies;
   for (int r = 0; r < 13 && n > 0; ++r) {
     hipError_t e = hipMemcpyAsync(out + (size_t)r * n, sim->d_state + (size_t)r * N, (size_t)n * sizeof(float),
@@ -351,6 +560,7 @@ pmbs_status pmbs_sim_get_state(pmbs_sim_t* sim, float* out, int32_t dst_is_devic
 
 pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_device, int32_t n_substeps) {
   if (!sim || !push) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (sim->pool_layout) return fail(PMBS_ERR_INVALID_ARG, "the env layout holds pool-only rollouts: load a state first");
   if (n_substeps < 0) return fail(PMBS_ERR_INVALID_ARG, "n_substeps must be >= 0");
   const float4* d_push;
   pmbs_status st = stage_push(sim, push, push_is_device, &d_push);
@@ -392,8 +602,10 @@ pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int3
   if ((src_slot || child_slot) && !sim->d_pool) return fail(PMBS_ERR_CAPACITY, "rollout from/to pool slots needs a pool");
   const bool use_queue = (flags & PMBS_ROLLOUT_QUEUE) != 0;
   if (use_queue && inputs_on_device) return fail(PMBS_ERR_INVALID_ARG, "the work queue orders host inputs");
+  if (sim->pool_layout && (inputs_on_device || !src_slot || (flags & PMBS_ROLLOUT_WRITE_STATE)))
+    return fail(PMBS_ERR_INVALID_ARG, "a pool-only layout needs host source slots and no state write-back");
   int total = 0;
-  std::vector<int32_t> order;
+  std::vector<int32_t> order, order_large;
   if (!inputs_on_device) {
     if (act_offset[0] != 0) return fail(PMBS_ERR_INVALID_ARG, "act_offset[0] must be 0");
     for (int e = 0; e < n; ++e) {
@@ -405,18 +617,25 @@ pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int3
         if (actions[k] < 0 || actions[k] >= nb * 8) return fail(PMBS_ERR_INVALID_ARG, "env %d: action %d out of range", e, actions[k]);
       if (target[e] < 0 || target[e] >= nb) return fail(PMBS_ERR_INVALID_ARG, "env %d: target out of range", e);
       if (src_slot && src_slot[e] >= sim->cfg.pool_slots) return fail(PMBS_ERR_CAPACITY, "env %d: source slot", e);
+      if (sim->pool_layout && src_slot[e] < 0) return fail(PMBS_ERR_INVALID_ARG, "env %d: needs a source slot", e);
       if (child_slot && child_slot[e] >= sim->cfg.pool_slots) return fail(PMBS_ERR_CAPACITY, "env %d: child slot", e);
       if ((src_slot && src_slot[e] >= 0) || (child_slot && child_slot[e] >= 0))
         if (nb > sim->cfg.pool_stride) return fail(PMBS_ERR_CAPACITY, "env %d: %d bodies > pool_stride", e, nb);
     }
     total = act_offset[n];
     if (use_queue) {
-      // longest horizon first, ties by env index (deterministic schedule)
-      order.resize(n);
-      for (int e = 0; e < n; ++e) order[e] = e;
-      std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return act_offset[a + 1] - act_offset[a] > act_offset[b + 1] - act_offset[b];
-      });
+      // contact class by body count, then largest estimated work first, ties
+      // by env index (a deterministic schedule)
+      const int T = sim->cfg.max_contacts == 128 ? PMBS_MAX_BODIES_PER_ENV : sim->plan.small_max_bodies;
+      std::vector<int64_t> wt(n);
+      for (int e = 0; e < n; ++e) {
+        const int h = act_offset[e + 1] - act_offset[e], nb = sim->host_offset[e + 1] - sim->host_offset[e];
+        wt[e] = sim->plan.order == 0 ? h : (int64_t)h * (nb + 4);
+        (nb <= T ? order : order_large).push_back(e);
+      }
+      auto by_work = [&](int a, int b) { return wt[a] > wt[b]; };
+      std::stable_sort(order.begin(), order.end(), by_work);
+      std::stable_sort(order_large.begin(), order_large.end(), by_work);
     }
   } else if (max_h > sim->cfg.max_horizon) {
     return fail(PMBS_ERR_CAPACITY, "max_h %d > max_horizon %d", max_h, sim->cfg.max_horizon);
@@ -435,12 +654,13 @@ pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int3
   a.child_slot = p;
   if ((st = stage_ints(sim, target, (size_t)n, inputs_on_device, sim->d_target, &p)) != PMBS_OK) return st;
   a.target = p;
-  int grid = 0;
+  const int32_t counts[2] = {(int32_t)order.size(), (int32_t)order_large.size()};
   if (use_queue) {
-    if ((st = stage_ints(sim, order.data(), (size_t)n, 0, sim->d_order, &p)) != PMBS_OK) return st;
-    a.order = p;
-    a.queue = sim->d_queue;
-    grid = persistent_grid(sim);
+    if ((st = stage_ints(sim, order.data(), order.size(), 0, sim->d_order, &p)) != PMBS_OK) return st;
+    if ((st = stage_ints(sim, order_large.data(), order_large.size(), 0, sim->d_order + sim->cfg.max_envs, &p)) !=
+        PMBS_OK)
+      return st;
+    if ((st = stage_ints(sim, counts, 2, 0, sim->d_ctl + 8, &p)) != PMBS_OK) return st;
   }
   if (!inputs_on_device) {
     hipError_t e = hipStreamSynchronize(sim->stream);
@@ -448,14 +668,57 @@ pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int3
   }
   a.pool = sim->d_pool;
   a.pool_stride = sim->cfg.pool_stride;
+  if (sim->pool_layout) {
+    a.bc_base = sim->d_bc_base;
+    a.bc_stride = sim->cfg.max_bodies;
+  }
   a.rewards = d_rewards;
   a.reward_count = d_reward_count;
   a.max_h = max_h;
   a.width = width;
   a.write_state = (flags & PMBS_ROLLOUT_WRITE_STATE) ? 1 : 0;
   a.n_substeps = n_substeps;
-  hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream, grid);
-  if (e != hipSuccess) return hip_fail(e, "rollout launch");
+  if (!use_queue) {
+    hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "rollout launch");
+    return PMBS_OK;
+  }
+  a.n_envs = 0;  // queued kernels take their counts from the device
+  hipError_t e = ensure_streams(sim);
+  if (e != hipSuccess) return hip_fail(e, "stream creation");
+  for (int mc : {128, 256, 512})
+    if (mc <= sim->cfg.max_contacts) (void)class_grid(sim, mc, 0);  // occupancy queries outside any capture
+  if (!(flags & PMBS_ROLLOUT_GRAPH)) {
+    e = enqueue_queued(sim, a, sim->stream, true, counts[0], counts[1]);
+    if (e != hipSuccess) return hip_fail(e, "rollout launch");
+    return PMBS_OK;
+  }
+  if (!sim->graph_exec || std::memcmp(&sim->graph_args, &a, sizeof a) != 0 ||
+      std::memcmp(&sim->graph_plan, &sim->plan, sizeof sim->plan) != 0) {
+    if (sim->graph_exec) (void)hipGraphExecDestroy(sim->graph_exec);
+    if (sim->graph) (void)hipGraphDestroy(sim->graph);
+    sim->graph_exec = nullptr;
+    sim->graph = nullptr;
+    e = hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+    const hipError_t ce = enqueue_queued(sim, a, sim->cap, false, 0, 0);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(sim->cap, &graph);
+    if (ce != hipSuccess || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(ce != hipSuccess ? ce : e, "graph capture");
+    }
+    sim->graph = graph;
+    e = hipGraphInstantiate(&sim->graph_exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      sim->graph_exec = nullptr;
+      return hip_fail(e, "graph instantiate");
+    }
+    sim->graph_args = a;
+    sim->graph_plan = sim->plan;
+  }
+  e = hipGraphLaunch(sim->graph_exec, sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
   return PMBS_OK;
 }
 
@@ -475,6 +738,7 @@ pmbs_status pmbs_sim_env_status(pmbs_sim_t* sim, uint32_t* out, int32_t dst_is_d
 pmbs_status pmbs_sim_collide(pmbs_sim_t* sim, const float* push, int32_t push_is_device, int32_t* d_counts,
                              float* d_contacts) {
   if (!sim || !d_counts || !d_contacts) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (sim->pool_layout) return fail(PMBS_ERR_INVALID_ARG, "the env layout holds pool-only rollouts: load a state first");
   const float4* d_push;
   pmbs_status st = stage_push(sim, push, push_is_device, &d_push);
   if (st != PMBS_OK) return st;
@@ -492,6 +756,7 @@ pmbs_status pmbs_sim_collide(pmbs_sim_t* sim, const float* push, int32_t push_is
 pmbs_status pmbs_eval_reward(pmbs_sim_t* sim, const int32_t* target, int32_t target_is_device, float width,
                              float* d_reward, float* d_clearance) {
   if (!sim || !target || !d_reward) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (sim->pool_layout) return fail(PMBS_ERR_INVALID_ARG, "the env layout holds pool-only rollouts: load a state first");
   if (!(width > 0)) return fail(PMBS_ERR_INVALID_ARG, "width must be > 0");
   const int n = sim->n_envs;
   if (!target_is_device) {
@@ -527,6 +792,7 @@ pmbs_status pmbs_eval_reward(pmbs_sim_t* sim, const int32_t* target, int32_t tar
 
 static pmbs_status pool_op(pmbs_sim_t* sim, const int32_t* slots, int32_t slots_is_device, int to_pool) {
   if (!sim || !slots) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (sim->pool_layout) return fail(PMBS_ERR_INVALID_ARG, "the env layout holds pool-only rollouts: load a state first");
   if (!sim->d_pool) return fail(PMBS_ERR_CAPACITY, "simulator was created without a state pool");
   const int n = sim->n_envs;
   if (!slots_is_device) {

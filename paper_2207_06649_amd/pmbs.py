@@ -19,9 +19,19 @@ LIB_PATH = os.path.join(HERE, "libpmbs.so")
 PMBS_ENV_CONTACT_OVERFLOW = 1
 PMBS_ENV_NONFINITE = 2
 PMBS_ENV_PUSH_INVALID = 4
+PMBS_ERR_CANCELLED = -6
 ROLLOUT_WRITE_STATE = 1
 ROLLOUT_QUEUE = 2
+ROLLOUT_GRAPH = 4
 MAX_BODIES_PER_ENV = 31
+
+
+class LaunchPlan(C.Structure):
+    _fields_ = [("small_max_bodies", C.c_int32), ("small_blocks_per_cu", C.c_int32),
+                ("large_blocks_per_cu", C.c_int32), ("order", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class SimConfig(C.Structure):
@@ -70,6 +80,11 @@ def lib():
         L.pmbs_sim_stats.argtypes = [vp, vp]
         L.pmbs_pool_gather.argtypes = [vp, vp, C.c_int32]
         L.pmbs_pool_scatter.argtypes = [vp, vp, C.c_int32]
+        L.pmbs_sim_set_launch_plan.argtypes = [vp, C.POINTER(LaunchPlan)]
+        L.pmbs_sim_get_launch_plan.argtypes = [vp, C.POINTER(LaunchPlan)]
+        L.pmbs_sim_autotune.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, C.c_float, vp, C.c_int32, vp, C.c_int32,
+                                        C.c_int32, C.c_char_p, C.POINTER(LaunchPlan), C.POINTER(C.c_float),
+                                        C.POINTER(C.c_int32)]
         L.pmbs_sim_rollout.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_float, vp, C.c_int32,
                                        vp, C.c_int32]
         L.pmbs_sim_shape.argtypes = [vp, ip, ip]
@@ -244,25 +259,27 @@ class Sim:
         _check(lib().pmbs_pool_scatter(self.handle, ptr, dev))
         return keep
 
-    def rollout(self, actions, act_offset, target, n_substeps=120, width=0.08, src_slot=None, child_slot=None,
-                max_h=None, flags=ROLLOUT_WRITE_STATE, sync=True):
-        """Contour-push rollouts (host int inputs).  Returns (rewards [E, max_h],
-        counts [E]) as numpy when sync, else the device tensors."""
-        t = self.torch
+    def _rollout_inputs(self, actions, act_offset, target, src_slot, child_slot, max_h):
         off = np.ascontiguousarray(act_offset, np.int32)
         acts = np.ascontiguousarray(actions, np.int32) if len(actions) else np.zeros(1, np.int32)
         tg = np.ascontiguousarray(target, np.int32)
         mh = int(max_h if max_h is not None else max(1, int(np.diff(off).max()) if len(off) > 1 else 1))
-        rew = t.full((self.n_envs, mh), -1.0, dtype=t.float32, device=self.device)
-        cnt = t.zeros(self.n_envs, dtype=t.int32, device=self.device)
-        keep = [off, acts, tg]
-        ss = cs = None
-        if src_slot is not None:
-            ss = np.ascontiguousarray(src_slot, np.int32)
-            keep.append(ss)
-        if child_slot is not None:
-            cs = np.ascontiguousarray(child_slot, np.int32)
-            keep.append(cs)
+        ss = None if src_slot is None else np.ascontiguousarray(src_slot, np.int32)
+        cs = None if child_slot is None else np.ascontiguousarray(child_slot, np.int32)
+        return off, acts, tg, mh, ss, cs
+
+    def rollout(self, actions, act_offset, target, n_substeps=120, width=0.08, src_slot=None, child_slot=None,
+                max_h=None, flags=ROLLOUT_WRITE_STATE, sync=True, rewards=None, counts=None):
+        """Contour-push rollouts (host int inputs).  Returns (rewards [E, max_h],
+        counts [E]) as numpy when sync, else the device tensors.  rewards /
+        counts may be given as device tensors to reuse (a captured graph is
+        replayed only while its output pointers stay the same)."""
+        t = self.torch
+        off, acts, tg, mh, ss, cs = self._rollout_inputs(actions, act_offset, target, src_slot, child_slot, max_h)
+        rew = rewards if rewards is not None else t.empty((self.n_envs, mh), dtype=t.float32, device=self.device)
+        cnt = counts if counts is not None else t.empty(self.n_envs, dtype=t.int32, device=self.device)
+        if tuple(rew.shape) != (self.n_envs, mh) or rew.dtype != t.float32 or cnt.numel() < self.n_envs:
+            raise PmbsError("rewards must be float32 [n_envs, max_h] and counts int32 [n_envs]")
         ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
         _check(lib().pmbs_sim_rollout(self.handle, ptr(acts), ptr(off), ptr(ss), ptr(cs), ptr(tg), 0, int(n_substeps),
                                       float(width), _ptr(rew), mh, _ptr(cnt), int(flags)))
@@ -270,6 +287,31 @@ class Sim:
             return rew, cnt
         self.sync()
         return rew.cpu().numpy(), cnt.cpu().numpy()
+
+    def set_launch_plan(self, small_max_bodies=16, small_blocks_per_cu=0, large_blocks_per_cu=0, order=1):
+        p = LaunchPlan(small_max_bodies, small_blocks_per_cu, large_blocks_per_cu, order)
+        _check(lib().pmbs_sim_set_launch_plan(self.handle, C.byref(p)))
+
+    def launch_plan(self) -> dict:
+        p = LaunchPlan()
+        _check(lib().pmbs_sim_get_launch_plan(self.handle, C.byref(p)))
+        return p.as_dict()
+
+    def autotune(self, actions, act_offset, target, n_substeps=120, width=0.08, src_slot=None, child_slot=None,
+                 max_h=None, flags=0, reps=3, cache_path=None, rewards=None, counts=None):
+        """Times launch plans on this rollout workload and installs the
+        fastest.  Returns (plan dict, milliseconds, cached)."""
+        t = self.torch
+        off, acts, tg, mh, ss, cs = self._rollout_inputs(actions, act_offset, target, src_slot, child_slot, max_h)
+        rew = rewards if rewards is not None else t.empty((self.n_envs, mh), dtype=t.float32, device=self.device)
+        cnt = counts if counts is not None else t.empty(self.n_envs, dtype=t.int32, device=self.device)
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
+        plan, ms, hit = LaunchPlan(), C.c_float(0.0), C.c_int32(0)
+        _check(lib().pmbs_sim_autotune(self.handle, ptr(acts), ptr(off), ptr(ss), ptr(cs), ptr(tg), int(n_substeps),
+                                       float(width), _ptr(rew), mh, _ptr(cnt), int(flags), int(reps),
+                                       None if cache_path is None else os.fsencode(cache_path),
+                                       C.byref(plan), C.byref(ms), C.byref(hit)))
+        return plan.as_dict(), float(ms.value), bool(hit.value)
 
     def sync(self):
         _check(lib().pmbs_sim_sync(self.handle))
@@ -393,3 +435,125 @@ def plan(sim: "Sim", tree: Tree, state, body, target: int, iters: int, n_substep
     out = {k: getattr(res, k) for k, _ in PlanResult._fields_}
     out["push"] = list(res.push)
     return out
+
+
+# ---------------------------------------------------------------- serving
+class ServerConfig(C.Structure):
+    _fields_ = [("sim", SimConfig), ("max_envs", C.c_int32), ("max_requests", C.c_int32),
+                ("pool_slots", C.c_int32), ("max_depth", C.c_int32), ("n_substeps", C.c_int32),
+                ("width", C.c_float), ("c", C.c_double), ("gamma", C.c_double), ("hbm_budget", C.c_int64),
+                ("graph", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("state", C.c_void_p), ("body", C.c_void_p), ("n_bodies", C.c_int32), ("target", C.c_int32),
+                ("leaves", C.c_int32), ("iterations", C.c_int32), ("seed", C.c_uint64)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("plan", PlanResult), ("queued_seconds", C.c_double), ("latency_seconds", C.c_double),
+                ("footprint_bytes", C.c_int64), ("status", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("launches", C.c_int64),
+                ("env_substeps", C.c_int64), ("busy_seconds", C.c_double), ("in_flight", C.c_int32),
+                ("waiting", C.c_int32), ("peak_in_flight", C.c_int32), ("held_bytes", C.c_int64),
+                ("peak_held_bytes", C.c_int64)]
+
+
+def _server_lib():
+    L = _tree_lib()
+    if not getattr(L, "_server_ready", False):
+        vp = C.c_void_p
+        L.pmbs_server_config_default.argtypes = [C.POINTER(ServerConfig)]
+        L.pmbs_server_config_default.restype = None
+        L.pmbs_server_query_workspace.argtypes = [C.POINTER(ServerConfig), C.POINTER(C.c_size_t)]
+        L.pmbs_server_create.argtypes = [C.POINTER(ServerConfig), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.pmbs_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+        L.pmbs_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(RequestResult), C.POINTER(C.c_int32)]
+        L.pmbs_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(RequestResult)]
+        L.pmbs_server_cancel.argtypes = [vp, C.c_uint64]
+        L.pmbs_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.pmbs_server_destroy.argtypes = [vp]
+        L.pmbs_server_destroy.restype = None
+        L._server_ready = True
+    return L
+
+
+def server_config(**over) -> ServerConfig:
+    c = ServerConfig()
+    _server_lib().pmbs_server_config_default(C.byref(c))
+    for k, v in over.items():
+        if k in dict(SimConfig._fields_):
+            setattr(c.sim, k, v)
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def _result_dict(r: RequestResult) -> dict:
+    out = {k: getattr(r.plan, k) for k, _ in PlanResult._fields_}
+    out["push"] = list(r.plan.push)
+    for k in ("queued_seconds", "latency_seconds", "footprint_bytes", "status"):
+        out[k] = getattr(r, k)
+    return out
+
+
+class Server:
+    """Planning requests with continuous batching (a worker thread in the
+    library owns the GPU work; submit never blocks)."""
+
+    def __init__(self, cfg: ServerConfig | None = None, device: str = "cuda:0", **over):
+        import torch
+        if not torch.cuda.is_available():
+            raise PmbsError("no GPU visible: the server runs only on the HIP path")
+        L = _server_lib()
+        self._L = L
+        self.cfg = cfg if cfg is not None else server_config(**over)
+        nbytes = C.c_size_t(0)
+        _check(L.pmbs_server_query_workspace(C.byref(self.cfg), C.byref(nbytes)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        torch.cuda.synchronize(self.device)
+        h = C.c_void_p()
+        _check(L.pmbs_server_create(C.byref(self.cfg), _ptr(self.workspace), int(nbytes.value),
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def submit(self, state, body, target: int, leaves: int, iterations: int, seed: int = 0) -> int:
+        st = soa(state, 13)
+        bd = soa(body, 5)
+        q = Request(_np_ptr(st), _np_ptr(bd), st.shape[1], int(target), int(leaves), int(iterations), int(seed))
+        rid = C.c_uint64(0)
+        _check(self._L.pmbs_server_submit(self.handle, C.byref(q), C.byref(rid)))
+        return int(rid.value)
+
+    def poll(self, rid: int):
+        r, done = RequestResult(), C.c_int32(0)
+        _check(self._L.pmbs_server_poll(self.handle, rid, C.byref(r), C.byref(done)))
+        return _result_dict(r) if done.value else None
+
+    def wait(self, rid: int) -> dict:
+        r = RequestResult()
+        _check(self._L.pmbs_server_wait(self.handle, rid, C.byref(r)))
+        return _result_dict(r)
+
+    def cancel(self, rid: int):
+        _check(self._L.pmbs_server_cancel(self.handle, rid))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(self._L.pmbs_server_get_stats(self.handle, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self._L.pmbs_server_destroy(h)
+            self.handle = None
+
+    def __del__(self):
+        if getattr(self, "_L", None) is not None:
+            self.close()

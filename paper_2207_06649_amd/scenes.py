@@ -222,3 +222,40 @@ def retrieval_scene(seed: int, n_others: int = 20, region: float = 0.4) -> Batch
 
 def horizons(seed: int, n_envs: int, lo=1, hi=5) -> np.ndarray:
     return np.random.default_rng([seed, 99]).integers(lo, hi + 1, size=n_envs).astype(np.int32)
+
+
+def contour_actions(seed: int, counts, horizon) -> tuple[np.ndarray, np.ndarray]:
+    """Random contour-push actions (object * 8 + direction, Sec. IV-B) for
+    envs with counts[e] objects and horizon[e] pushes.  Returns the packed
+    actions and their offsets [E+1]."""
+    rng = np.random.default_rng([seed, 123])
+    counts = np.asarray(counts)
+    horizon = np.asarray(horizon)
+    off = np.zeros(len(counts) + 1, np.int32)
+    off[1:] = np.cumsum(horizon)
+    obj = np.floor(rng.random(int(off[-1])) * np.repeat(counts, horizon)).astype(np.int32)
+    dirs = rng.integers(0, 8, size=int(off[-1])).astype(np.int32)
+    return obj * 8 + dirs, off
+
+
+def pad_batch(b: Batch, n_to: int, spacing=0.1, at=(5.0, 5.0)) -> Batch:
+    """Pads every env to n_to bodies with 3 cm cubes resting on the table on a
+    grid far from the scene (they touch nothing but the table), as a fixed
+    shape batch does.  The real bodies keep their indices 0..n-1."""
+    envs = []
+    for e in range(b.n_envs):
+        x = b.env(e)
+        k = n_to - x.n_bodies
+        if k < 0:
+            raise ValueError(f"env {e} has {x.n_bodies} > {n_to} bodies")
+        st = np.zeros((k, STATE_W))
+        bd = np.zeros((k, BODY_W))
+        for i in range(k):
+            st[i, 0] = at[0] + spacing * (i % 8)
+            st[i, 1] = at[1] + spacing * (i // 8)
+            st[i, 2] = 0.015
+            st[i, 3] = 1.0
+            bd[i] = (0.015, 0.015, 0.015, 0.1, 0.5)
+        envs.append(Batch(np.array([0, n_to], np.int32), np.concatenate([x.state, st]),
+                          np.concatenate([x.body, bd]), x.push, x.target, x.region))
+    return concat(envs)

@@ -58,3 +58,16 @@ def test_create_rejects_small_workspace_without_gpu():
     h = C.c_void_p()
     st = pmbs.lib().pmbs_sim_create(C.byref(cfg), C.c_void_p(256), 16, None, C.byref(h))
     assert st == -2 and not h.value
+
+
+def test_server_config_and_workspace_size():
+    """Server defaults and the workspace size of the node pool (no GPU)."""
+    import ctypes as C
+    from paper_2207_06649_amd import pmbs
+    c = pmbs.server_config(max_requests=4, pool_slots=1000, max_envs=256)
+    assert c.max_depth == 5 and c.n_substeps == 120 and c.graph == 1 and c.sim.max_contacts == 256
+    n = C.c_size_t(0)
+    assert pmbs._server_lib().pmbs_server_query_workspace(C.byref(c), C.byref(n)) == 0
+    assert n.value >= 1000 * 31 * 13 * 4
+    bad = pmbs.server_config(max_requests=0)
+    assert pmbs._server_lib().pmbs_server_query_workspace(C.byref(bad), C.byref(n)) == -1  # invalid argument

@@ -94,12 +94,14 @@ def test_rollout_single_push_exact_and_child_snapshot(pm):
 
 
 def test_rollout_work_queue_matches_plain_launch(pm):
-    """Uneven horizons 1-5: the persistent longest-first launch gives bitwise
-    the plain launch's rewards and states."""
+    """Uneven horizons 1-5: the persistent longest-first launch (every env in
+    the 256-contact kernel) gives bitwise the plain launch's rewards and
+    states."""
     b, acts, off, tgt = rollout_case(3, 96, (5, 20), [1, 5, 3, 2, 4], substeps=15)
     outs = []
     for flags in (pm.ROLLOUT_WRITE_STATE, pm.ROLLOUT_WRITE_STATE | pm.ROLLOUT_QUEUE):
         sim = pm.Sim(max_envs=b.n_envs, max_bodies=b.n_bodies, max_contacts=256)
+        sim.set_launch_plan(small_max_bodies=-1)
         sim.set_state(b.env_offset, f32(b.state), f32(b.body))
         rew, cnt = sim.rollout(acts, off, tgt, n_substeps=15, flags=flags, max_h=5)
         outs.append((rew, cnt, sim.get_state()))

@@ -1,0 +1,112 @@
+"""Serving with continuous batching: each request's result is the same
+alone, in a mix, and through the single-request planner; admission by
+device-memory footprint; cancellation."""
+import numpy as np
+import pytest
+
+from paper_2207_06649_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("action", "value", "visits", "nodes", "simulations", "env_substeps", "iterations")
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_06649_amd import pmbs
+    return pmbs
+
+
+def requests():
+    out = []
+    for k, (n_others, leaves, iters) in enumerate([(5, 64, 4), (12, 32, 6), (20, 128, 3), (9, 16, 5)]):
+        sc = scenes.retrieval_scene(200 + k, n_others=n_others, region=0.3)
+        out.append(dict(state=sc.state, body=sc.body, target=0, leaves=leaves, iterations=iters, seed=50 + k))
+    return out
+
+
+def small_server(pm, **over):
+    kw = dict(max_envs=512, max_requests=8, pool_slots=4096, n_substeps=30)
+    kw.update(over)
+    return pm.Server(**kw)
+
+
+def same(a, b):
+    return all(a[k] == b[k] for k in KEYS) and a["push"] == b["push"] and a["status"] == b["status"] == 0
+
+
+def test_result_alone_equals_result_in_the_mix(pm):
+    reqs = requests()
+    srv = small_server(pm)
+    alone = [srv.wait(srv.submit(**q)) for q in reqs]
+    srv.close()
+    srv = small_server(pm)
+    ids = [srv.submit(**q) for q in reqs]
+    mixed = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    assert st["peak_in_flight"] >= 2, st
+    for a, m in zip(alone, mixed):
+        assert a["action"] >= 0 and a["iterations"] > 0
+        assert same(a, m), (a, m)
+
+
+def test_server_matches_the_single_request_planner(pm):
+    """pmbs_plan on a simulator of the same contact classes gives bitwise the
+    server's result (the server packs scenes by body-table rows and pool
+    slots; the planner replicates one scene)."""
+    q = requests()[1]
+    srv = small_server(pm)
+    got = srv.wait(srv.submit(**q))
+    srv.close()
+    n = q["state"].shape[0]
+    E, D, iters = q["leaves"], 5, q["iterations"]
+    sim = pm.Sim(max_envs=E, max_bodies=E * n, pool_slots=E * iters + 1, pool_stride=n, max_horizon=D,
+                 max_contacts=256)
+    s1 = pm.Sim(max_envs=1, max_bodies=n)
+    s1.set_state([0, n], q["state"], q["body"])
+    r0 = float(s1.eval_reward([0], 0.08)[0][0])
+    tree = pm.Tree(n, r0, n_envs=E, max_depth=D, c=1.4, gamma=0.8, seed=q["seed"], max_nodes=E * iters + 1)
+    ref = pm.plan(sim, tree, q["state"], q["body"], 0, iters, n_substeps=30)
+    for k in KEYS:
+        assert got[k] == ref[k], (k, got[k], ref[k])
+    assert got["push"] == ref["push"]
+
+
+def test_admission_by_footprint(pm):
+    """A budget that holds one request at a time: the second waits for the
+    first to finish, and the results are unchanged."""
+    reqs = requests()[:2]
+    srv = small_server(pm)
+    alone = [srv.wait(srv.submit(**q)) for q in reqs]
+    srv.close()
+    need = max(a["footprint_bytes"] for a in alone)
+    srv = small_server(pm, hbm_budget=need + need // 2)
+    ids = [srv.submit(**q) for q in reqs]
+    res = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    assert st["peak_in_flight"] == 1 and st["peak_held_bytes"] <= need + need // 2
+    # the second request waits while the first runs
+    assert res[1]["queued_seconds"] >= 0.9 * res[0]["seconds"]
+    for a, m in zip(alone, res):
+        assert same(a, m)
+
+
+def test_cancel_and_capacity_errors(pm):
+    reqs = requests()
+    srv = small_server(pm, max_requests=1)
+    a = srv.submit(**dict(reqs[2], iterations=40))
+    b = srv.submit(**reqs[0])
+    srv.cancel(b)
+    rb = srv.wait(b)
+    assert rb["status"] == pm.PMBS_ERR_CANCELLED and rb["iterations"] == 0
+    srv.cancel(a)
+    ra = srv.wait(a)
+    assert ra["status"] == pm.PMBS_ERR_CANCELLED and ra["iterations"] < 40
+    with pytest.raises(pm.PmbsError):
+        srv.submit(**dict(reqs[0], leaves=100000))
+    srv.close()
