@@ -255,6 +255,9 @@ typedef struct pmbs_tree_config {
     int32_t max_nodes;  /* node and pool-slot capacity (65536) */
     int32_t n_dirs;     /* contour directions per object, N_a (8) */
     uint64_t seed;      /* Philox key of action orders and random pushes */
+    int32_t sim_depth;  /* d_s: simulations run to depth max_depth + sim_depth (0) */
+    int32_t early_stop; /* Alg. 1 early-stop level and graspable-node termination with the
+                           dynamic depth of Sec. IV-A (0: off) */
 } pmbs_tree_config;
 
 typedef struct pmbs_tree pmbs_tree_t;
@@ -281,7 +284,8 @@ void pmbs_tree_destroy(pmbs_tree_t* tree);
  * during the phase and reset after it.  The remaining envs replicate the
  * pairs round-robin (leaf parallelisation).  Outputs, host, n_envs entries
  * each: act_offset [n_envs+1] and actions (the pair's action followed by
- * the replica's random pushes down to max_depth, Philox-keyed), src_slot
+ * the replica's random pushes down to the simulation depth d_T + d_s,
+ * Philox-keyed; the actions buffer holds n_envs * (max_depth + sim_depth)), src_slot
  * (the node's pool slot) and child_slot (the new node's slot for the first
  * replica of a pair, else -1).  n_pairs = 0 when nothing is selectable. */
 pmbs_status pmbs_tree_select(pmbs_tree_t* tree, int32_t* n_pairs, int32_t* actions, int32_t* act_offset,
@@ -295,6 +299,17 @@ pmbs_status pmbs_tree_select(pmbs_tree_t* tree, int32_t* n_pairs, int32_t* actio
  * max_t gamma^t r_t (Sec. IV-C, backpropagation). */
 pmbs_status pmbs_tree_update(pmbs_tree_t* tree, const float* rewards, int32_t max_h, const int32_t* counts,
                              const uint32_t* env_status, int32_t* n_children);
+
+/* Alg. 1 (early_stop): a child whose first reward is 1 stands in for a node
+ * the grasp classifier accepts (graspable).  The early-stop level starts at
+ * 1 and rises by one after an update in which every node at depth level-1
+ * is fully expanded (no untried action, or at the depth limit) or
+ * terminal; a graspable child at depth d below the tree depth d_T sets
+ * d_T = d and d_s = 0 (Sec. IV-A).  *done = 1 once a graspable node has
+ * depth <= the level (always 0 without early_stop); d_tree / d_sim /
+ * level (optional) receive the current values. */
+pmbs_status pmbs_tree_status(const pmbs_tree_t* tree, int32_t* done, int32_t* level, int32_t* d_tree,
+                             int32_t* d_sim);
 
 /* The root child with the best average reward Q/N (Sec. III-B); ties to
  * more visits, then the lower action.  action = -1 without children. */
@@ -321,10 +336,39 @@ typedef struct pmbs_plan_result {
  * The scene (root_state SoA [13][n_bodies], body [5][n_bodies], host) is
  * loaded into tree->n_envs environments of sim; sim needs max_envs >=
  * n_envs, max_bodies >= n_envs * n_bodies, pool_slots >= max_nodes,
- * pool_stride >= n_bodies, max_horizon >= max_depth.  Synchronous. */
+ * pool_stride >= n_bodies, max_horizon >= max_depth + sim_depth.  With
+ * early_stop the loop also ends before an iteration once the tree is done
+ * (pmbs_tree_status).  Synchronous. */
 pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_state, const float* body,
                       int32_t n_bodies, int32_t target, int32_t iters, int32_t n_substeps, float width,
                       pmbs_plan_result* out);
+
+/* ------------------------------------------------------------------ */
+/* brute-force search over short push sequences                        */
+typedef struct pmbs_brute_result {
+  int32_t best;          /* index of the best sequence (actions a_0 * A^(depth-1) + ...), -1 if none */
+  int32_t actions[4];    /* its actions (obj * 8 + dir), -1 past its length */
+  double value;          /* its return max_t gamma^t r_t */
+  float rewards[4];      /* its reward after each push (-1 past the pushes applied) */
+  int64_t sequences;     /* sequences simulated */
+  int64_t env_substeps;  /* substeps simulated */
+  double seconds;        /* wall time of the call */
+} pmbs_brute_result;
+
+/* Every sequence of `depth` (1..4) contour pushes (A = 8 n_bodies actions
+ * each, Sec. IV-B) from one scene (root_state SoA [13][n_bodies], body
+ * [5][n_bodies], host), as one env each in queued rollout launches of at
+ * most sim->max_envs envs (rollout rules of pmbs_sim_rollout: a discarded
+ * first push drops the sequence, a reward of 1 stops it).  The best
+ * sequence has the largest return max_t gamma^t r_t, ties to the lower
+ * index.  The scene sits in pool slot 0 and body rows 0..n_bodies-1 of
+ * sim (pool_slots >= 1, pool_stride >= n_bodies, max_horizon >= depth);
+ * the loaded state of sim is replaced.  d_rewards (optional, device,
+ * float [A^depth][depth]) receives every sequence's rewards and d_counts
+ * (optional, device, int32 [A^depth]) their counts.  Synchronous. */
+pmbs_status pmbs_brute_force(pmbs_sim_t* sim, const float* root_state, const float* body, int32_t n_bodies,
+                             int32_t target, int32_t depth, int32_t n_substeps, float width, double gamma,
+                             float* d_rewards, int32_t* d_counts, pmbs_brute_result* out);
 
 /* ------------------------------------------------------------------ */
 /* serving: planning requests with continuous batching                 */
@@ -350,6 +394,7 @@ typedef struct pmbs_server_config {
   double c, gamma;        /* Eq. 2 exploration constant, discount */
   int64_t hbm_budget;     /* bytes of node-pool footprint the requests in flight may hold; 0: the pool */
   int32_t graph;          /* replay the batched launch as a captured graph */
+  int32_t early_stop;     /* Alg. 1 early stop in every request's tree (pmbs_tree_status) */
 } pmbs_server_config;
 
 typedef struct pmbs_request {

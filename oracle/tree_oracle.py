@@ -20,6 +20,14 @@ What it follows in the paper:
   * Depth limit (Sec. IV-A): a node at depth D is not expanded and
     simulations stop at depth D.
   * Final action: the root child with the best average reward (Sec. III-B).
+  * Optional (early_stop): Alg. 1's early-stop level and graspable nodes,
+    and the dynamic depth of Sec. IV-A.  A child whose reward is 1 stands
+    in for a node the grasp classifier accepts.  es_level starts at 1; after
+    each expansion it rises by one when every node at depth es_level - 1 is
+    fully expanded (no untried action, or at the depth limit) or terminal;
+    the search stops before an iteration once a graspable node sits at a
+    depth <= es_level.  A terminal child at depth d < d_T sets d_T = d and
+    the simulation depth d_s = 0.  Simulations run to depth d_T + d_s.
 
 Readings where the paper is silent (listed in the design notes): a node is
 a leaf for Alg. 2 when its depth is below D and it has an untried action,
@@ -62,6 +70,10 @@ def ucb(child: Node, parent: Node, c: float) -> float:
     if n == 0:
         return math.inf
     return child.Q / n + c * math.sqrt(2.0 * math.log(parent.N + parent.Nhat) / n)
+
+
+def fully_expanded(n: Node, depth_limit: int) -> bool:
+    return n.depth >= depth_limit or not n.untried
 
 
 def selectable(n: Node, depth_limit: int) -> bool:
@@ -149,12 +161,30 @@ class Planner:
       root_reward(state) -> float
     """
 
-    def __init__(self, env, root_state, n_envs, c=1.4, gamma=0.8, depth=5, seed=0):
+    def __init__(self, env, root_state, n_envs, c=1.4, gamma=0.8, depth=5, seed=0, sim_depth=0, early_stop=False):
         self.env, self.n_envs, self.c, self.gamma, self.D, self.seed = env, n_envs, c, gamma, depth, seed
+        self.Ds, self.early_stop = sim_depth, early_stop
+        self.es_level = 1
+        self.graspable = []
         self.next_id = 0
         self.root = self._node(None, None, 0, root_state, env.root_reward(root_state))
         self.iterations = 0
         self.simulations = 0
+
+    def done(self) -> bool:
+        """Alg. 1 loop condition (early_stop only): a graspable node at a
+        depth no greater than es_level ends the search."""
+        return self.early_stop and any(g.depth <= self.es_level for g in self.graspable)
+
+    def _nodes_at(self, depth):
+        out, stack = [], [self.root]
+        while stack:
+            n = stack.pop()
+            if n.depth == depth:
+                out.append(n)
+            elif n.depth < depth:
+                stack.extend(n.children)
+        return out
 
     def _node(self, parent, action, depth, state, reward):
         nid = self.next_id
@@ -172,7 +202,8 @@ class Planner:
         for pi, rep in envs:
             n, a = pairs[pi]
             na = self.env.n_actions(n.state)
-            acts = [a] + [rollout_action(n.id, a, rep, t, na, self.seed) for t in range(1, self.D - n.depth)]
+            acts = [a] + [rollout_action(n.id, a, rep, t, na, self.seed)
+                          for t in range(1, self.D + self.Ds - n.depth)]
             results.append(self.env.run(n.state, acts))
         self.simulations += len(envs)
         best_g = {}
@@ -188,13 +219,20 @@ class Planner:
                 continue
             child = self._node(n, a, n.depth + 1, child_state, rewards[0])
             n.children.append(child)
+            if self.early_stop and child.terminal:
+                self.graspable.append(child)
+                if child.depth < self.D:      # dynamic depth (Sec. IV-A)
+                    self.D, self.Ds = child.depth, 0
             backprop(child, best_g[pi], self.gamma)
+        if self.early_stop and all(m.terminal or fully_expanded(m, self.D)
+                                   for m in self._nodes_at(self.es_level - 1)):
+            self.es_level += 1
         self.iterations += 1
         return True
 
     def plan(self, iters: int):
         for _ in range(iters):
-            if not self.iterate():
+            if self.done() or not self.iterate():
                 break
         b = best_action(self.root)
         return (None, None) if b is None else (b.action, b.Q / b.N)

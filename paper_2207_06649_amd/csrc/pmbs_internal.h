@@ -72,6 +72,9 @@ struct pmbs_tree {
   std::vector<int32_t> pair_node, pair_action, pair_slot, env_pair, env_replica;
   bool pending;
   int64_t simulations;
+  // current tree depth d_T and simulation depth d_s (dynamic with early_stop),
+  // Alg. 1 early-stop level, smallest depth of a graspable node
+  int32_t d_tree, d_sim, es_level, grasp_depth;
 };
 
 

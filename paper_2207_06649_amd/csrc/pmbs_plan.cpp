@@ -49,7 +49,7 @@ pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_stat
   const auto t0 = std::chrono::steady_clock::now();
   const pmbs_tree_config& tc = tree->cfg;
   const pmbs_sim_config& sc = sim->cfg;
-  const int E = tc.n_envs, D = tc.max_depth, n = n_bodies;
+  const int E = tc.n_envs, D = tc.max_depth + tc.sim_depth, n = n_bodies;
   if (n < 1 || n > PMBS_MAX_BODIES_PER_ENV || target < 0 || target >= n)
     return fail(PMBS_ERR_INVALID_ARG, "bad scene size or target");
   if (tree->n_actions != n * tc.n_dirs || tc.n_dirs != 8)
@@ -79,6 +79,9 @@ pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_stat
   int it = 0;
   int64_t env_substeps = 0;
   for (; it < iters; ++it) {
+    int32_t done = 0;
+    if ((s = pmbs_tree_status(tree, &done, nullptr, nullptr, nullptr)) != PMBS_OK) return s;
+    if (done) break;
     int32_t n_pairs = 0, n_envs = 0;
     if ((s = pmbs_tree_select(tree, &n_pairs, actions.data(), act_off.data(), src.data(), child.data(), &n_envs)) !=
         PMBS_OK)

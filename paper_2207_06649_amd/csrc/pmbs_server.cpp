@@ -251,6 +251,7 @@ pmbs_status pmbs_server::start_requests(const std::vector<Request*>& fresh) {
     tc.max_nodes = r->max_nodes;
     tc.n_dirs = 8;
     tc.seed = r->seed;
+    tc.early_stop = cfg.early_stop;
     if ((s = pmbs_tree_create(&tc, r->nb, root_r[i], &r->tree)) != PMBS_OK) return s;
   }
   return PMBS_OK;
@@ -273,7 +274,10 @@ pmbs_status pmbs_server::pass() {
       std::lock_guard<std::mutex> lk(mu);
       cancel = r->cancel;
     }
-    if (cancel || r->iter >= r->iterations) {
+    int32_t tree_done = 0;
+    pmbs_status ts = pmbs_tree_status(r->tree, &tree_done, nullptr, nullptr, nullptr);
+    if (ts != PMBS_OK) return ts;
+    if (cancel || r->iter >= r->iterations || tree_done) {
       done_now.push_back(r);
       continue;
     }

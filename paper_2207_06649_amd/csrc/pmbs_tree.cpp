@@ -2,6 +2,8 @@
 // device (Sec. IV-C of the paper: selection with virtual loss, Eq. 2 and
 // Alg. 2; batch expansion; batch simulation with leaf parallelisation;
 // backpropagation keeping the maximum over repeated simulations).
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -78,7 +80,7 @@ static int32_t add_node(pmbs_tree_t* t, int32_t parent, int32_t action, int32_t 
   n.Nhat = 0;
   shuffled(t->n_actions, n.id, t->cfg.seed, &n.untried);
   n.next_untried = 0;
-  n.sel = !n.terminal && n.expandable(t->cfg.max_depth);
+  n.sel = !n.terminal && n.expandable(t->d_tree);
   t->nodes.push_back(std::move(n));
   return t->nodes.back().id;
 }
@@ -87,7 +89,7 @@ static int32_t add_node(pmbs_tree_t* t, int32_t parent, int32_t action, int32_t 
 static void refresh_sel(pmbs_tree_t* t, int32_t id) {
   while (id >= 0) {
     Node& n = t->nodes[id];
-    bool s = !n.terminal && n.expandable(t->cfg.max_depth);
+    bool s = !n.terminal && n.expandable(t->d_tree);
     if (!s && !n.terminal)
       for (int32_t c : n.children)
         if (t->nodes[c].sel) {
@@ -132,8 +134,13 @@ pmbs_status pmbs_tree_create(const pmbs_tree_config* cfg, int32_t n_objects, flo
     return fail(PMBS_ERR_INVALID_ARG, "bad tree config");
   pmbs_tree* t = new (std::nothrow) pmbs_tree();
   if (!t) return fail(PMBS_ERR_INVALID_ARG, "out of host memory");
+  if (cfg->sim_depth < 0 || cfg->max_depth + cfg->sim_depth > 64) return fail(PMBS_ERR_INVALID_ARG, "bad sim_depth");
   t->cfg = *cfg;
   t->n_actions = n_objects * cfg->n_dirs;
+  t->d_tree = cfg->max_depth;
+  t->d_sim = cfg->sim_depth;
+  t->es_level = 1;
+  t->grasp_depth = INT32_MAX;
   t->nodes.reserve(1024);
   add_node(t, -1, -1, 0, 0, root_reward);
   t->next_slot = 1;
@@ -149,7 +156,7 @@ pmbs_status pmbs_tree_select(pmbs_tree_t* t, int32_t* n_pairs, int32_t* actions,
                              int32_t* child_slot, int32_t* n_envs) {
   if (!t || !n_pairs || !actions || !act_offset || !src_slot || !child_slot || !n_envs)
     return fail(PMBS_ERR_INVALID_ARG, "null argument");
-  const int E = t->cfg.n_envs, D = t->cfg.max_depth;
+  const int E = t->cfg.n_envs, D = t->d_tree, H = t->d_tree + t->d_sim;
   t->pair_node.clear();
   t->pair_action.clear();
   t->pair_slot.clear();
@@ -205,7 +212,7 @@ pmbs_status pmbs_tree_select(pmbs_tree_t* t, int32_t* n_pairs, int32_t* actions,
     t->env_replica[e] = r;
     const Node& n = t->nodes[t->pair_node[p]];
     actions[k++] = t->pair_action[p];
-    for (int tt = 1; tt < D - n.depth; ++tt)
+    for (int tt = 1; tt < H - n.depth; ++tt)
       actions[k++] = rollout_action(n.id, t->pair_action[p], r, tt, t->n_actions, t->cfg.seed);
     act_offset[e + 1] = k;
     src_slot[e] = n.slot;
@@ -242,6 +249,28 @@ pmbs_status pmbs_tree_update(pmbs_tree_t* t, const float* rewards, int32_t max_h
                                    rewards[(size_t)e * max_h]);
     t->nodes[par].children.push_back(child);
     refresh_sel(t, child);
+    if (t->cfg.early_stop && t->nodes[child].terminal) {
+      const int32_t d = t->nodes[child].depth;
+      t->grasp_depth = std::min(t->grasp_depth, d);
+      if (d < t->d_tree) {
+        // dynamic depth (Sec. IV-A): nodes at depth >= d are no longer
+        // expandable, so every cached selectability is recomputed
+        // (children have larger ids than their parents)
+        t->d_tree = d;
+        t->d_sim = 0;
+        for (int32_t id = (int32_t)t->nodes.size() - 1; id >= 0; --id) {
+          Node& m = t->nodes[id];
+          bool sel = !m.terminal && m.expandable(t->d_tree);
+          if (!sel && !m.terminal)
+            for (int32_t c : m.children)
+              if (t->nodes[c].sel) {
+                sel = true;
+                break;
+              }
+          m.sel = sel;
+        }
+      }
+    }
     double G = best[p];
     int j = 0;
     for (int32_t m = child; m >= 0; m = t->nodes[m].parent, ++j) {
@@ -253,6 +282,17 @@ pmbs_status pmbs_tree_update(pmbs_tree_t* t, const float* rewards, int32_t max_h
   t->next_slot += P;
   t->simulations += E;
   t->pending = false;
+  if (t->cfg.early_stop) {
+    // Alg. 1: raise the early-stop level once every node at depth level-1
+    // is fully expanded or terminal
+    bool all_done = true;
+    for (const Node& m : t->nodes)
+      if (m.depth == t->es_level - 1 && !m.terminal && m.expandable(t->d_tree)) {
+        all_done = false;
+        break;
+      }
+    if (all_done) t->es_level += 1;
+  }
   if (n_children) *n_children = made;
   return PMBS_OK;
 }
@@ -280,6 +320,15 @@ pmbs_status pmbs_tree_best(const pmbs_tree_t* t, int32_t* action, double* value,
   *action = t->nodes[best].action;
   if (value) *value = t->nodes[best].Q / (double)t->nodes[best].N;
   if (visits) *visits = t->nodes[best].N;
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_tree_status(const pmbs_tree_t* t, int32_t* done, int32_t* level, int32_t* d_tree, int32_t* d_sim) {
+  if (!t || !done) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  *done = t->cfg.early_stop && t->grasp_depth <= t->es_level ? 1 : 0;
+  if (level) *level = t->es_level;
+  if (d_tree) *d_tree = t->d_tree;
+  if (d_sim) *d_sim = t->d_sim;
   return PMBS_OK;
 }
 

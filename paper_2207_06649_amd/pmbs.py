@@ -320,7 +320,8 @@ class Sim:
 # ---------------------------------------------------------------- tree / plan
 class TreeConfig(C.Structure):
     _fields_ = [("c", C.c_double), ("gamma", C.c_double), ("max_depth", C.c_int32), ("n_envs", C.c_int32),
-                ("max_nodes", C.c_int32), ("n_dirs", C.c_int32), ("seed", C.c_uint64)]
+                ("max_nodes", C.c_int32), ("n_dirs", C.c_int32), ("seed", C.c_uint64), ("sim_depth", C.c_int32),
+                ("early_stop", C.c_int32)]
 
 
 class NodeInfo(C.Structure):
@@ -349,6 +350,7 @@ def _tree_lib():
         L.pmbs_tree_best.argtypes = [vp, vp, vp, vp]
         L.pmbs_tree_node.argtypes = [vp, C.c_int32, C.POINTER(NodeInfo)]
         L.pmbs_tree_size.argtypes = [vp, vp, vp, vp]
+        L.pmbs_tree_status.argtypes = [vp, vp, vp, vp, vp]
         L.pmbs_plan.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_float,
                                 C.POINTER(PlanResult)]
         L._tree_ready = True
@@ -377,7 +379,7 @@ class Tree:
         h = C.c_void_p()
         _check(L.pmbs_tree_create(C.byref(self.cfg), int(n_objects), float(root_reward), C.byref(h)))
         self.handle = h
-        E, D = self.cfg.n_envs, self.cfg.max_depth
+        E, D = self.cfg.n_envs, self.cfg.max_depth + self.cfg.sim_depth
         self._acts = np.zeros(E * D, np.int32)
         self._off = np.zeros(E + 1, np.int32)
         self._src = np.zeros(E, np.int32)
@@ -418,6 +420,12 @@ class Tree:
         _check(_tree_lib().pmbs_tree_node(self.handle, int(i), C.byref(info)))
         return {k: getattr(info, k) for k, _ in NodeInfo._fields_}
 
+    def status(self) -> dict:
+        """Alg. 1 early-stop state: done, level, current d_T and d_s."""
+        d, lv, dt, ds = (C.c_int32(0) for _ in range(4))
+        _check(_tree_lib().pmbs_tree_status(self.handle, C.byref(d), C.byref(lv), C.byref(dt), C.byref(ds)))
+        return dict(done=bool(d.value), level=lv.value, d_tree=dt.value, d_sim=ds.value)
+
     def size(self):
         n, s, p = C.c_int32(0), C.c_int64(0), C.c_int32(0)
         _check(_tree_lib().pmbs_tree_size(self.handle, C.byref(n), C.byref(s), C.byref(p)))
@@ -437,12 +445,42 @@ def plan(sim: "Sim", tree: Tree, state, body, target: int, iters: int, n_substep
     return out
 
 
+# ---------------------------------------------------------------- brute force
+class BruteResult(C.Structure):
+    _fields_ = [("best", C.c_int32), ("actions", C.c_int32 * 4), ("value", C.c_double), ("rewards", C.c_float * 4),
+                ("sequences", C.c_int64), ("env_substeps", C.c_int64), ("seconds", C.c_double)]
+
+
+def brute_force(sim: "Sim", state, body, target: int, depth: int, n_substeps: int = 120, width: float = 0.08,
+                gamma: float = 0.8, rewards=None, counts=None) -> dict:
+    """Every sequence of `depth` contour pushes from one scene (state [n,13],
+    body [n,5]); rewards / counts: optional device tensors [A^depth, depth] /
+    [A^depth] for every sequence's rewards."""
+    L = _tree_lib()
+    if not getattr(L, "_brute_ready", False):
+        vp = C.c_void_p
+        L.pmbs_brute_force.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_double,
+                                       vp, vp, C.POINTER(BruteResult)]
+        L._brute_ready = True
+    st = soa(state, 13)
+    bd = soa(body, 5)
+    res = BruteResult()
+    _check(L.pmbs_brute_force(sim.handle, _np_ptr(st), _np_ptr(bd), st.shape[1], int(target), int(depth),
+                              int(n_substeps), float(width), float(gamma),
+                              None if rewards is None else _ptr(rewards), None if counts is None else _ptr(counts),
+                              C.byref(res)))
+    out = {k: getattr(res, k) for k, _ in BruteResult._fields_}
+    out["actions"] = list(res.actions)[:depth]
+    out["rewards"] = list(res.rewards)[:depth]
+    return out
+
+
 # ---------------------------------------------------------------- serving
 class ServerConfig(C.Structure):
     _fields_ = [("sim", SimConfig), ("max_envs", C.c_int32), ("max_requests", C.c_int32),
                 ("pool_slots", C.c_int32), ("max_depth", C.c_int32), ("n_substeps", C.c_int32),
                 ("width", C.c_float), ("c", C.c_double), ("gamma", C.c_double), ("hbm_budget", C.c_int64),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("early_stop", C.c_int32)]
 
 
 class Request(C.Structure):

@@ -29,16 +29,31 @@ def make_sim(pm, n_envs, n_bodies, max_nodes, depth):
                   max_horizon=max(depth, 1))
 
 
-@pytest.mark.parametrize("seed,n_envs,depth,iters", [(3, 12, 2, 2), (5, 24, 3, 3)])
-def test_plan_matches_oracle_planner(pm, seed, n_envs, depth, iters):
-    b = scenes.retrieval_scene(seed, n_others=6, region=0.25)
-    n = len(b.body)
-    st, bd = f32(b.state), f32(b.body)
+def near_clear_scene():
+    """A target with one cube 5 cm away and one far away: pushing the near
+    cube away clears the target (reward 1) within two 60-substep pushes."""
+    st, bd = np.zeros((3, 13)), np.zeros((3, 5))
+    for i, (x, y) in enumerate([(0.0, 0.0), (0.09, 0.0), (-0.2, 0.03)]):
+        st[i, :3] = (x, y, 0.02)
+        st[i, 3] = 1.0
+        bd[i] = (0.02, 0.02, 0.02, 0.1, 0.5)
+    return st, bd
+
+
+@pytest.mark.parametrize("seed,n_envs,depth,iters,early", [(3, 12, 2, 2, 0), (5, 24, 3, 3, 0), (1, 24, 3, 6, 1)])
+def test_plan_matches_oracle_planner(pm, seed, n_envs, depth, iters, early):
+    if early:
+        st, bd = (f32(a) for a in near_clear_scene())
+    else:
+        b = scenes.retrieval_scene(seed, n_others=6, region=0.25)
+        st, bd = f32(b.state), f32(b.body)
+    n = len(bd)
     sim = make_sim(pm, n_envs, n, 4096, depth)
-    tree = pm.Tree(n, O.reward(st, bd, 0, 0.08), n_envs=n_envs, max_depth=depth, seed=seed, max_nodes=4096)
+    tree = pm.Tree(n, O.reward(st, bd, 0, 0.08), n_envs=n_envs, max_depth=depth, seed=seed, max_nodes=4096,
+                   early_stop=early)
     res = pm.plan(sim, tree, st, bd, 0, iters, n_substeps=60)
     env = T.PhysicsEnv(O.make_config(), bd, target=0, substeps=60)
-    p = T.Planner(env, st, n_envs=n_envs, depth=depth, seed=seed)
+    p = T.Planner(env, st, n_envs=n_envs, depth=depth, seed=seed, early_stop=bool(early))
     a_ref, v_ref = p.plan(iters)
     nodes = []
     stack = [p.root]
@@ -58,7 +73,11 @@ def test_plan_matches_oracle_planner(pm, seed, n_envs, depth, iters):
         assert abs(info["Q"] - nd.Q) < 1e-3 * max(1, nd.N)
     assert res["action"] == a_ref
     assert abs(res["value"] - v_ref) < 1e-3
-    assert res["iterations"] == iters and res["simulations"] == n_envs * iters
+    assert res["iterations"] == p.iterations and res["simulations"] == n_envs * p.iterations
+    if early:
+        st_ = tree.status()
+        assert p.done() and p.iterations < iters   # the case does stop early
+        assert st_["done"] == p.done() and st_["level"] == p.es_level and st_["d_tree"] == p.D
     # the returned push is the contour push of the chosen action from the root state
     want = O.contour_push(O.make_config(), st[a_ref // 8], bd[a_ref // 8], a_ref % 8, 8)
     assert np.abs(np.array(res["push"]) - want).max() < 1e-5

@@ -230,3 +230,38 @@ def test_physics_planner_small_retrieval_scene():
         assert valid[0] == 1
         assert np.array_equal(st, ch.state)
         assert ch.reward == O.reward(st, b.body, 0, 0.08)
+
+
+def test_early_stop_graspable_child_of_the_root():
+    """Alg. 1 worked by hand: 4 root actions in one batch, action 2 reaches
+    reward 1.  After the first iteration the root is fully expanded
+    (es_level 1 -> 2) and a graspable node sits at depth 1 <= 2: the search
+    stops after one iteration; the terminal child at depth 1 < d_T = 3 sets
+    d_T = 1 and d_s = 0 (Sec. IV-A); the final action is 2."""
+    env = ToyEnv(k=4, lock=(2,))
+    p = T.Planner(env, (), n_envs=4, depth=3, seed=0, sim_depth=1, early_stop=True)
+    a, v = p.plan(10)
+    assert p.iterations == 1 and p.done()
+    assert p.es_level == 2 and (p.D, p.Ds) == (1, 0)
+    assert a == 2 and v == 1.0
+    q = T.Planner(ToyEnv(k=4, lock=(2,)), (), n_envs=4, depth=3, seed=0, sim_depth=1, early_stop=False)
+    q.plan(3)
+    assert q.iterations == 3 and (q.D, q.Ds) == (3, 1)
+
+
+def test_early_stop_waits_for_the_level_of_a_deeper_graspable_node():
+    """A graspable node at depth 2 ends the search only once es_level >= 2,
+    i.e. once the root is fully expanded; the search stops at the first
+    iteration boundary where both hold, never earlier."""
+    def run(iters):
+        p = T.Planner(ToyEnv(k=3, lock=(1, 2)), (), n_envs=1, depth=3, seed=4, early_stop=True)
+        p.plan(iters)
+        return p
+
+    p = run(100)
+    assert p.done()
+    assert not p.root.untried and p.es_level >= 2
+    assert min(g.depth for g in p.graspable) == 2 and p.D == 2
+    before = run(p.iterations - 1)
+    assert not before.done()
+    assert before.root.untried or not any(g.depth <= before.es_level for g in before.graspable)

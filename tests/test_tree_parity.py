@@ -40,10 +40,12 @@ def run_library_tree(env, n_objects, n_dirs, iters, **cfg):
     hist = {0: ()}
     trace = []
     for _ in range(iters):
+        if tree.status()["done"]:
+            break
         sel = tree.select()
         if sel["n_pairs"] == 0:
             break
-        E, D = sel["n_envs"], cfg["max_depth"]
+        E, D = sel["n_envs"], cfg["max_depth"] + cfg.get("sim_depth", 0)
         rewards = np.zeros((E, D), np.float32)
         counts = np.zeros(E, np.int32)
         status = np.zeros(E, np.uint32)
@@ -65,9 +67,9 @@ def run_library_tree(env, n_objects, n_dirs, iters, **cfg):
 
 def run_oracle_tree(env, iters, **cfg):
     p = T.Planner(env, (), n_envs=cfg["n_envs"], c=cfg["c"], gamma=cfg["gamma"], depth=cfg["max_depth"],
-                  seed=cfg["seed"])
+                  seed=cfg["seed"], sim_depth=cfg.get("sim_depth", 0), early_stop=bool(cfg.get("early_stop", 0)))
     for _ in range(iters):
-        if not p.iterate():
+        if p.done() or not p.iterate():
             break
     return p
 
@@ -81,11 +83,14 @@ def oracle_nodes(p):
     return sorted(out, key=lambda n: n.id)
 
 
-@pytest.mark.parametrize("n_envs,depth,iters,seed", [(1, 4, 30, 7), (4, 3, 12, 1), (16, 4, 8, 3), (64, 5, 5, 9)])
-def test_library_tree_matches_oracle(n_envs, depth, iters, seed):
+@pytest.mark.parametrize("n_envs,depth,iters,seed,extra", [
+    (1, 4, 30, 7, {}), (4, 3, 12, 1, {}), (16, 4, 8, 3, {}), (64, 5, 5, 9, {}),
+    (4, 3, 12, 1, dict(sim_depth=2)), (1, 4, 40, 7, dict(early_stop=1)), (8, 5, 20, 2, dict(early_stop=1)),
+    (16, 4, 20, 5, dict(early_stop=1, sim_depth=1))])
+def test_library_tree_matches_oracle(n_envs, depth, iters, seed, extra):
     base = lambda h: 0.03 * ((sum(h) * 7 + len(h)) % 9)
     env = Toy(k=6, lock=(5, 0, 3), base=base, invalid={2})
-    cfg = dict(n_envs=n_envs, max_depth=depth, c=1.4, gamma=0.8, seed=seed, max_nodes=100000)
+    cfg = dict(n_envs=n_envs, max_depth=depth, c=1.4, gamma=0.8, seed=seed, max_nodes=100000, **extra)
     tree, hist, _ = run_library_tree(env, 3, 2, iters, **cfg)     # 3 objects x 2 dirs = 6 actions
     p = run_oracle_tree(env, iters, **cfg)
     nodes = oracle_nodes(p)
@@ -102,6 +107,8 @@ def test_library_tree_matches_oracle(n_envs, depth, iters, seed):
     a, v, visits = tree.best()
     b = T.best_action(p.root)
     assert a == b.action and v == b.Q / b.N and visits == b.N
+    st = tree.status()
+    assert st["done"] == p.done() and st["level"] == p.es_level and st["d_tree"] == p.D and st["d_sim"] == p.Ds
 
 
 def test_library_selection_unique_pairs_and_fill():
