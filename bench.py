@@ -168,7 +168,7 @@ def plain_per_push(sim, acts, off, tgt, n_substeps, width=0.08, rewards=None, co
     ended = np.zeros(E, bool)
     for t in range(H):
         go = (~ended) & (t < h)
-        a1 = acts[off[:-1] + t][go] if go.any() else np.zeros(0, np.int32)
+        a1 = acts[(off[:-1] + t)[go]] if go.any() else np.zeros(0, np.int32)
         o1 = np.zeros(E + 1, np.int32)
         o1[1:] = np.cumsum(go)
         r1, c1 = sim.rollout(a1, o1, tgt, n_substeps=n_substeps, width=width, max_h=1,

@@ -764,14 +764,24 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       if (lane < n_obj) s.sorted[rank] = lane;
     }
     wave_sync();
-    if (lane < n_obj) {
-      int i = s.sorted[lane] & (MAXB - 1);
-      float hix = s.hi[0][i], loy = s.lo[1][i], hiy = s.hi[1][i], loz = s.lo[2][i], hiz = s.hi[2][i];
-      for (int q = lane + 1; q < n_obj; ++q) {
-        int j = s.sorted[q] & (MAXB - 1);
-        if (s.lo[0][j] > hix) break;
-        if (loy <= s.hi[1][j] && s.lo[1][j] <= hiy && loz <= s.hi[2][j] && s.lo[2][j] <= hiz) {
-          int lo_i = i < j ? i : j, hi_i = i < j ? j : i;
+    {
+      // sweep: lane r holds the box at sorted position r and compares it with
+      // the boxes d = 1, 2, ... positions later (shuffled down) until every
+      // lane has passed its box's max-x
+      const bool in = lane < n_obj;
+      const int oi = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
+      const float lox = in ? s.lo[0][oi] : INFINITY, hix = in ? s.hi[0][oi] : -INFINITY;
+      const float loy = in ? s.lo[1][oi] : 0.0f, hiy = in ? s.hi[1][oi] : 0.0f;
+      const float loz = in ? s.lo[2][oi] : 0.0f, hiz = in ? s.hi[2][oi] : 0.0f;
+      for (int d = 1; d < n_obj; ++d) {
+        const float lox_q = __shfl_down(lox, d, 64);
+        const bool go = lane + d < n_obj && lox_q <= hix;
+        if (__ballot(go) == 0ull) break;
+        const float loy_q = __shfl_down(loy, d, 64), hiy_q = __shfl_down(hiy, d, 64);
+        const float loz_q = __shfl_down(loz, d, 64), hiz_q = __shfl_down(hiz, d, 64);
+        const int oj = __shfl_down(oi, d, 64);
+        if (go && loy <= hiy_q && loy_q <= hiy && loz <= hiz_q && loz_q <= hiz) {
+          const int lo_i = oi < oj ? oi : oj, hi_i = oi < oj ? oj : oi;
           atomicOr(&s.mask[lo_i], 1u << hi_i);
         }
       }
@@ -980,6 +990,13 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       iw_d = mk(ia.x, ia.y, ia.z);
       iw_o = mk(ia.w, ib.x, ib.y);
     }
+    // the first 8 incidences of each body stay in registers for the whole
+    // solve (16 bits each), so their impulse loads need no index load first
+    unsigned inc_reg[4] = {0u, 0u, 0u, 0u};
+    const int n_reg = inc_count < 8 ? inc_count : 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < n_reg) inc_reg[k >> 1] |= (unsigned)s.inc[inc_start + k] << (16 * (k & 1));
     // it = -1 applies the warm-start impulses; it >= 0 are the Jacobi iterations
     wave_sync();
     for (int it = -1; it < p.iters; ++it) {
@@ -1030,7 +1047,26 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         // LDS loads are in flight together
         f3 acc = mk(0, 0, 0);
         const int sel0 = part == 0 ? 0 : 1;
-        int k = 0;
+#pragma unroll
+        for (int k0 = 0; k0 < 8; k0 += 4) {
+          if (k0 < n_reg) {
+            float4 val[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int en = (int)((inc_reg[(k0 + u) >> 1] >> (16 * (u & 1))) & 0xffffu);
+              val[u] = s.u.imp[part == 0 ? 0 : sel0 + (en & 1)][en >> 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (k0 + u < n_reg) {
+                const int en = (int)((inc_reg[(k0 + u) >> 1] >> (16 * (u & 1))) & 0xffffu);
+                const float sg = (en & 1) ? 1.0f : -1.0f;
+                acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
+              }
+            }
+          }
+        }
+        int k = n_reg;
         for (; k + 4 <= inc_count; k += 4) {
           int en[4];
           float4 val[4];

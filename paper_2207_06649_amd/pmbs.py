@@ -276,8 +276,8 @@ class Sim:
         replayed only while its output pointers stay the same)."""
         t = self.torch
         off, acts, tg, mh, ss, cs = self._rollout_inputs(actions, act_offset, target, src_slot, child_slot, max_h)
-        rew = rewards if rewards is not None else t.empty((self.n_envs, mh), dtype=t.float32, device=self.device)
-        cnt = counts if counts is not None else t.empty(self.n_envs, dtype=t.int32, device=self.device)
+        rew = rewards if rewards is not None else t.full((self.n_envs, mh), -1.0, dtype=t.float32, device=self.device)
+        cnt = counts if counts is not None else t.zeros(self.n_envs, dtype=t.int32, device=self.device)
         if tuple(rew.shape) != (self.n_envs, mh) or rew.dtype != t.float32 or cnt.numel() < self.n_envs:
             raise PmbsError("rewards must be float32 [n_envs, max_h] and counts int32 [n_envs]")
         ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None

@@ -30,13 +30,18 @@ def make_sim(pm, n_envs, n_bodies, max_nodes, depth):
 
 
 def near_clear_scene():
-    """A target with one cube 5 cm away and one far away: pushing the near
-    cube away clears the target (reward 1) within two 60-substep pushes."""
+    """A target with one cuboid about 5 cm away and one far away: pushing the
+    near one away clears the target (reward 1) within two 60-substep pushes.
+    Sizes, masses and yaws differ so that no two different pushes give equal
+    rewards by symmetry (an exact tie in FP64 that FP32 would break)."""
+    import math
     st, bd = np.zeros((3, 13)), np.zeros((3, 5))
-    for i, (x, y) in enumerate([(0.0, 0.0), (0.09, 0.0), (-0.2, 0.03)]):
-        st[i, :3] = (x, y, 0.02)
-        st[i, 3] = 1.0
-        bd[i] = (0.02, 0.02, 0.02, 0.1, 0.5)
+    spec = [((0.0, 0.0), 0.03, (0.02, 0.02, 0.02), 0.1), ((0.09, 0.006), -0.07, (0.018, 0.021, 0.02), 0.13),
+            ((-0.2, 0.03), 0.4, (0.02, 0.015, 0.02), 0.08)]
+    for i, ((x, y), yaw, h, m) in enumerate(spec):
+        st[i, :3] = (x, y, h[2])
+        st[i, 3], st[i, 6] = math.cos(yaw / 2), math.sin(yaw / 2)
+        bd[i] = (*h, m, 0.5)
     return st, bd
 
 
