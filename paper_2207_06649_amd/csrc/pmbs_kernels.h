@@ -13,6 +13,7 @@ struct Params {
   float phx, phy, phz, pusher_z, push_speed;
   float tau_face, tau_edge, edge_eps;
   float push_length, push_standoff;
+  float inv_dt;
   int iters, n_dirs;
 };
 

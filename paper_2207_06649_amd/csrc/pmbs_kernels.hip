@@ -32,7 +32,7 @@ constexpr int MAXB = 32;             // boxes (<= 31) + the pusher
 constexpr int PLANE = MAXB;          // LDS index of the table
 constexpr int NOBJ = MAXB + 1;
 constexpr int MAX_PAIRS = MAXB * (MAXB - 1) / 2;
-constexpr int CLIP_LANES = 16;       // pair lanes per narrowphase round
+constexpr int CLIP_GROUPS = 8;       // pairs per narrowphase pass (8-lane groups)
 constexpr int POLY = 8;              // clip polygon capacity
 
 // ------------------------------------------------------------------ vectors
@@ -47,6 +47,7 @@ __device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y 
 __device__ __forceinline__ f3 cross(f3 a, f3 b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
+__device__ __forceinline__ float sel(bool c, float a, float b) { return c ? a : b; }
 __device__ __forceinline__ f3 xyz(float4 v) { return {v.x, v.y, v.z}; }
 __device__ __forceinline__ float4 f4(f3 v, float w) { return make_float4(v.x, v.y, v.z, w); }
 __device__ __forceinline__ float comp(f3 v, int k) {
@@ -89,6 +90,11 @@ __device__ __forceinline__ int wave_excl_scan_bits(int x, int bits, int* total) 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
 // ------------------------------------------------------------------ LDS layout
+// Hardware reciprocal and reciprocal square root (about 1 ulp), used where
+// a correctly rounded divide or square root would cost ten instructions.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 template <int K>
 struct Smem {
   static constexpr int C = 64 * K;
@@ -112,7 +118,10 @@ struct Smem {
     float4 stage[C][2];              // narrowphase output: (p, sep), (n, -)
     float4 imp[3][C];                // solver exchange: P, ra x P, rb x P
   } u;
-  float clip[2][POLY][3][CLIP_LANES];
+  union {
+    float clip[2][POLY][3][CLIP_GROUPS]; // narrowphase: clip polygons of the eight groups
+    unsigned incm[NOBJ][2 * K];          // incidence build: contact bit masks per body
+  } x;
 };
 
 // Contact key (a+1, b, feature) with the table as a = -1: strictly
@@ -191,114 +200,89 @@ __device__ __forceinline__ float sat_max(const Smem<K>& s, int ia, int ib, float
   return best;
 }
 
-struct SatResult {
-  float s;
-  int idx;  // -1: separated beyond the margin
-  f3 L;
-};
+// Row broadcast: every lane of a 16-lane row receives lane k of its row.
+template <int k>
+__device__ __forceinline__ int row_bcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + k, 0xf, 0xf, false);
+}
 
-// contact axis: early out when any s > margin; the kept axis starts at the
-// first candidate and is replaced only when s exceeds it by tau (face) or
-// tau_edge (edge axes).  Both boxes sit in registers; the 15 candidates are
-// unrolled so every axis index is static.
-template <int K>
-__device__ __forceinline__ SatResult sat_best(const Smem<K>& s, int ia, int ib, const Params& p) {
-  const Box A = load_box(s, ia), B = load_box(s, ib);
-  SatResult r;
-  r.s = -INFINITY;
-  r.idx = -1;
-  r.L = mk(0, 0, 0);
-  const f3 d = B.c - A.c;
-  int best = -1;
-  bool out = false;
-#pragma unroll
-  for (int idx = 0; idx < 15; ++idx) {
-    f3 L;
-    bool ok = true;
-    if (idx < 3) {
-      L = axis(A, idx);
-    } else if (idx < 6) {
-      L = axis(B, idx - 3);
-    } else {
-      const f3 v = cross(axis(A, (idx - 6) / 3), axis(B, (idx - 6) % 3));
-      const float len = sqrtf(dot(v, v));
-      ok = len >= p.edge_eps;
-      L = v * (1.0f / len);
-    }
-    if (ok && !out) {
-      const float sv = fabsf(dot(d, L)) - radius_along(A, L) - radius_along(B, L);
-      if (sv > p.margin) out = true;
-      const float tau = idx < 6 ? p.tau_face : p.tau_edge;
-      if (!out && (best < 0 || sv > r.s + tau)) {
-        r.s = sv;
-        best = idx;
-        r.L = L;
-      }
-    }
+// Candidate k of an 8-lane group: held by lane k mod 8 of the group, in its
+// first value for k < 8 and its second for k >= 8.  Lane `hi` groups are the
+// upper halves of their rows.
+template <int k>
+__device__ __forceinline__ void sat_scan_step(float sv0, float sv1, int ok0, int ok1, bool hi, float tau_face,
+                                              float tau_edge, float* bs, int* best) {
+  const int sv = __float_as_int(k < 8 ? sv0 : sv1), ok = k < 8 ? ok0 : ok1;
+  const float sk = __int_as_float(hi ? row_bcast<8 + (k & 7)>(sv) : row_bcast<k & 7>(sv));
+  const int okk = hi ? row_bcast<8 + (k & 7)>(ok) : row_bcast<k & 7>(ok);
+  const float tau = k < 6 ? tau_face : tau_edge;
+  if (okk && (*best < 0 || sk > *bs + tau)) {
+    *bs = sk;
+    *best = k;
   }
-  r.idx = out ? -1 : best;
-  return r;
+}
+
+// Contact axis of a pair from its 15 candidates (0-2 faces of A, 3-5 faces
+// of B, 6-14 edge crosses) held by the 8 lanes of a group: the kept axis
+// starts at the first valid candidate and is replaced only when a later one
+// exceeds it by tau (face) or tau_edge (edge axes).
+__device__ __forceinline__ void sat_scan8(float sv0, float sv1, int ok0, int ok1, bool hi, float tf, float te,
+                                          float* bs, int* best) {
+  sat_scan_step<0>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<1>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<2>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<3>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<4>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<5>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<6>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<7>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<8>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<9>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<10>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<11>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<12>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<13>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+  sat_scan_step<14>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
 }
 
 // ------------------------------------------------------------------ clipping
 template <int K>
-__device__ __forceinline__ f3 cl_get(const Smem<K>& s, int buf, int i, int lane) {
-  return mk(s.clip[buf][i][0][lane], s.clip[buf][i][1][lane], s.clip[buf][i][2][lane]);
+__device__ __forceinline__ f3 cl_get(const Smem<K>& s, int buf, int i, int grp) {
+  return mk(s.x.clip[buf][i][0][grp], s.x.clip[buf][i][1][grp], s.x.clip[buf][i][2][grp]);
 }
 template <int K>
-__device__ __forceinline__ void cl_put(Smem<K>& s, int buf, int i, int lane, f3 v) {
-  s.clip[buf][i][0][lane] = v.x;
-  s.clip[buf][i][1][lane] = v.y;
-  s.clip[buf][i][2][lane] = v.z;
+__device__ __forceinline__ void cl_put(Smem<K>& s, int buf, int i, int grp, f3 v) {
+  s.x.clip[buf][i][0][grp] = v.x;
+  s.x.clip[buf][i][1][grp] = v.y;
+  s.x.clip[buf][i][2][grp] = v.z;
 }
 
-// Sutherland-Hodgman against sign * ((x - f).dir) - h <= 0, from buffer
-// `src` (n points) into `dst`; at most POLY points are kept.  The input
-// polygon is read into registers once (static slots), outputs go to LDS.
+// One Sutherland-Hodgman stage against sign * ((x - f).dir) - h <= 0 for
+// the polygons of all eight groups at once, point i of a group's polygon
+// in lane i of the group.  Lane i handles the edge from point i-1 (the last
+// point for i = 0) to point i: it emits the crossing point if the edge
+// crosses the plane, then point i if inside, at its rank among the group's
+// emissions; at most POLY points are kept.  Called by the whole wave.
 template <int K>
-__device__ __forceinline__ int clip_stage(Smem<K>& s, int src, int n, int dst, int lane, f3 f, f3 dir, float sign,
-                                          float h) {
-  if (n == 0) return 0;
-  f3 P[POLY];
-  float d[POLY];
-#pragma unroll
-  for (int i = 0; i < POLY; ++i) {
-    if (i < n) {
-      P[i] = cl_get(s, src, i, lane);
-      d[i] = sign * dot(P[i] - f, dir) - h;
-    }
-  }
-  f3 prev = P[0];
-  float dp = d[0];
-#pragma unroll
-  for (int i = 1; i < POLY; ++i) {
-    if (i == n - 1) {
-      prev = P[i];
-      dp = d[i];
-    }
-  }
-  int m = 0;
-#pragma unroll
-  for (int i = 0; i < POLY; ++i) {
-    if (i < n) {
-      const f3 cur = P[i];
-      const float dc = d[i];
-      if (dc <= 0.0f) {
-        if (dp > 0.0f) {
-          if (m < POLY) cl_put(s, dst, m, lane, prev + (cur - prev) * (dp / (dp - dc)));
-          ++m;
-        }
-        if (m < POLY) cl_put(s, dst, m, lane, cur);
-        ++m;
-      } else if (dp <= 0.0f) {
-        if (m < POLY) cl_put(s, dst, m, lane, prev + (cur - prev) * (dp / (dp - dc)));
-        ++m;
-      }
-      prev = cur;
-      dp = dc;
-    }
-  }
-  return m < POLY ? m : POLY;
+__device__ __forceinline__ int clip_group(Smem<K>& s, f3* P, int n, f3 f, f3 dir, float sign, float h, int buf,
+                                          int grp, int gl, int lane) {
+  const float dc = sign * dot(*P - f, dir) - h;
+  const int src = (grp << 3) | (gl == 0 ? (n > 0 ? n - 1 : 0) : gl - 1);
+  const f3 Pp = mk(__shfl(P->x, src, 64), __shfl(P->y, src, 64), __shfl(P->z, src, 64));
+  const float dp = __shfl(dc, src, 64);
+  const bool live = gl < n;
+  const bool in_c = dc <= 0.0f, in_p = dp <= 0.0f;
+  const bool emit_x = live && (in_c != in_p), emit_c = live && in_c;
+  const unsigned long long mx = __ballot(emit_x), mc = __ballot(emit_c);
+  const unsigned long long gm = 0xffull << (8 * grp), below = ((1ull << lane) - 1ull) & gm;
+  const int q = __popcll(mx & below) + __popcll(mc & below);
+  const int m = __popcll(mx & gm) + __popcll(mc & gm);
+  if (emit_x && q < POLY) cl_put(s, buf, q, grp, Pp + (*P - Pp) * (dp * rcp(dp - dc)));
+  if (emit_c && q + (emit_x ? 1 : 0) < POLY) cl_put(s, buf, q + (emit_x ? 1 : 0), grp, *P);
+  wave_sync();
+  const int nn = m < POLY ? m : POLY;
+  if (gl < nn) *P = cl_get(s, buf, gl, grp);
+  return nn;
 }
 
 // Axis k and half extent k of LDS body i (dynamic k reads LDS, so no
@@ -310,49 +294,6 @@ __device__ __forceinline__ f3 lds_axis(const Smem<K>& s, int i, int k) {
 template <int K>
 __device__ __forceinline__ float lds_half(const Smem<K>& s, int i, int k) {
   return reinterpret_cast<const float*>(&s.half[i])[k];
-}
-
-// Face-axis manifold: reference face of the axis owner, incident face of the
-// other box, clipped by the reference face's side planes (+u, -u, +v, -v).
-// Leaves the polygon in clip buffer 1 and returns its size; nref, f for sep.
-template <int K>
-__device__ __forceinline__ int face_manifold(Smem<K>& s, int ia, int ib, int idx, f3 n, int lane, f3* nref_out,
-                                             f3* f_out) {
-  const bool a_ref = idx < 3;
-  const int ri = a_ref ? ia : ib;
-  const int ii = a_ref ? ib : ia;
-  const int k = a_ref ? idx : idx - 3;
-  f3 nref = sel(a_ref, n, neg(n));
-  f3 f = xyz(s.pos[ri]) + nref * lds_half(s, ri, k);
-  int ku = k == 2 ? 0 : k + 1, kv = k == 0 ? 2 : k - 1;
-  f3 u = lds_axis(s, ri, ku), v = lds_axis(s, ri, kv);
-  float hu = lds_half(s, ri, ku), hv = lds_half(s, ri, kv);
-  int best = 0;
-  float bd = INFINITY;
-#pragma unroll
-  for (int fi = 0; fi < 6; ++fi) {
-    float sg = (fi & 1) ? -1.0f : 1.0f;
-    float dd = sg * dot(xyz(s.col[fi >> 1][ii]), nref);
-    if (dd < bd) { bd = dd; best = fi; }
-  }
-  int m = best >> 1;
-  float sg = (best & 1) ? -1.0f : 1.0f;
-  int pa = m == 2 ? 0 : m + 1, qa = m == 0 ? 2 : m - 1;
-  f3 fc = xyz(s.pos[ii]) + lds_axis(s, ii, m) * (sg * lds_half(s, ii, m));
-  f3 ep = lds_axis(s, ii, pa) * lds_half(s, ii, pa);
-  f3 eq = lds_axis(s, ii, qa) * lds_half(s, ii, qa);
-  cl_put(s, 1, 0, lane, fc + (ep + eq));
-  cl_put(s, 1, 1, lane, fc + (eq - ep));
-  cl_put(s, 1, 2, lane, fc - (ep + eq));
-  cl_put(s, 1, 3, lane, fc + (ep - eq));
-  int np = 4;
-  np = clip_stage(s, 1, np, 0, lane, f, u, 1.0f, hu);
-  np = clip_stage(s, 0, np, 1, lane, f, u, -1.0f, hu);
-  np = clip_stage(s, 1, np, 0, lane, f, v, 1.0f, hv);
-  np = clip_stage(s, 0, np, 1, lane, f, v, -1.0f, hv);
-  *nref_out = nref;
-  *f_out = f;
-  return np;
 }
 
 // Edge-axis contact: closest points of the two extreme edges parallel to the
@@ -390,7 +331,7 @@ __device__ __forceinline__ f3 edge_point(const Smem<K>& s, int ia, int ib, int i
 // ------------------------------------------------------------------ contact record in VGPRs
 struct Contact {
   int ab;
-  f3 n, t1, ra, rb;
+  f3 n, t1, t2, ra, rb;
   float kn, kt1, kt2, vstar, mu;
   float ln, lt1, lt2;
 };
@@ -422,15 +363,16 @@ __device__ __forceinline__ void prep_contact(const Smem<K>& s, int c, const Para
   const int ei = (ax <= ay && ax <= az) ? 0 : (ay <= az ? 1 : 2);
   f3 e = mk(ei == 0 ? 1.0f : 0.0f, ei == 1 ? 1.0f : 0.0f, ei == 2 ? 1.0f : 0.0f);
   f3 t1 = cross(e, n);
-  t1 = t1 * (1.0f / sqrtf(dot(t1, t1)));
+  t1 = t1 * rsq(dot(t1, t1));
   f3 t2 = cross(n, t1);
+  ct->t2 = t2;
   ct->t1 = t1;
   float ca = (float)s.cnt[a], cb = (float)s.cnt[b];
-  ct->kn = 1.0f / (ca * eff_mass_side(s, a, ct->ra, n) + cb * eff_mass_side(s, b, ct->rb, n));
-  ct->kt1 = 1.0f / (ca * eff_mass_side(s, a, ct->ra, t1) + cb * eff_mass_side(s, b, ct->rb, t1));
-  ct->kt2 = 1.0f / (ca * eff_mass_side(s, a, ct->ra, t2) + cb * eff_mass_side(s, b, ct->rb, t2));
+  ct->kn = rcp(ca * eff_mass_side(s, a, ct->ra, n) + cb * eff_mass_side(s, b, ct->rb, n));
+  ct->kt1 = rcp(ca * eff_mass_side(s, a, ct->ra, t1) + cb * eff_mass_side(s, b, ct->rb, t1));
+  ct->kt2 = rcp(ca * eff_mass_side(s, a, ct->ra, t2) + cb * eff_mass_side(s, b, ct->rb, t2));
   ct->mu = 0.5f * (s.iwb[a].z + s.iwb[b].z);
-  ct->vstar = sep > 0.0f ? -sep / p.dt : p.beta * fmaxf(-sep - p.slop, 0.0f) / p.dt;
+  ct->vstar = sep > 0.0f ? -sep * p.inv_dt : p.beta * fmaxf(-sep - p.slop, 0.0f) * p.inv_dt;
   // warm start from the previous substep's contact with the same key
   ct->ln = ct->lt1 = ct->lt2 = 0.0f;
   const int key = contact_key(ab);
@@ -834,68 +776,129 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       nc_raw = total;
     }
 
-    // ---- 4b. box-box and pusher-box contacts, pairs in lexicographic order
-    for (int r0 = 0; r0 < n_pairs; r0 += CLIP_LANES) {
-      const int pi = r0 + lane;
-      const bool has = lane < CLIP_LANES && pi < n_pairs && pi < MAX_PAIRS;
-      int cnt = 0, np = 0, ia = 0, ib = 0;
-      SatResult sr;
-      sr.idx = -1;
-      f3 poly[POLY];
-      float psep[POLY];
-      f3 n = mk(0, 0, 0), nref = mk(0, 0, 0), fref = mk(0, 0, 0), ept = mk(0, 0, 0);
+    // ---- 4b. box-box and pusher-box contacts, pairs in lexicographic order.
+    // Eight pairs per pass, one 8-lane group each: lane k of a group
+    // evaluates candidate axes k and k + 8, the group scans the candidates in
+    // order (row broadcasts), and the incident face is clipped with one
+    // polygon point per lane.
+    for (int r0 = 0; r0 < n_pairs; r0 += 8) {
+      const int grp = lane >> 3, gl = lane & 7;
+      const int pi = r0 + grp;
+      const bool has = pi < n_pairs && pi < MAX_PAIRS;
+      int ia = 0, ib = 1;
       if (has) {
-        unsigned pr = s.pairs[pi];
+        const unsigned pr = s.pairs[pi];
         ia = pr >> 8;
         ib = pr & 255;
-        sr = sat_best(s, ia, ib, p);
-        if (sr.idx >= 0) {
-          f3 d = xyz(s.pos[ib]) - xyz(s.pos[ia]);
-          n = sel(dot(d, sr.L) >= 0.0f, sr.L, neg(sr.L));
-          if (sr.idx < 6) {
-            np = face_manifold(s, ia, ib, sr.idx, n, lane, &nref, &fref);
-#pragma unroll
-            for (int i = 0; i < POLY; ++i) {
-              if (i < np) {
-                poly[i] = cl_get(s, 1, i, lane);
-                psep[i] = dot(nref, poly[i] - fref);
-                cnt += psep[i] <= p.margin ? 1 : 0;
-              }
-            }
-          } else {
-            ept = edge_point(s, ia, ib, sr.idx, n);
-            cnt = 1;
-          }
-        }
       }
-      int total;
-      int off = nc_raw + wave_excl_scan_bits(cnt, 4, &total);
-      if (has && cnt > 0) {
+      const Box A = load_box(s, ia), B = load_box(s, ib);
+      const f3 d = B.c - A.c;
+      // candidate gl: 0-2 faces of A, 3-5 faces of B, 6-7 edge crosses A0 x B0, A0 x B1
+      f3 L0;
+      bool ok0 = has;
+      if (gl < 3) {
+        L0 = axis(A, gl);
+      } else if (gl < 6) {
+        L0 = axis(B, gl - 3);
+      } else {
+        const f3 v = cross(A.a0, axis(B, gl - 6));
+        const float l2 = dot(v, v);
+        ok0 = ok0 && l2 >= p.edge_eps * p.edge_eps;
+        L0 = v * rsq(l2);
+      }
+      // candidate gl + 8: edge crosses 8-14 (gl = 7 has none)
+      const int e1 = gl + 2;  // index of the edge pair (i, j) = (e1 / 3, e1 % 3)
+      const f3 v1 = cross(axis(A, e1 / 3), axis(B, e1 % 3));
+      const float l21 = dot(v1, v1);
+      const bool ok1 = has && gl < 7 && l21 >= p.edge_eps * p.edge_eps;
+      const f3 L1 = v1 * rsq(l21);
+      const float sv0 = fabsf(dot(d, L0)) - radius_along(A, L0) - radius_along(B, L0);
+      const float sv1 = fabsf(dot(d, L1)) - radius_along(A, L1) - radius_along(B, L1);
+      const unsigned long long gm = 0xffull << (8 * grp);
+      const bool out = (__ballot((ok0 && sv0 > p.margin) || (ok1 && sv1 > p.margin)) & gm) != 0ull;
+      float bs = -INFINITY;
+      int best = -1;
+      sat_scan8(sv0, sv1, ok0 ? 1 : 0, ok1 ? 1 : 0, (lane & 8) != 0, p.tau_face, p.tau_edge, &bs, &best);
+      if (!has || out) best = -1;
+      // every lane of the group holds the pair's axis: its direction again
+      f3 n = mk(0, 0, 0);
+      if (best >= 0) {
+        f3 Lb;
+        if (best < 3) {
+          Lb = axis(A, best);
+        } else if (best < 6) {
+          Lb = axis(B, best - 3);
+        } else {
+          const f3 v = cross(axis(A, (best - 6) / 3), axis(B, (best - 6) % 3));
+          Lb = v * rsq(dot(v, v));
+        }
+        n = sel(dot(d, Lb) >= 0.0f, Lb, neg(Lb));
+      }
+      // face axis: reference face of the axis owner, incident face of the
+      // other box (most anti-parallel, ties to +x, -x, +y, -y, +z, -z), its
+      // four corners one per lane, clipped by the reference face's side
+      // planes +u, -u, +v, -v
+      const bool face = best >= 0 && best < 6;
+      f3 P = mk(0, 0, 0), nref = mk(0, 0, 1), fref = mk(0, 0, 0), u = mk(1, 0, 0), w = mk(0, 1, 0);
+      float hu = 0.0f, hw = 0.0f;
+      int np = 0;
+      if (face) {
+        const bool a_ref = best < 3;
+        const int k = a_ref ? best : best - 3;
+        const int ku = k == 2 ? 0 : k + 1, kv = k == 0 ? 2 : k - 1;
+        nref = sel(a_ref, n, neg(n));
+        fref = sel(a_ref, A.c, B.c) + nref * sel(a_ref, hcomp(A, k), hcomp(B, k));
+        u = sel(a_ref, axis(A, ku), axis(B, ku));
+        w = sel(a_ref, axis(A, kv), axis(B, kv));
+        hu = sel(a_ref, hcomp(A, ku), hcomp(B, ku));
+        hw = sel(a_ref, hcomp(A, kv), hcomp(B, kv));
+        // incident box: the other one
+        const f3 i0 = sel(a_ref, B.a0, A.a0), i1 = sel(a_ref, B.a1, A.a1), i2 = sel(a_ref, B.a2, A.a2);
+        const f3 ih = sel(a_ref, B.h, A.h), ic = sel(a_ref, B.c, A.c);
+        const float c0 = dot(i0, nref), c1 = dot(i1, nref), c2 = dot(i2, nref);
+        int fb = 0;
+        float bd = c0;
+        if (-c0 < bd) { bd = -c0; fb = 1; }
+        if (c1 < bd) { bd = c1; fb = 2; }
+        if (-c1 < bd) { bd = -c1; fb = 3; }
+        if (c2 < bd) { bd = c2; fb = 4; }
+        if (-c2 < bd) { bd = -c2; fb = 5; }
+        const int m = fb >> 1;
+        const float sg = (fb & 1) ? -1.0f : 1.0f;
+        const f3 am = sel(m == 0, i0, sel(m == 1, i1, i2));
+        const f3 ap = sel(m == 0, i1, sel(m == 1, i2, i0));
+        const f3 aq = sel(m == 0, i2, sel(m == 1, i0, i1));
+        const float hm = sel(m == 0, ih.x, sel(m == 1, ih.y, ih.z));
+        const float hp = sel(m == 0, ih.y, sel(m == 1, ih.z, ih.x));
+        const float hq = sel(m == 0, ih.z, sel(m == 1, ih.x, ih.y));
+        const f3 fc = ic + am * (sg * hm);
+        const f3 ep = ap * hp, eq = aq * hq;
+        P = sel(gl == 0, fc + (ep + eq), sel(gl == 1, fc + (eq - ep), sel(gl == 2, fc - (ep + eq), fc + (ep - eq))));
+        np = 4;
+      }
+      np = clip_group(s, &P, np, fref, u, 1.0f, hu, 0, grp, gl, lane);
+      np = clip_group(s, &P, np, fref, u, -1.0f, hu, 1, grp, gl, lane);
+      np = clip_group(s, &P, np, fref, w, 1.0f, hw, 0, grp, gl, lane);
+      np = clip_group(s, &P, np, fref, w, -1.0f, hw, 1, grp, gl, lane);
+      // contacts: kept polygon points (face) or one edge-edge point
+      const float psep = dot(nref, P - fref);
+      const bool keep = face ? (gl < np && psep <= p.margin) : (best >= 6 && gl == 0);
+      const unsigned long long km = __ballot(keep);
+      const unsigned long long below = (1ull << lane) - 1ull;
+      const int off = nc_raw + __popcll(km & below);
+      if (keep && off < C) {
         const int ab = ia | (ib << 8);
-        if (sr.idx < 6) {
-          int t = 0;
-#pragma unroll
-          for (int i = 0; i < POLY; ++i) {
-            if (i >= np) continue;
-            const f3 pt = poly[i];
-            const float sep = psep[i];
-            if (sep <= p.margin) {
-              const int c = off + t;
-              if (c < C) {
-                s.u.stage[c][0] = f4(pt - nref * (0.5f * sep), sep);
-                s.u.stage[c][1] = f4(n, 0.0f);
-                s.cab[c] = ab | (t << 16);
-              }
-              ++t;
-            }
-          }
-        } else if (off < C) {
-          s.u.stage[off][0] = f4(ept, sr.s);
+        if (face) {
+          s.u.stage[off][0] = f4(P - nref * (0.5f * psep), psep);
+          s.u.stage[off][1] = f4(n, 0.0f);
+          s.cab[off] = ab | (__popcll(km & below & gm) << 16);
+        } else {
+          s.u.stage[off][0] = f4(edge_point(s, ia, ib, best, n), bs);
           s.u.stage[off][1] = f4(n, 0.0f);
           s.cab[off] = ab;
         }
       }
-      nc_raw += total;
+      nc_raw += __popcll(km);
     }
     if (nc_raw > C) {
       status |= PMBS_ENV_CONTACT_OVERFLOW;
@@ -928,48 +931,55 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       return;
     }
 
-    // ---- 5. per-body incidence lists in contact-index order (CSR) and counts
+    // ---- 5. per-body incidence lists in contact-index order (CSR) and counts:
+    // every contact sets its bit in the masks of its two bodies; a body's
+    // list length is its bit count; every contact then writes itself into
+    // both lists at its rank among the set bits (contact-index order)
     int inc_start = 0, inc_count = 0;
     {
+      constexpr int W = 2 * K;  // mask words per body: slot sl, lane half
+      for (int t = lane; t < NOBJ * W; t += 64) (&s.x.incm[0][0])[t] = 0u;
+      wave_sync();
       int ca[K], cb[K];
+      const unsigned bit = 1u << (lane & 31);
 #pragma unroll
       for (int sl = 0; sl < K; ++sl) {
         const int c = 64 * sl + lane;
         const int ab = c < nc ? s.cab[c] : -1;
-        ca[sl] = c < nc ? (ab & 255) : -1;
-        cb[sl] = c < nc ? ((ab >> 8) & 255) : -1;
+        ca[sl] = c < nc && (ab & 255) < nb ? (ab & 255) : -1;
+        cb[sl] = c < nc && ((ab >> 8) & 255) < nb ? ((ab >> 8) & 255) : -1;
+        const int w = 2 * sl + (lane >> 5);
+        if (ca[sl] >= 0) atomicOr(&s.x.incm[ca[sl]][w], bit);
+        if (cb[sl] >= 0) atomicOr(&s.x.incm[cb[sl]][w], bit);
       }
-      unsigned long long mA[K], mB[K];
-#pragma unroll
-      for (int sl = 0; sl < K; ++sl) { mA[sl] = 0ull; mB[sl] = 0ull; }
-      for (int j = 0; j < nb; ++j) {
-#pragma unroll
-        for (int sl = 0; sl < K; ++sl) {
-          if (64 * sl < nc) {
-            const unsigned long long ma = __ballot(ca[sl] == j), mb = __ballot(cb[sl] == j);
-            if (b == j) { mA[sl] = ma; mB[sl] = mb; }
-          }
-        }
-      }
+      wave_sync();
       int cn = 0;
+      if (active) {
 #pragma unroll
-      for (int sl = 0; sl < K; ++sl) cn += __popcll(mA[sl] | mB[sl]);
-      if (!active) cn = 0;
+        for (int w = 0; w < W; ++w) cn += __popc(s.x.incm[b][w]);
+      }
       int tot;
       int st0 = wave_excl_scan_bits(part == 0 ? cn : 0, 11, &tot);
       inc_start = __shfl(st0, b, 64);
       inc_count = cn;
       if (active && part == 0) {
         s.cnt[b] = cn;
-        int t = inc_start;
+        s.sorted[b] = inc_start;  // list starts (the sort keys are no longer needed)
+      }
+      wave_sync();
 #pragma unroll
-        for (int sl = 0; sl < K; ++sl) {
-          unsigned long long m = mA[sl] | mB[sl];
-          while (m) {
-            const int bit = __builtin_ctzll(m);
-            m &= m - 1;
-            const int side = (int)((mB[sl] >> bit) & 1ull);
-            s.inc[t++] = (unsigned short)(((64 * sl + bit) << 1) | side);
+      for (int sl = 0; sl < K; ++sl) {
+        const int c = 64 * sl + lane;
+        const int w = 2 * sl + (lane >> 5);
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int j = side ? cb[sl] : ca[sl];
+          if (j >= 0) {
+            int r = s.sorted[j] + __popc(s.x.incm[j][w] & (bit - 1u));
+#pragma unroll
+            for (int w2 = 0; w2 < W; ++w2)
+              if (w2 < w) r += __popc(s.x.incm[j][w2]);
+            s.inc[r] = (unsigned short)((c << 1) | side);
           }
         }
       }
@@ -1012,7 +1022,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         const int c = 64 * sl + lane;
         if (c < nc) {
           Contact& q = ct[sl];
-          const f3 t2 = cross(q.n, q.t1);
+          const f3 t2 = q.t2;
           f3 P;
           if (it < 0) {
             P = q.n * q.ln + (q.t1 * q.lt1 + t2 * q.lt2);
@@ -1027,7 +1037,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
             float lt2 = q.lt2 - q.kt2 * dot(u, t2);
             float lim = q.mu * ln, mag2 = lt1 * lt1 + lt2 * lt2;
             if (mag2 > lim * lim) {
-              float sc = lim / sqrtf(mag2);
+              float sc = lim * rsq(mag2);
               lt1 *= sc;
               lt2 *= sc;
             }
@@ -1119,8 +1129,8 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         float dz = q0 * w.z + (w.x * q2 - w.y * q1);
         float hd = 0.5f * dt;
         q0 += hd * dw; q1 += hd * dx; q2 += hd * dy; q3 += hd * dz;
-        float l = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-        q0 /= l; q1 /= l; q2 /= l; q3 /= l;
+        const float il = rsq(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        q0 *= il; q1 *= il; q2 *= il; q3 *= il;
       }
     }
     xp = xp + vp * dt;

@@ -115,6 +115,7 @@ Params params_of(const pmbs_sim_config& c) {
   p.edge_eps = c.edge_eps;
   p.push_length = c.push_length;
   p.push_standoff = c.push_standoff;
+  p.inv_dt = (float)(1.0 / (double)c.dt);
   p.iters = c.solver_iters;
   p.n_dirs = 8;
   return p;
