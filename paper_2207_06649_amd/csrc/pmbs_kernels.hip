@@ -136,25 +136,10 @@ struct Box {
   f3 c, a0, a1, a2, h;
 };
 
-// switch (not a conditional on struct lvalues) keeps the boxes in registers
-__device__ __forceinline__ f3 axis(const Box& b, int k) {
-  f3 r;
-  switch (k) {
-    case 0: r = b.a0; break;
-    case 1: r = b.a1; break;
-    default: r = b.a2; break;
-  }
-  return r;
-}
-__device__ __forceinline__ float hcomp(const Box& b, int k) {
-  float r;
-  switch (k) {
-    case 0: r = b.h.x; break;
-    case 1: r = b.h.y; break;
-    default: r = b.h.z; break;
-  }
-  return r;
-}
+// per-component selects (no indexing into a struct copy) keep the boxes in
+// registers when k varies across lanes
+__device__ __forceinline__ f3 axis(const Box& b, int k) { return sel(k == 0, b.a0, sel(k == 1, b.a1, b.a2)); }
+__device__ __forceinline__ float hcomp(const Box& b, int k) { return sel(k == 0, b.h.x, sel(k == 1, b.h.y, b.h.z)); }
 
 template <int K>
 __device__ __forceinline__ Box load_box(const Smem<K>& s, int i) {
@@ -207,16 +192,17 @@ __device__ __forceinline__ int row_bcast(int v) {
 }
 
 // Candidate k of an 8-lane group: held by lane k mod 8 of the group, in its
-// first value for k < 8 and its second for k >= 8.  Lane `hi` groups are the
-// upper halves of their rows.
+// first value for k < 8 and its second for k >= 8; an invalid candidate
+// holds -inf (candidate 0, a face of A, is always valid, so -inf never
+// replaces a kept axis).  Lanes with `hi` set are the upper halves of their
+// 16-lane rows.
 template <int k>
-__device__ __forceinline__ void sat_scan_step(float sv0, float sv1, int ok0, int ok1, bool hi, float tau_face,
-                                              float tau_edge, float* bs, int* best) {
-  const int sv = __float_as_int(k < 8 ? sv0 : sv1), ok = k < 8 ? ok0 : ok1;
+__device__ __forceinline__ void sat_scan_step(float sv0, float sv1, bool hi, float tau_face, float tau_edge, float* bs,
+                                              int* best) {
+  const int sv = __float_as_int(k < 8 ? sv0 : sv1);
   const float sk = __int_as_float(hi ? row_bcast<8 + (k & 7)>(sv) : row_bcast<k & 7>(sv));
-  const int okk = hi ? row_bcast<8 + (k & 7)>(ok) : row_bcast<k & 7>(ok);
   const float tau = k < 6 ? tau_face : tau_edge;
-  if (okk && (*best < 0 || sk > *bs + tau)) {
+  if (*best < 0 || sk > *bs + tau) {
     *bs = sk;
     *best = k;
   }
@@ -224,25 +210,24 @@ __device__ __forceinline__ void sat_scan_step(float sv0, float sv1, int ok0, int
 
 // Contact axis of a pair from its 15 candidates (0-2 faces of A, 3-5 faces
 // of B, 6-14 edge crosses) held by the 8 lanes of a group: the kept axis
-// starts at the first valid candidate and is replaced only when a later one
+// starts at the first candidate and is replaced only when a later valid one
 // exceeds it by tau (face) or tau_edge (edge axes).
-__device__ __forceinline__ void sat_scan8(float sv0, float sv1, int ok0, int ok1, bool hi, float tf, float te,
-                                          float* bs, int* best) {
-  sat_scan_step<0>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<1>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<2>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<3>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<4>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<5>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<6>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<7>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<8>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<9>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<10>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<11>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<12>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<13>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
-  sat_scan_step<14>(sv0, sv1, ok0, ok1, hi, tf, te, bs, best);
+__device__ __forceinline__ void sat_scan8(float sv0, float sv1, bool hi, float tf, float te, float* bs, int* best) {
+  sat_scan_step<0>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<1>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<2>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<3>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<4>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<5>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<6>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<7>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<8>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<9>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<10>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<11>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<12>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<13>(sv0, sv1, hi, tf, te, bs, best);
+  sat_scan_step<14>(sv0, sv1, hi, tf, te, bs, best);
 }
 
 // ------------------------------------------------------------------ clipping
@@ -818,7 +803,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       const bool out = (__ballot((ok0 && sv0 > p.margin) || (ok1 && sv1 > p.margin)) & gm) != 0ull;
       float bs = -INFINITY;
       int best = -1;
-      sat_scan8(sv0, sv1, ok0 ? 1 : 0, ok1 ? 1 : 0, (lane & 8) != 0, p.tau_face, p.tau_edge, &bs, &best);
+      sat_scan8(ok0 ? sv0 : -INFINITY, ok1 ? sv1 : -INFINITY, (lane & 8) != 0, p.tau_face, p.tau_edge, &bs, &best);
       if (!has || out) best = -1;
       // every lane of the group holds the pair's axis: its direction again
       f3 n = mk(0, 0, 0);
