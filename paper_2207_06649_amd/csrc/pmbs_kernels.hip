@@ -47,6 +47,12 @@ __device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y 
 __device__ __forceinline__ f3 cross(f3 a, f3 b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
+// xyz of a float4 slot (the w lane is never read)
+__device__ __forceinline__ void st3(float4* d, f3 v) {
+  d->x = v.x;
+  d->y = v.y;
+  d->z = v.z;
+}
 __device__ __forceinline__ float sel(bool c, float a, float b) { return c ? a : b; }
 __device__ __forceinline__ f3 xyz(float4 v) { return {v.x, v.y, v.z}; }
 __device__ __forceinline__ float4 f4(f3 v, float w) { return make_float4(v.x, v.y, v.z, w); }
@@ -986,19 +992,28 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       iw_o = mk(ia.w, ib.x, ib.y);
     }
     // the first 8 incidences of each body stay in registers for the whole
-    // solve (16 bits each), so their impulse loads need no index load first
+    // solve as 16-bit codes: the byte offset of the impulse row this lane
+    // reads (linear lanes P, angular lanes r x P of the body's side) with
+    // the side in bit 0, so a load needs no index arithmetic
     unsigned inc_reg[4] = {0u, 0u, 0u, 0u};
     const int n_reg = inc_count < 8 ? inc_count : 8;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < n_reg) inc_reg[k >> 1] |= (unsigned)s.inc[inc_start + k] << (16 * (k & 1));
+    for (int k = 0; k < 8; ++k) {
+      if (k < n_reg) {
+        const unsigned en = s.inc[inc_start + k], side = en & 1u;
+        const unsigned row = part == 0 ? 0u : 1u + side;
+        const unsigned code = ((row * (unsigned)C + (en >> 1)) * 16u) | side;
+        inc_reg[k >> 1] |= code << (16 * (k & 1));
+      }
+    }
+    const char* imp_base = reinterpret_cast<const char*>(&s.u.imp[0][0]);
     // it = -1 applies the warm-start impulses; it >= 0 are the Jacobi iterations
     wave_sync();
     for (int it = -1; it < p.iters; ++it) {
       if (it >= 0) {
         if (active) {
-          if (part == 0) s.vel[b] = f4(v, 0.0f);
-          else s.ang[b] = f4(w, 0.0f);
+          if (part == 0) st3(&s.vel[b], v);
+          else st3(&s.ang[b], w);
         }
         wave_sync();
       }
@@ -1031,9 +1046,9 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
             q.lt2 = lt2;
             P = q.n * dln + (q.t1 * dl1 + t2 * dl2);
           }
-          s.u.imp[0][c] = f4(P, 0.0f);
-          s.u.imp[1][c] = f4(cross(q.ra, P), 0.0f);
-          s.u.imp[2][c] = f4(cross(q.rb, P), 0.0f);
+          st3(&s.u.imp[0][c], P);
+          st3(&s.u.imp[1][c], cross(q.ra, P));
+          st3(&s.u.imp[2][c], cross(q.rb, P));
         }
       }
       wave_sync();
@@ -1046,16 +1061,16 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         for (int k0 = 0; k0 < 8; k0 += 4) {
           if (k0 < n_reg) {
             float4 val[4];
+            unsigned code[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              const int en = (int)((inc_reg[(k0 + u) >> 1] >> (16 * (u & 1))) & 0xffffu);
-              val[u] = s.u.imp[part == 0 ? 0 : sel0 + (en & 1)][en >> 1];
+              code[u] = (inc_reg[(k0 + u) >> 1] >> (16 * (u & 1))) & 0xffffu;
+              val[u] = *reinterpret_cast<const float4*>(imp_base + (code[u] & 0xfffeu));
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               if (k0 + u < n_reg) {
-                const int en = (int)((inc_reg[(k0 + u) >> 1] >> (16 * (u & 1))) & 0xffffu);
-                const float sg = (en & 1) ? 1.0f : -1.0f;
+                const float sg = (code[u] & 1u) ? 1.0f : -1.0f;
                 acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
               }
             }
