@@ -198,6 +198,29 @@ pmbs_status pmbs_sim_autotune(pmbs_sim_t* sim, const int32_t* actions, const int
                               int32_t* d_reward_count, int32_t flags, int32_t reps, const char* cache_path,
                               pmbs_launch_plan* best, float* best_ms, int32_t* cached);
 
+/* Re-purposing descriptors for pmbs_sim_rollout_ex (host arrays of n_envs
+ * entries, see pmbs_tree_extra) and the extra simulations' outputs. */
+typedef struct pmbs_repurpose {
+  const int32_t* src_slot;   /* pool slot of the extra simulation's node */
+  const int32_t* action;     /* its first push (obj * 8 + dir) */
+  const int32_t* node_id;    /* node id keying its random pushes */
+  const int32_t* replica;    /* replica index keying its random pushes */
+  const uint64_t* seed;      /* Philox key of its random pushes */
+  float* d_rewards;          /* device [n_envs][max_h] */
+  int32_t* d_counts;         /* device [n_envs]: rewards written (0: none) */
+} pmbs_repurpose;
+
+/* pmbs_sim_rollout with re-purposing: an env whose rollout reaches reward
+ * 1 with pushes left runs one extra simulation from rp->src_slot[e] with
+ * the pushes left (first rp->action[e], then Philox4x32-10 random pushes
+ * keyed by rp->seed[e] with counter (node_id, action, replica << 8 | push
+ * index, 2)), writing its rewards to rp->d_rewards.  Needs source slots and
+ * no PMBS_ROLLOUT_WRITE_STATE.  rp = NULL is pmbs_sim_rollout. */
+pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const int32_t* act_offset,
+                                const int32_t* src_slot, const int32_t* child_slot, const int32_t* target,
+                                int32_t inputs_on_device, int32_t n_substeps, float width, float* d_rewards,
+                                int32_t max_h, int32_t* d_reward_count, int32_t flags, const pmbs_repurpose* rp);
+
 /* Status word per environment, cleared by every step.  A host destination
  * synchronises. */
 pmbs_status pmbs_sim_env_status(pmbs_sim_t* sim, uint32_t* status_out, int32_t dst_is_device);
@@ -258,6 +281,8 @@ typedef struct pmbs_tree_config {
     int32_t sim_depth;  /* d_s: simulations run to depth max_depth + sim_depth (0) */
     int32_t early_stop; /* Alg. 1 early-stop level and graspable-node termination with the
                            dynamic depth of Sec. IV-A (0: off) */
+    int32_t repurpose;  /* re-purpose environments whose simulation ends early (Sec. IV-C,
+                           batch simulation): see pmbs_tree_extra (0: off) */
 } pmbs_tree_config;
 
 typedef struct pmbs_tree pmbs_tree_t;
@@ -299,6 +324,26 @@ pmbs_status pmbs_tree_select(pmbs_tree_t* tree, int32_t* n_pairs, int32_t* actio
  * max_t gamma^t r_t (Sec. IV-C, backpropagation). */
 pmbs_status pmbs_tree_update(pmbs_tree_t* tree, const float* rewards, int32_t max_h, const int32_t* counts,
                              const uint32_t* env_status, int32_t* n_children);
+
+/* Re-purposing (repurpose on): an environment whose simulation reaches
+ * reward 1 after push t of its h pushes (t + 1 < h) spends the h - t - 1
+ * pushes left on one extra simulation of the next pair in round-robin
+ * order, p' = (p + 1) mod P, as replica R + e (R = ceil(n_envs / P) static
+ * replicas): first the pair's action, then random pushes keyed by (node id,
+ * action, replica, push index) as for the static replicas.  This returns,
+ * for every env of the last selection (host, n_envs entries each), that
+ * pair's node pool slot, action, node id and the replica index; the device
+ * runs the extra simulation (pmbs_sim_rollout_ex) only when the env stops
+ * early. */
+pmbs_status pmbs_tree_extra(const pmbs_tree_t* tree, int32_t* src_slot, int32_t* action, int32_t* node_id,
+                            int32_t* replica);
+
+/* pmbs_tree_update plus the extra simulations' rewards [n_envs][max_h] and
+ * counts (0: none ran, or its first push was discarded); a valid extra
+ * simulation's return joins its pair's maximum. */
+pmbs_status pmbs_tree_update_ex(pmbs_tree_t* tree, const float* rewards, int32_t max_h, const int32_t* counts,
+                                const uint32_t* env_status, const float* extra_rewards, const int32_t* extra_counts,
+                                int32_t* n_children);
 
 /* Alg. 1 (early_stop): a child whose first reward is 1 stands in for a node
  * the grasp classifier accepts (graspable).  The early-stop level starts at
@@ -395,6 +440,7 @@ typedef struct pmbs_server_config {
   int64_t hbm_budget;     /* bytes of node-pool footprint the requests in flight may hold; 0: the pool */
   int32_t graph;          /* replay the batched launch as a captured graph */
   int32_t early_stop;     /* Alg. 1 early stop in every request's tree (pmbs_tree_status) */
+  int32_t repurpose;      /* environment re-purposing in every request (pmbs_tree_extra) */
 } pmbs_server_config;
 
 typedef struct pmbs_request {

@@ -28,6 +28,13 @@ What it follows in the paper:
     the search stops before an iteration once a graspable node sits at a
     depth <= es_level.  A terminal child at depth d < d_T sets d_T = d and
     the simulation depth d_s = 0.  Simulations run to depth d_T + d_s.
+  * Optional (repurpose): leaf parallelisation with early termination and
+    environment re-purposing (Sec. IV-C, batch simulation).  An environment
+    whose simulation reaches reward 1 after push t of h (t + 1 < h) has
+    h - t - 1 pushes of budget left; it spends them on one extra simulation
+    of the next pair in round-robin order, p' = (p + 1) mod P, as replica
+    R + e (R = ceil(N_e / P) static replicas, e the environment), truncated
+    to the budget.  A valid extra simulation joins pair p''s maximum.
 
 Readings where the paper is silent (listed in the design notes): a node is
 a leaf for Alg. 2 when its depth is below D and it has an untried action,
@@ -161,9 +168,11 @@ class Planner:
       root_reward(state) -> float
     """
 
-    def __init__(self, env, root_state, n_envs, c=1.4, gamma=0.8, depth=5, seed=0, sim_depth=0, early_stop=False):
+    def __init__(self, env, root_state, n_envs, c=1.4, gamma=0.8, depth=5, seed=0, sim_depth=0, early_stop=False,
+                 repurpose=False):
         self.env, self.n_envs, self.c, self.gamma, self.D, self.seed = env, n_envs, c, gamma, depth, seed
-        self.Ds, self.early_stop = sim_depth, early_stop
+        self.Ds, self.early_stop, self.repurpose = sim_depth, early_stop, repurpose
+        self.extra_simulations = 0
         self.es_level = 1
         self.graspable = []
         self.next_id = 0
@@ -212,6 +221,24 @@ class Planner:
                 continue
             g = max(self.gamma ** t * r for t, r in enumerate(rewards))
             best_g[pi] = max(best_g.get(pi, -math.inf), g)
+        if self.repurpose:
+            P = len(pairs)
+            R = -(-len(envs) // P)
+            for e, ((pi, rep), (valid, child_state, rewards)) in enumerate(zip(envs, results)):
+                n, a = pairs[pi]
+                h = self.D + self.Ds - n.depth
+                if not valid or not rewards or rewards[-1] < 1.0 or len(rewards) >= h:
+                    continue
+                budget = h - len(rewards)
+                q = (pi + 1) % P
+                nq, aq = pairs[q]
+                na = self.env.n_actions(nq.state)
+                acts = [aq] + [rollout_action(nq.id, aq, R + e, t, na, self.seed) for t in range(1, budget)]
+                v2, _, rw2 = self.env.run(nq.state, acts)
+                self.extra_simulations += 1
+                if v2 and rw2:
+                    g = max(self.gamma ** t * r for t, r in enumerate(rw2))
+                    best_g[q] = max(best_g.get(q, -math.inf), g)
         for pi, (n, a) in enumerate(pairs):
             first = envs.index((pi, 0))
             valid, child_state, rewards = results[first]

@@ -33,6 +33,10 @@ struct pmbs_sim {
   // the overflow lists feeding the 256- and 512-contact fallbacks
   int32_t *d_ctl, *d_ovf4, *d_ovf8;
   int32_t *d_bc_base;      // [max_envs] optional body-constant rows per env
+  int32_t* d_x_desc;       // [max_envs][4] re-purposing descriptors
+  uint32_t* d_x_key;       // [max_envs][2] their Philox keys
+  float* d_x_rewards;      // [max_envs][max_horizon] extra simulations' rewards (planner, server)
+  int32_t* d_x_counts;     // [max_envs]
   int cus = 0, occ[3] = {0, 0, 0};   // CUs; resident blocks per CU of the 128/256/512 kernels
   pmbs_launch_plan plan;
   // internal streams and events for the concurrent class launches and graph capture

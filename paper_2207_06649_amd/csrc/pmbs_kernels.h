@@ -43,6 +43,14 @@ struct StepArgs {
   // stride bc_stride (null: row env_offset[e], stride `stride`)
   const int* bc_base;
   int bc_stride;
+  // re-purposing (null x_desc: off): per env, the extra simulation's node
+  // pool slot, first action, node id and replica (x, y, z, w; the node id and
+  // replica key its random pushes with x_key), and its rewards
+  // [n_envs][max_h] and count
+  const int4* x_desc;
+  const uint2* x_key;
+  float* x_rewards;
+  int* x_count;
   // work distribution
   const int* order;         // work item -> env (null: identity)
   int* queue;               // device counter (null: one block per work item)

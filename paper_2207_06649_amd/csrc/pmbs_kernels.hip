@@ -466,6 +466,30 @@ __device__ __forceinline__ void quat_cols(float q0, float q1, float q2, float q3
   *c2 = mk(2 * (q1 * q3 + q0 * q2), 2 * (q2 * q3 - q0 * q1), 1 - 2 * (q1 * q1 + q2 * q2));
 }
 
+// ------------------------------------------------------------------ random pushes
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011) keyed by a 64-bit
+// seed; the random push of a simulation is the first output word modulo the
+// number of actions, counter (node id, first action, replica << 8 | push
+// index, 2).
+__device__ __forceinline__ int philox_action(uint2 key, unsigned c0, unsigned c1, unsigned c2, unsigned n_actions) {
+  unsigned c3 = 2u, k0 = key.x, k1 = key.y;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const unsigned hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const unsigned hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const unsigned n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return (int)(c0 % n_actions);
+}
+
 // ------------------------------------------------------------------ one environment
 // Runs env e through its pushes: one explicit push (step mode) or a list of
 // contour pushes (rollout mode, with a reward after each push).
@@ -483,7 +507,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   const float dt = p.dt;
   const bool rollout = g.actions != nullptr;
   const int act0 = rollout ? g.act_offset[e] : 0;
-  const int n_push = rollout ? g.act_offset[e + 1] - act0 : 1;
+  int n_push = rollout ? g.act_offset[e + 1] - act0 : 1;
   const int src = (rollout && g.src_slot) ? g.src_slot[e] : -1;
   const int PS = g.pool_stride;
 
@@ -559,6 +583,11 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   long long stat_nc = 0, stat_pairs = 0, stat_sub = 0;
   const int n_obj = nb + 1;
 
+  // job 0 is the env's own simulation; job 1 (re-purposing) is one extra
+  // simulation of another pair that spends the pushes left when job 0
+  // reached reward 1 early
+  int t_stop = -1, n_rewards_x = 0;
+  for (int job = 0; job < 2; ++job) {
   for (int t = 0; t < n_push; ++t) {
   // ---- push begin (uniform across the wave)
   write_body_frames();
@@ -570,7 +599,15 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     // its yaw frame, starting beyond the footprint's ray-to-boundary
     // distance by the pusher half width plus the standoff, moving
     // push_length toward the object centre
-    const int act = g.actions[act0 + t];
+    int act;
+    if (job == 0) {
+      act = g.actions[act0 + t];
+    } else {
+      const int4 xd = g.x_desc[e];
+      act = t == 0 ? xd.y
+                   : philox_action(g.x_key[e], (unsigned)xd.z, (unsigned)xd.y, ((unsigned)xd.w << 8) | (unsigned)t,
+                                   (unsigned)(nb * p.n_dirs));
+    }
     const int obj = act / p.n_dirs, dir = act - obj * p.n_dirs;
     have_push = obj >= 0 && obj < nb;
     if (have_push) {
@@ -646,13 +683,14 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     pc1 = mk(0, 1, 0);
     n_move = 0;
   }
-  if (have_push && !valid && (!rollout || t == 0)) status |= PMBS_ENV_PUSH_INVALID;
+  if (have_push && !valid && (!rollout || t == 0) && job == 0) status |= PMBS_ENV_PUSH_INVALID;
   if (rollout && !valid) {
     // a discarded expansion push ends the rollout; a discarded random push
     // leaves the state and repeats the previous reward
     if (t == 0) break;
-    if (lane == 0) g.rewards[(size_t)e * g.max_h + t] = last_r;
-    n_rewards = t + 1;
+    if (lane == 0) (job ? g.x_rewards : g.rewards)[(size_t)e * g.max_h + t] = last_r;
+    if (job == 0) n_rewards = t + 1;
+    else n_rewards_x = t + 1;
     continue;
   }
 
@@ -1152,10 +1190,11 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     for (int o = 32; o > 0; o >>= 1) d = fminf(d, __shfl_xor(d, o, 64));
     const float r = d > g.width ? 1.0f : d / g.width;
     last_r = r;
-    n_rewards = t + 1;
-    if (lane == 0) g.rewards[(size_t)e * g.max_h + t] = r;
+    if (job == 0) n_rewards = t + 1;
+    else n_rewards_x = t + 1;
+    if (lane == 0) (job ? g.x_rewards : g.rewards)[(size_t)e * g.max_h + t] = r;
     // the expanded child's state goes to its pool slot
-    const int cs = (t == 0 && g.child_slot) ? g.child_slot[e] : -1;
+    const int cs = (t == 0 && job == 0 && g.child_slot) ? g.child_slot[e] : -1;
     if (cs >= 0 && active) {
       float* dst = g.pool + (size_t)cs * 13 * PS;
       if (part == 0) {
@@ -1167,15 +1206,35 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       }
     }
     wave_sync();
-    if (r >= 1.0f) break;
+    if (r >= 1.0f) {
+      if (job == 0) t_stop = t;
+      break;
+    }
   }
   }  // pushes
+  if (deferred) break;
+  // re-purposing: the extra simulation starts from its node's pool slot
+  if (job == 1 || !g.x_desc || t_stop < 0 || t_stop + 1 >= n_push) break;
+  n_push = n_push - t_stop - 1;
+  last_r = 0.0f;
+  if (active) {
+    const float* st = g.pool + (size_t)g.x_desc[e].x * 13 * PS;
+    if (part == 0) {
+      x = mk(st[0 * PS + b], st[1 * PS + b], st[2 * PS + b]);
+      v = mk(st[7 * PS + b], st[8 * PS + b], st[9 * PS + b]);
+    } else {
+      q0 = st[3 * PS + b]; q1 = st[4 * PS + b]; q2 = st[5 * PS + b]; q3 = st[6 * PS + b];
+      w = mk(st[10 * PS + b], st[11 * PS + b], st[12 * PS + b]);
+    }
+  }
+  }  // jobs
 
   if (deferred) {
     if (lane == 0) g.overflow_list[atomicAdd(g.overflow_count, 1)] = e;
     return;
   }
   if (rollout && lane == 0 && g.reward_count) g.reward_count[e] = n_rewards;
+  if (rollout && lane == 0 && g.x_count) g.x_count[e] = n_rewards_x;
   if (rollout && !g.write_state) {
     if (lane == 0) {
       g.env_status[e] = status;

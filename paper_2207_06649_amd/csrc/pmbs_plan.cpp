@@ -73,7 +73,9 @@ pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_stat
   if ((s = pmbs_pool_scatter(sim, slots.data(), 0)) != PMBS_OK) return s;
 
   std::vector<int32_t> actions((size_t)E * D), act_off(E + 1), src(E), child(E), tgt(E, target), counts(E);
-  std::vector<float> rewards((size_t)E * D);
+  std::vector<float> rewards((size_t)E * D), x_rewards((size_t)E * D);
+  std::vector<int32_t> x_src(E), x_act(E), x_node(E), x_rep(E), x_counts(E);
+  std::vector<uint64_t> x_seed(E, tc.seed);
   std::vector<uint32_t> status(E);
   std::vector<int64_t> stats((size_t)E * 3);
   int it = 0;
@@ -87,8 +89,20 @@ pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_stat
         PMBS_OK)
       return s;
     if (n_pairs == 0) break;
-    if ((s = pmbs_sim_rollout(sim, actions.data(), act_off.data(), src.data(), child.data(), tgt.data(), 0, n_substeps,
-                              width, sim->d_roll_rewards, D, sim->d_roll_counts, PMBS_ROLLOUT_QUEUE)) != PMBS_OK)
+    pmbs_repurpose rp{};
+    if (tc.repurpose) {
+      if ((s = pmbs_tree_extra(tree, x_src.data(), x_act.data(), x_node.data(), x_rep.data())) != PMBS_OK) return s;
+      rp.src_slot = x_src.data();
+      rp.action = x_act.data();
+      rp.node_id = x_node.data();
+      rp.replica = x_rep.data();
+      rp.seed = x_seed.data();
+      rp.d_rewards = sim->d_x_rewards;
+      rp.d_counts = sim->d_x_counts;
+    }
+    if ((s = pmbs_sim_rollout_ex(sim, actions.data(), act_off.data(), src.data(), child.data(), tgt.data(), 0,
+                                 n_substeps, width, sim->d_roll_rewards, D, sim->d_roll_counts, PMBS_ROLLOUT_QUEUE,
+                                 tc.repurpose ? &rp : nullptr)) != PMBS_OK)
       return s;
     hipError_t e = hipMemcpyAsync(rewards.data(), sim->d_roll_rewards, rewards.size() * sizeof(float),
                                   hipMemcpyDeviceToHost, sim->stream);
@@ -100,10 +114,19 @@ pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_stat
                          sim->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(stats.data(), sim->d_stats, stats.size() * sizeof(int64_t), hipMemcpyDeviceToHost, sim->stream);
+    if (e == hipSuccess && tc.repurpose)
+      e = hipMemcpyAsync(x_rewards.data(), sim->d_x_rewards, x_rewards.size() * sizeof(float), hipMemcpyDeviceToHost,
+                         sim->stream);
+    if (e == hipSuccess && tc.repurpose)
+      e = hipMemcpyAsync(x_counts.data(), sim->d_x_counts, x_counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         sim->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
     if (e != hipSuccess) return hip_fail(e, "plan readback");
     for (int k = 0; k < E; ++k) env_substeps += stats[(size_t)3 * k + 2];
-    if ((s = pmbs_tree_update(tree, rewards.data(), D, counts.data(), status.data(), nullptr)) != PMBS_OK) return s;
+    if ((s = pmbs_tree_update_ex(tree, rewards.data(), D, counts.data(), status.data(),
+                                 tc.repurpose ? x_rewards.data() : nullptr, tc.repurpose ? x_counts.data() : nullptr,
+                                 nullptr)) != PMBS_OK)
+      return s;
   }
   int32_t a = -1;
   double v = 0.0;

@@ -130,8 +130,9 @@ struct pmbs_server {
   std::thread worker;
   // packed launch buffers (worker only)
   std::vector<int32_t> actions, act_off, src, child, target, env_off, bc_base, counts, t_actions, t_off, t_src,
-      t_child;
-  std::vector<float> rewards;
+      t_child, x_src, x_act, x_node, x_rep, x_counts, tx_src, tx_act, tx_node, tx_rep;
+  std::vector<uint64_t> x_seed;
+  std::vector<float> rewards, x_rewards;
   std::vector<uint32_t> status;
   std::vector<int64_t> stats;
 
@@ -252,6 +253,7 @@ pmbs_status pmbs_server::start_requests(const std::vector<Request*>& fresh) {
     tc.n_dirs = 8;
     tc.seed = r->seed;
     tc.early_stop = cfg.early_stop;
+    tc.repurpose = cfg.repurpose;
     if ((s = pmbs_tree_create(&tc, r->nb, root_r[i], &r->tree)) != PMBS_OK) return s;
   }
   return PMBS_OK;
@@ -267,6 +269,11 @@ pmbs_status pmbs_server::pass() {
   target.clear();
   actions.clear();
   act_off.assign(1, 0);
+  x_src.clear();
+  x_act.clear();
+  x_node.clear();
+  x_rep.clear();
+  x_seed.clear();
   std::vector<Request*> done_now, in_launch;
   for (Request* r : active) {
     bool cancel;
@@ -295,6 +302,21 @@ pmbs_status pmbs_server::pass() {
     }
     r->env_begin = (int32_t)src.size();
     r->n_envs = n_envs;
+    if (cfg.repurpose) {
+      tx_src.resize(n_envs);
+      tx_act.resize(n_envs);
+      tx_node.resize(n_envs);
+      tx_rep.resize(n_envs);
+      if ((s = pmbs_tree_extra(r->tree, tx_src.data(), tx_act.data(), tx_node.data(), tx_rep.data())) != PMBS_OK)
+        return s;
+      for (int e = 0; e < n_envs; ++e) {
+        x_src.push_back(r->slot_base + tx_src[e]);
+        x_act.push_back(tx_act[e]);
+        x_node.push_back(tx_node[e]);
+        x_rep.push_back(tx_rep[e]);
+        x_seed.push_back(r->seed);
+      }
+    }
     for (int e = 0; e < n_envs; ++e) {
       env_off.push_back(env_off.back() + r->nb);
       bc_base.push_back(r->req_slot * kStride);
@@ -312,8 +334,19 @@ pmbs_status pmbs_server::pass() {
   pmbs_status s = set_layout(sim, E, env_off.data(), bc_base.data());
   if (s != PMBS_OK) return s;
   int32_t flags = PMBS_ROLLOUT_QUEUE | (cfg.graph ? PMBS_ROLLOUT_GRAPH : 0);
-  s = pmbs_sim_rollout(sim, actions.data(), act_off.data(), src.data(), child.data(), target.data(), 0,
-                       cfg.n_substeps, cfg.width, sim->d_roll_rewards, D, sim->d_roll_counts, flags);
+  pmbs_repurpose rp{};
+  if (cfg.repurpose) {
+    rp.src_slot = x_src.data();
+    rp.action = x_act.data();
+    rp.node_id = x_node.data();
+    rp.replica = x_rep.data();
+    rp.seed = x_seed.data();
+    rp.d_rewards = sim->d_x_rewards;
+    rp.d_counts = sim->d_x_counts;
+  }
+  s = pmbs_sim_rollout_ex(sim, actions.data(), act_off.data(), src.data(), child.data(), target.data(), 0,
+                          cfg.n_substeps, cfg.width, sim->d_roll_rewards, D, sim->d_roll_counts, flags,
+                          cfg.repurpose ? &rp : nullptr);
   if (s != PMBS_OK) return s;
   rewards.resize((size_t)E * D);
   counts.resize(E);
@@ -328,12 +361,24 @@ pmbs_status pmbs_server::pass() {
     e = hipMemcpyAsync(status.data(), sim->d_status, (size_t)E * sizeof(uint32_t), hipMemcpyDeviceToHost, sim->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(stats.data(), sim->d_stats, (size_t)E * 3 * sizeof(int64_t), hipMemcpyDeviceToHost, sim->stream);
+  if (cfg.repurpose) {
+    x_rewards.resize((size_t)E * D);
+    x_counts.resize(E);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(x_rewards.data(), sim->d_x_rewards, x_rewards.size() * sizeof(float), hipMemcpyDeviceToHost,
+                         sim->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(x_counts.data(), sim->d_x_counts, (size_t)E * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         sim->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
   if (e != hipSuccess) return hip_fail(e, "server read-back");
   int64_t total = 0;
   for (Request* r : in_launch) {
     const int b0 = r->env_begin;
-    s = pmbs_tree_update(r->tree, rewards.data() + (size_t)b0 * D, D, counts.data() + b0, status.data() + b0, nullptr);
+    s = pmbs_tree_update_ex(r->tree, rewards.data() + (size_t)b0 * D, D, counts.data() + b0, status.data() + b0,
+                            cfg.repurpose ? x_rewards.data() + (size_t)b0 * D : nullptr,
+                            cfg.repurpose ? x_counts.data() + b0 : nullptr, nullptr);
     if (s != PMBS_OK) return s;
     int64_t sub = 0;
     for (int k = b0; k < b0 + r->n_envs; ++k) sub += stats[(size_t)3 * k + 2];

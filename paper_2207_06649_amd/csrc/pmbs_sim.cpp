@@ -41,7 +41,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
   size_t state, bconst, env_offset, push, status, target, reward, clearance, slots, stats, pool;
   size_t actions, act_offset, src_slot, child_slot, order, roll_rewards, roll_counts;
-  size_t ctl, ovf4, ovf8, bc_base, total;
+  size_t ctl, ovf4, ovf8, bc_base, x_desc, x_key, x_rewards, x_counts, total;
 };
 
 static Layout layout_of(const pmbs_sim_config& c) {
@@ -75,6 +75,10 @@ static Layout layout_of(const pmbs_sim_config& c) {
   L.ovf4 = take(ne * sizeof(int32_t));
   L.ovf8 = take(ne * sizeof(int32_t));
   L.bc_base = take(ne * sizeof(int32_t));
+  L.x_desc = take(ne * 4 * sizeof(int32_t));
+  L.x_key = take(ne * 2 * sizeof(uint32_t));
+  L.x_rewards = take(ne * (size_t)c.max_horizon * sizeof(float));
+  L.x_counts = take(ne * sizeof(int32_t));
   L.total = o;
   return L;
 }
@@ -462,6 +466,10 @@ pmbs_status pmbs_sim_create(const pmbs_sim_config* cfg, void* d_workspace, size_
   s->d_ovf4 = reinterpret_cast<int32_t*>(base + L.ovf4);
   s->d_ovf8 = reinterpret_cast<int32_t*>(base + L.ovf8);
   s->d_bc_base = reinterpret_cast<int32_t*>(base + L.bc_base);
+  s->d_x_desc = reinterpret_cast<int32_t*>(base + L.x_desc);
+  s->d_x_key = reinterpret_cast<uint32_t*>(base + L.x_key);
+  s->d_x_rewards = reinterpret_cast<float*>(base + L.x_rewards);
+  s->d_x_counts = reinterpret_cast<int32_t*>(base + L.x_counts);
   s->plan.small_max_bodies = 16;
   s->plan.small_blocks_per_cu = 0;
   s->plan.large_blocks_per_cu = 0;
@@ -597,6 +605,14 @@ pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int3
                              const int32_t* child_slot, const int32_t* target, int32_t inputs_on_device,
                              int32_t n_substeps, float width, float* d_rewards, int32_t max_h,
                              int32_t* d_reward_count, int32_t flags) {
+  return pmbs_sim_rollout_ex(sim, actions, act_offset, src_slot, child_slot, target, inputs_on_device, n_substeps, width,
+                             d_rewards, max_h, d_reward_count, flags, nullptr);
+}
+
+pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const int32_t* act_offset,
+                                const int32_t* src_slot, const int32_t* child_slot, const int32_t* target,
+                                int32_t inputs_on_device, int32_t n_substeps, float width, float* d_rewards,
+                                int32_t max_h, int32_t* d_reward_count, int32_t flags, const pmbs_repurpose* rp) {
   if (!sim || !actions || !act_offset || !target || !d_rewards) return fail(PMBS_ERR_INVALID_ARG, "null argument");
   if (n_substeps < 0 || !(width > 0)) return fail(PMBS_ERR_INVALID_ARG, "n_substeps must be >= 0 and width > 0");
   const int n = sim->n_envs;
@@ -605,6 +621,19 @@ pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int3
   if (use_queue && inputs_on_device) return fail(PMBS_ERR_INVALID_ARG, "the work queue orders host inputs");
   if (sim->pool_layout && (inputs_on_device || !src_slot || (flags & PMBS_ROLLOUT_WRITE_STATE)))
     return fail(PMBS_ERR_INVALID_ARG, "a pool-only layout needs host source slots and no state write-back");
+  if (rp) {
+    if (!rp->src_slot || !rp->action || !rp->node_id || !rp->replica || !rp->seed || !rp->d_rewards || !rp->d_counts)
+      return fail(PMBS_ERR_INVALID_ARG, "re-purposing needs every descriptor array and both outputs");
+    if (inputs_on_device || !src_slot || (flags & PMBS_ROLLOUT_WRITE_STATE) || !sim->d_pool)
+      return fail(PMBS_ERR_INVALID_ARG, "re-purposing needs host inputs, source slots, a pool and no state write-back");
+    for (int e = 0; e < sim->n_envs; ++e) {
+      const int nb = sim->host_offset[e + 1] - sim->host_offset[e];
+      if (rp->src_slot[e] < 0 || rp->src_slot[e] >= sim->cfg.pool_slots)
+        return fail(PMBS_ERR_CAPACITY, "env %d: extra source slot %d", e, rp->src_slot[e]);
+      if (rp->action[e] < 0 || rp->action[e] >= nb * 8 || rp->replica[e] < 0 || rp->replica[e] >= (1 << 24))
+        return fail(PMBS_ERR_INVALID_ARG, "env %d: extra action or replica out of range", e);
+    }
+  }
   int total = 0;
   std::vector<int32_t> order, order_large;
   if (!inputs_on_device) {
@@ -662,6 +691,29 @@ pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int3
         PMBS_OK)
       return st;
     if ((st = stage_ints(sim, counts, 2, 0, sim->d_ctl + 8, &p)) != PMBS_OK) return st;
+  }
+  std::vector<int32_t> xdesc;
+  std::vector<uint32_t> xkey;
+  if (rp && n > 0) {
+    xdesc.resize((size_t)4 * n);
+    xkey.resize((size_t)2 * n);
+    for (int e = 0; e < n; ++e) {
+      xdesc[4 * e + 0] = rp->src_slot[e];
+      xdesc[4 * e + 1] = rp->action[e];
+      xdesc[4 * e + 2] = rp->node_id[e];
+      xdesc[4 * e + 3] = rp->replica[e];
+      xkey[2 * e + 0] = (uint32_t)rp->seed[e];
+      xkey[2 * e + 1] = (uint32_t)(rp->seed[e] >> 32);
+    }
+    hipError_t e = hipMemcpyAsync(sim->d_x_desc, xdesc.data(), xdesc.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  sim->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(sim->d_x_key, xkey.data(), xkey.size() * sizeof(uint32_t), hipMemcpyHostToDevice, sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "re-purposing upload");
+    a.x_desc = reinterpret_cast<const int4*>(sim->d_x_desc);
+    a.x_key = reinterpret_cast<const uint2*>(sim->d_x_key);
+    a.x_rewards = rp->d_rewards;
+    a.x_count = rp->d_counts;
   }
   if (!inputs_on_device) {
     hipError_t e = hipStreamSynchronize(sim->stream);

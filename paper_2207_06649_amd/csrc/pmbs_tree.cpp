@@ -223,9 +223,34 @@ pmbs_status pmbs_tree_select(pmbs_tree_t* t, int32_t* n_pairs, int32_t* actions,
   return PMBS_OK;
 }
 
+pmbs_status pmbs_tree_extra(const pmbs_tree_t* t, int32_t* src_slot, int32_t* action, int32_t* node_id,
+                            int32_t* replica) {
+  if (!t || !src_slot || !action || !node_id || !replica) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (!t->pending) return fail(PMBS_ERR_INVALID_ARG, "no selection pending");
+  const int P = (int)t->pair_node.size(), E = (int)t->env_pair.size();
+  const int R = (E + P - 1) / P;
+  for (int e = 0; e < E; ++e) {
+    const int q = (t->env_pair[e] + 1) % P;
+    const Node& n = t->nodes[t->pair_node[q]];
+    src_slot[e] = n.slot;
+    action[e] = t->pair_action[q];
+    node_id[e] = n.id;
+    replica[e] = R + e;
+  }
+  return PMBS_OK;
+}
+
 pmbs_status pmbs_tree_update(pmbs_tree_t* t, const float* rewards, int32_t max_h, const int32_t* counts,
                              const uint32_t* env_status, int32_t* n_children) {
+  return pmbs_tree_update_ex(t, rewards, max_h, counts, env_status, nullptr, nullptr, n_children);
+}
+
+pmbs_status pmbs_tree_update_ex(pmbs_tree_t* t, const float* rewards, int32_t max_h, const int32_t* counts,
+                                const uint32_t* env_status, const float* extra_rewards, const int32_t* extra_counts,
+                                int32_t* n_children) {
   if (!t || !rewards || !counts || !env_status) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if ((extra_rewards == nullptr) != (extra_counts == nullptr))
+    return fail(PMBS_ERR_INVALID_ARG, "extra rewards and counts go together");
   if (!t->pending) return fail(PMBS_ERR_INVALID_ARG, "no selection pending");
   const int P = (int)t->pair_node.size(), E = (int)t->env_pair.size();
   const double gamma = t->cfg.gamma;
@@ -239,6 +264,17 @@ pmbs_status pmbs_tree_update(pmbs_tree_t* t, const float* rewards, int32_t max_h
     for (int tt = 0; tt < counts[e] && tt < max_h; ++tt)
       g = std::fmax(g, std::pow(gamma, (double)tt) * (double)rewards[(size_t)e * max_h + tt]);
     best[p] = std::fmax(best[p], g);
+  }
+  if (extra_rewards) {
+    // re-purposed environments: an extra simulation of pair (p + 1) mod P
+    for (int e = 0; e < E; ++e) {
+      if (extra_counts[e] < 1) continue;
+      const int q = (t->env_pair[e] + 1) % P;
+      double g = -INFINITY;
+      for (int tt = 0; tt < extra_counts[e] && tt < max_h; ++tt)
+        g = std::fmax(g, std::pow(gamma, (double)tt) * (double)extra_rewards[(size_t)e * max_h + tt]);
+      best[q] = std::fmax(best[q], g);
+    }
   }
   int made = 0;
   for (int p = 0; p < P; ++p) {

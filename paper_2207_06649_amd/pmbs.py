@@ -34,6 +34,11 @@ class LaunchPlan(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class Repurpose(C.Structure):
+    _fields_ = [("src_slot", C.c_void_p), ("action", C.c_void_p), ("node_id", C.c_void_p), ("replica", C.c_void_p),
+                ("seed", C.c_void_p), ("d_rewards", C.c_void_p), ("d_counts", C.c_void_p)]
+
+
 class SimConfig(C.Structure):
     _fields_ = [("max_envs", C.c_int32), ("max_bodies", C.c_int32), ("max_contacts", C.c_int32),
                 ("solver_iters", C.c_int32), ("pool_slots", C.c_int32), ("pool_stride", C.c_int32),
@@ -85,6 +90,8 @@ def lib():
         L.pmbs_sim_autotune.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, C.c_float, vp, C.c_int32, vp, C.c_int32,
                                         C.c_int32, C.c_char_p, C.POINTER(LaunchPlan), C.POINTER(C.c_float),
                                         C.POINTER(C.c_int32)]
+        L.pmbs_sim_rollout_ex.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_float, vp, C.c_int32,
+                                          vp, C.c_int32, C.POINTER(Repurpose)]
         L.pmbs_sim_rollout.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_float, vp, C.c_int32,
                                        vp, C.c_int32]
         L.pmbs_sim_shape.argtypes = [vp, ip, ip]
@@ -269,7 +276,7 @@ class Sim:
         return off, acts, tg, mh, ss, cs
 
     def rollout(self, actions, act_offset, target, n_substeps=120, width=0.08, src_slot=None, child_slot=None,
-                max_h=None, flags=ROLLOUT_WRITE_STATE, sync=True, rewards=None, counts=None):
+                max_h=None, flags=ROLLOUT_WRITE_STATE, sync=True, rewards=None, counts=None, repurpose=None):
         """Contour-push rollouts (host int inputs).  Returns (rewards [E, max_h],
         counts [E]) as numpy when sync, else the device tensors.  rewards /
         counts may be given as device tensors to reuse (a captured graph is
@@ -281,12 +288,25 @@ class Sim:
         if tuple(rew.shape) != (self.n_envs, mh) or rew.dtype != t.float32 or cnt.numel() < self.n_envs:
             raise PmbsError("rewards must be float32 [n_envs, max_h] and counts int32 [n_envs]")
         ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
-        _check(lib().pmbs_sim_rollout(self.handle, ptr(acts), ptr(off), ptr(ss), ptr(cs), ptr(tg), 0, int(n_substeps),
-                                      float(width), _ptr(rew), mh, _ptr(cnt), int(flags)))
-        if not sync:
-            return rew, cnt
+        if repurpose is None:
+            _check(lib().pmbs_sim_rollout(self.handle, ptr(acts), ptr(off), ptr(ss), ptr(cs), ptr(tg), 0,
+                                          int(n_substeps), float(width), _ptr(rew), mh, _ptr(cnt), int(flags)))
+            if not sync:
+                return rew, cnt
+            self.sync()
+            return rew.cpu().numpy(), cnt.cpu().numpy()
+        # re-purposing: descriptors (host, per env) and the extra outputs
+        xs = {k: np.ascontiguousarray(repurpose[k], np.int32) for k in ("src_slot", "action", "node_id", "replica")}
+        seed = np.ascontiguousarray(np.broadcast_to(np.asarray(repurpose["seed"], np.uint64), (self.n_envs,)))
+        xrew = t.full((self.n_envs, mh), -1.0, dtype=t.float32, device=self.device)
+        xcnt = t.zeros(self.n_envs, dtype=t.int32, device=self.device)
+        rp = Repurpose(ptr(xs["src_slot"]), ptr(xs["action"]), ptr(xs["node_id"]), ptr(xs["replica"]), ptr(seed),
+                       _ptr(xrew), _ptr(xcnt))
+        _check(lib().pmbs_sim_rollout_ex(self.handle, ptr(acts), ptr(off), ptr(ss), ptr(cs), ptr(tg), 0,
+                                         int(n_substeps), float(width), _ptr(rew), mh, _ptr(cnt), int(flags),
+                                         C.byref(rp)))
         self.sync()
-        return rew.cpu().numpy(), cnt.cpu().numpy()
+        return rew.cpu().numpy(), cnt.cpu().numpy(), xrew.cpu().numpy(), xcnt.cpu().numpy()
 
     def set_launch_plan(self, small_max_bodies=16, small_blocks_per_cu=0, large_blocks_per_cu=0, order=1):
         p = LaunchPlan(small_max_bodies, small_blocks_per_cu, large_blocks_per_cu, order)
@@ -321,7 +341,7 @@ class Sim:
 class TreeConfig(C.Structure):
     _fields_ = [("c", C.c_double), ("gamma", C.c_double), ("max_depth", C.c_int32), ("n_envs", C.c_int32),
                 ("max_nodes", C.c_int32), ("n_dirs", C.c_int32), ("seed", C.c_uint64), ("sim_depth", C.c_int32),
-                ("early_stop", C.c_int32)]
+                ("early_stop", C.c_int32), ("repurpose", C.c_int32)]
 
 
 class NodeInfo(C.Structure):
@@ -351,6 +371,8 @@ def _tree_lib():
         L.pmbs_tree_node.argtypes = [vp, C.c_int32, C.POINTER(NodeInfo)]
         L.pmbs_tree_size.argtypes = [vp, vp, vp, vp]
         L.pmbs_tree_status.argtypes = [vp, vp, vp, vp, vp]
+        L.pmbs_tree_extra.argtypes = [vp, vp, vp, vp, vp]
+        L.pmbs_tree_update_ex.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, vp]
         L.pmbs_plan.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_float,
                                 C.POINTER(PlanResult)]
         L._tree_ready = True
@@ -401,14 +423,24 @@ class Tree:
                     actions=self._acts[:self._off[E]].copy() if E else np.zeros(0, np.int32),
                     src_slot=self._src[:E].copy(), child_slot=self._child[:E].copy())
 
-    def update(self, rewards, counts, status):
+    def update(self, rewards, counts, status, extra_rewards=None, extra_counts=None):
         rw = np.ascontiguousarray(rewards, np.float32)
         ct = np.ascontiguousarray(counts, np.int32)
         stt = np.ascontiguousarray(status, np.uint32)
+        xr = None if extra_rewards is None else np.ascontiguousarray(extra_rewards, np.float32)
+        xc = None if extra_counts is None else np.ascontiguousarray(extra_counts, np.int32)
         made = C.c_int32(0)
-        _check(_tree_lib().pmbs_tree_update(self.handle, _np_ptr(rw), rw.shape[1], _np_ptr(ct), _np_ptr(stt),
-                                            C.byref(made)))
+        _check(_tree_lib().pmbs_tree_update_ex(self.handle, _np_ptr(rw), rw.shape[1], _np_ptr(ct), _np_ptr(stt),
+                                               None if xr is None else _np_ptr(xr),
+                                               None if xc is None else _np_ptr(xc), C.byref(made)))
         return made.value
+
+    def extra(self, n_envs: int) -> dict:
+        """Re-purposing descriptors of the last selection (per env)."""
+        out = {k: np.zeros(n_envs, np.int32) for k in ("src_slot", "action", "node_id", "replica")}
+        _check(_tree_lib().pmbs_tree_extra(self.handle, *(_np_ptr(out[k]) for k in ("src_slot", "action", "node_id",
+                                                                                     "replica"))))
+        return out
 
     def best(self):
         a, v, n = C.c_int32(0), C.c_double(0), C.c_int64(0)
@@ -480,7 +512,7 @@ class ServerConfig(C.Structure):
     _fields_ = [("sim", SimConfig), ("max_envs", C.c_int32), ("max_requests", C.c_int32),
                 ("pool_slots", C.c_int32), ("max_depth", C.c_int32), ("n_substeps", C.c_int32),
                 ("width", C.c_float), ("c", C.c_double), ("gamma", C.c_double), ("hbm_budget", C.c_int64),
-                ("graph", C.c_int32), ("early_stop", C.c_int32)]
+                ("graph", C.c_int32), ("early_stop", C.c_int32), ("repurpose", C.c_int32)]
 
 
 class Request(C.Structure):

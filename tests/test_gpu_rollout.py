@@ -125,3 +125,48 @@ def test_rollout_early_stop_at_reward_one(pm):
     rew, cnt = sim.rollout(acts, [0, 3], [0], n_substeps=20)
     ref = O.rollout(CFG, f32(st), f32(bd), [(1, 0), (2, 3), (1, 4)], 20, 0)
     assert cnt[0] == 1 == ref["applied"] and rew[0, 0] == 1.0
+
+
+def test_repurposed_envs_run_extra_simulations(pm):
+    """An env whose rollout reaches reward 1 with pushes left runs one extra
+    simulation from its descriptor's pool slot: its first push, then random
+    pushes from Philox4x32-10 (the published generator of the tree oracle);
+    rewards and counts match the FP64 oracle's rollout of those actions."""
+    from oracle import tree_oracle as T
+    st = np.zeros((3, 13))
+    bd = np.zeros((3, 5))
+    for i, (x, y, hx) in enumerate([(0.0, 0.0, 0.02), (0.105, 0.004, 0.018), (-0.2, 0.03, 0.02)]):
+        st[i, :3] = (x, y, 0.02)
+        st[i, 3] = 1.0
+        bd[i] = (hx, 0.021, 0.02, 0.1, 0.5)
+    n, E, H, sub, seed = 3, 6, 4, 60, 42
+    b = scenes.concat([scenes.Batch(np.array([0, n], np.int32), st, bd, np.zeros((1, 4)), np.zeros(1, np.int32))] * E)
+    sim = pm.Sim(max_envs=E, max_bodies=E * n, pool_slots=E, pool_stride=n, max_horizon=H)
+    sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+    slots = np.arange(E, dtype=np.int32)
+    sim.pool_scatter(slots)
+    # env 0, 2, 4 push the near cube away first (reward 1 at once); 1, 3, 5 do not
+    seqs = [[12, 1, 2, 3], [17, 5, 6, 0], [12, 4, 4], [9, 3, 2, 1], [12, 20, 21, 22], [3]]
+    acts = np.array([a for q in seqs for a in q], np.int32)
+    off = np.r_[0, np.cumsum([len(q) for q in seqs])].astype(np.int32)
+    rp = dict(src_slot=slots[::-1].copy(), action=np.array([1, 8, 16, 9, 2, 0], np.int32),
+              node_id=np.arange(E, dtype=np.int32) + 7, replica=np.arange(E, dtype=np.int32) + 100, seed=seed)
+    rew, cnt, xrew, xcnt = sim.rollout(acts, off, np.zeros(E, np.int32), n_substeps=sub, src_slot=slots, max_h=H,
+                                       flags=pm.ROLLOUT_QUEUE, repurpose=rp)
+    ran = 0
+    for e in range(E):
+        r = O.rollout(CFG, f32(st), f32(bd), [(a // 8, a % 8) for a in seqs[e]], sub, 0, 0.08)
+        k = r["applied"]
+        assert cnt[e] == k and np.abs(rew[e, :k] - r["rewards"]).max(initial=0) <= 2e-5
+        if r["valid"][0] and k < len(seqs[e]) and r["rewards"][-1] >= 1.0:
+            budget = len(seqs[e]) - k
+            a0 = int(rp["action"][e])
+            xs = [a0] + [T.rollout_action(int(rp["node_id"][e]), a0, int(rp["replica"][e]), t, n * 8, seed)
+                         for t in range(1, budget)]
+            rx = O.rollout(CFG, f32(st), f32(bd), [(a // 8, a % 8) for a in xs], sub, 0, 0.08)
+            kx = rx["applied"]
+            assert xcnt[e] == kx and np.abs(xrew[e, :kx] - rx["rewards"]).max(initial=0) <= 2e-5, (e, xrew[e], rx)
+            ran += kx > 1
+        else:
+            assert xcnt[e] == 0
+    assert ran >= 1   # at least one extra simulation drew random pushes

@@ -265,3 +265,31 @@ def test_early_stop_waits_for_the_level_of_a_deeper_graspable_node():
     before = run(p.iterations - 1)
     assert not before.done()
     assert before.root.untried or not any(g.depth <= before.es_level for g in before.graspable)
+
+
+def test_repurposed_environment_runs_an_extra_replica_of_the_next_pair():
+    """Leaf parallelisation with re-purposing, worked by hand: two root
+    actions, two environments, depth 3.  The environment of the first pair
+    reaches reward 1 on its first push, so its two remaining pushes go to
+    one extra simulation of the second pair (replica R + e = 1 + 0), whose
+    random push differs from the static replica's; its return joins the
+    second pair's maximum."""
+    for seed in range(50):
+        order = T.shuffled_actions(2, 0, seed)
+        a0, a1 = order
+        z_static = T.rollout_action(0, a1, 0, 1, 2, seed)
+        z_extra = T.rollout_action(0, a1, 1, 1, 2, seed)
+        if z_static != z_extra:
+            break
+    base = lambda h: 0.5 if (len(h) == 2 and h[0] == a1 and h[1] == z_extra) else 0.0
+    env = ToyEnv(k=2, lock=(a0,), base=base)
+    p = T.Planner(env, (), n_envs=2, depth=3, seed=seed, repurpose=True)
+    p.iterate()
+    assert p.extra_simulations == 1
+    assert env.calls[-1] == ((), (a1, z_extra))
+    ch = {c.action: c for c in p.root.children}
+    # the second pair's static replica scores 0 everywhere; the extra scores 0.5 after its 2nd push
+    assert ch[a1].Q == 0.8 * 0.5 and ch[a0].Q == 1.0
+    q = T.Planner(ToyEnv(k=2, lock=(a0,), base=base), (), n_envs=2, depth=3, seed=seed, repurpose=False)
+    q.iterate()
+    assert q.extra_simulations == 0 and {c.action: c for c in q.root.children}[a1].Q == 0.0

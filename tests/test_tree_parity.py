@@ -51,9 +51,13 @@ def run_library_tree(env, n_objects, n_dirs, iters, **cfg):
         status = np.zeros(E, np.uint32)
         off, acts = sel["act_offset"], sel["actions"]
         trace.append([(int(sel["src_slot"][e]), tuple(acts[off[e]:off[e + 1]])) for e in range(E)])
+        xr = np.zeros((E, D), np.float32)
+        xc = np.zeros(E, np.int32)
+        x = tree.extra(E) if cfg.get("repurpose") else None
         for e in range(E):
             h = hist[int(sel["src_slot"][e])]
-            valid, child, rw = env.run(h, list(acts[off[e]:off[e + 1]]))
+            seq = list(acts[off[e]:off[e + 1]])
+            valid, child, rw = env.run(h, seq)
             if not valid:
                 status[e] = pmbs.PMBS_ENV_PUSH_INVALID
                 continue
@@ -61,13 +65,27 @@ def run_library_tree(env, n_objects, n_dirs, iters, **cfg):
             rewards[e, :len(rw)] = rw
             if sel["child_slot"][e] >= 0:
                 hist[int(sel["child_slot"][e])] = child
-        tree.update(rewards, counts, status)
+            if x is not None and rw[-1] >= 1.0 and len(rw) < len(seq):
+                # what the device does for a re-purposed env (random pushes from the
+                # published Philox definition)
+                a0, nid, rep = int(x["action"][e]), int(x["node_id"][e]), int(x["replica"][e])
+                xs = [a0] + [T.rollout_action(nid, a0, rep, t, n_objects * n_dirs, cfg["seed"])
+                             for t in range(1, len(seq) - len(rw))]
+                v2, _, rw2 = env.run(hist[int(x["src_slot"][e])], xs)
+                if v2:
+                    xc[e] = len(rw2)
+                    xr[e, :len(rw2)] = rw2
+        if x is not None:
+            tree.update(rewards, counts, status, xr, xc)
+        else:
+            tree.update(rewards, counts, status)
     return tree, hist, trace
 
 
 def run_oracle_tree(env, iters, **cfg):
     p = T.Planner(env, (), n_envs=cfg["n_envs"], c=cfg["c"], gamma=cfg["gamma"], depth=cfg["max_depth"],
-                  seed=cfg["seed"], sim_depth=cfg.get("sim_depth", 0), early_stop=bool(cfg.get("early_stop", 0)))
+                  seed=cfg["seed"], sim_depth=cfg.get("sim_depth", 0), early_stop=bool(cfg.get("early_stop", 0)),
+                  repurpose=bool(cfg.get("repurpose", 0)))
     for _ in range(iters):
         if p.done() or not p.iterate():
             break
@@ -86,7 +104,8 @@ def oracle_nodes(p):
 @pytest.mark.parametrize("n_envs,depth,iters,seed,extra", [
     (1, 4, 30, 7, {}), (4, 3, 12, 1, {}), (16, 4, 8, 3, {}), (64, 5, 5, 9, {}),
     (4, 3, 12, 1, dict(sim_depth=2)), (1, 4, 40, 7, dict(early_stop=1)), (8, 5, 20, 2, dict(early_stop=1)),
-    (16, 4, 20, 5, dict(early_stop=1, sim_depth=1))])
+    (16, 4, 20, 5, dict(early_stop=1, sim_depth=1)), (8, 4, 10, 3, dict(repurpose=1)),
+    (3, 5, 15, 5, dict(repurpose=1, sim_depth=1)), (16, 4, 12, 0, dict(repurpose=1, early_stop=1))])
 def test_library_tree_matches_oracle(n_envs, depth, iters, seed, extra):
     base = lambda h: 0.03 * ((sum(h) * 7 + len(h)) % 9)
     env = Toy(k=6, lock=(5, 0, 3), base=base, invalid={2})
@@ -109,6 +128,8 @@ def test_library_tree_matches_oracle(n_envs, depth, iters, seed, extra):
     assert a == b.action and v == b.Q / b.N and visits == b.N
     st = tree.status()
     assert st["done"] == p.done() and st["level"] == p.es_level and st["d_tree"] == p.D and st["d_sim"] == p.Ds
+    if extra.get("repurpose"):
+        assert p.extra_simulations > 0   # the case does re-purpose environments
 
 
 def test_library_selection_unique_pairs_and_fill():
