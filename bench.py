@@ -483,6 +483,12 @@ def main() -> int:
         t1 = time.perf_counter()
         O.step(cfg, batch.env_offset, st, bd, ps, args.substeps, n_threads=th)
         dt = time.perf_counter() - t1
+        # one host thread on the first 256 envs (envs are independent)
+        n1 = min(256, E)
+        o1 = int(batch.env_offset[n1])
+        t2 = time.perf_counter()
+        O.step(cfg, batch.env_offset[:n1 + 1], st[:o1], bd[:o1], ps[:n1], args.substeps, n_threads=1)
+        dt1 = time.perf_counter() - t2
         out["cpu_baseline"] = {
             "value": round(env_substeps / dt, 1),
             "unit": "env-substeps/s",
@@ -490,6 +496,8 @@ def main() -> int:
             "kind": "oracle",
             "sample": f"the full workload once ({E} envs x {args.bodies} cuboids, one {args.substeps}-substep "
                       f"push each) in the FP64 oracle on {th} host threads, {dt:.2f} s wall",
+            "single_core": {"value": round(n1 * args.substeps / dt1, 1), "unit": "env-substeps/s",
+                            "sample": f"the first {n1} envs on 1 host thread, {dt1:.2f} s wall"},
         }
 
     print(json.dumps(out), flush=True)

@@ -426,7 +426,9 @@ pmbs_status pmbs_brute_force(pmbs_sim_t* sim, const float* root_state, const flo
  * several trees packed into one rollout launch).  Requests that arrive
  * while others run join at the next iteration boundary; a finished
  * request frees its slots at once.  A request's result does not depend on
- * which other requests shared its launches. */
+ * which other requests shared its launches.  The client calls (submit, poll, wait, cancel,
+ * stats) may come from any host threads; pmbs_server_destroy must not
+ * overlap any of them. */
 typedef struct pmbs_server_config {
   pmbs_sim_config sim;    /* physics and contact class (max_contacts, solver_iters, ...); its sizes are
                              derived from the fields below */
