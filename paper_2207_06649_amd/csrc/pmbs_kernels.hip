@@ -93,7 +93,14 @@ __device__ __forceinline__ int wave_excl_scan_bits(int x, int bits, int* total) 
   return prefix;
 }
 
-__device__ __forceinline__ void wave_sync() { __syncthreads(); }
+// Orders the LDS accesses of the wave's lanes around this point.  A
+// workgroup is one wave and a wave's LDS operations are performed in issue
+// order, so a wavefront-scope fence (no wait instruction) plus a
+// code-motion barrier suffices; no wait for outstanding LDS operations.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 // ------------------------------------------------------------------ LDS layout
 // Hardware reciprocal and reciprocal square root (about 1 ulp), used where
