@@ -346,8 +346,8 @@ def main() -> int:
                     help="size of a plain device copy run after the timed region (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(environments shard across GPUs with no exchange inside a step; see the design notes)",
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(environments would shard across GPUs with no exchange inside a step)",
               file=sys.stderr)
         return 2
 

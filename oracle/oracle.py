@@ -31,8 +31,8 @@ class Config(C.Structure):
                 ("iters", C.c_int32), ("max_contacts", C.c_int32)]
 
 
-# The readings of the constants the paper leaves open (each listed with its
-# reason in the design notes): gravity along -z, contact margin 2 mm,
+# The readings of the constants the paper leaves open: gravity along -z,
+# contact margin 2 mm,
 # Baumgarte 0.2 with 0.5 mm slop, friction 0.5 for plane and pusher, a
 # 2x2x4 cm kinematic pusher 2 mm above the plane, 0.1 m/s pushes of 5 cm
 # (Sec. V-A) starting 5 mm off the contour, SAT hysteresis 1e-5 / 5e-4 m,

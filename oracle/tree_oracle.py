@@ -36,7 +36,7 @@ What it follows in the paper:
     R + e (R = ceil(N_e / P) static replicas, e the environment), truncated
     to the budget.  A valid extra simulation joins pair p''s maximum.
 
-Readings where the paper is silent (listed in the design notes): a node is
+Readings where the paper is silent: a node is
 a leaf for Alg. 2 when its depth is below D and it has an untried action,
 and selection stops early when no node is selectable; the reward of a
 simulation is G = max_t gamma^t r_t over its pushes (t = 0: the expanded
