@@ -206,3 +206,26 @@ def test_packed_matches_plain_padded_per_push(pm):
         assert np.array_equal(rew[e, :k], prew[e, :k]), e
         lo, hi = b.env_offset[e], b.env_offset[e + 1]
         assert np.array_equal(st[lo:hi], pst[30 * e:30 * e + (hi - lo)]), e
+
+
+def test_two_level_fallback_reaches_the_512_contact_kernel(pm):
+    """A 30-cube touching grid (about 400 contacts) overflows both the 128-
+    and the 256-contact kernels: with max_contacts 512 it finishes in the
+    512-contact kernel, bitwise equal to a plain 512-contact launch, eagerly
+    and replayed as a graph."""
+    b, acts, off, tgt = uneven_case(13, 20, n_bodies=(5, 12), region=0.3, n_grid=0)
+    b = scenes.concat([b, grid_env(n=30, cols=6)])
+    acts = np.concatenate([acts, np.array([4, 4], np.int32)])
+    off = np.concatenate([off, [off[-1] + 2]]).astype(np.int32)
+    tgt = np.concatenate([tgt, [0]]).astype(np.int32)
+    ref = Run(pm, b, 512).go(acts, off, tgt, SUB, 0)
+    r = Run(pm, b, 512)
+    r.sim.set_launch_plan(small_max_bodies=31)
+    for flags in (pm.ROLLOUT_QUEUE, pm.ROLLOUT_QUEUE | pm.ROLLOUT_GRAPH, pm.ROLLOUT_QUEUE | pm.ROLLOUT_GRAPH):
+        r.rew.fill_(-3.0)
+        got = r.go(acts, off, tgt, SUB, flags)
+        for e in range(b.n_envs):
+            assert env_equal(b, e, got, ref), (flags, e)
+    c128 = Run(pm, b, 128).go(acts, off, tgt, SUB, 0)
+    c256 = Run(pm, b, 256).go(acts, off, tgt, SUB, 0)
+    assert c128[2][-1] & 1 and c256[2][-1] & 1 and not (ref[2][-1] & 1)

@@ -38,12 +38,13 @@ def same(a, b):
     return all(a[k] == b[k] for k in KEYS) and a["push"] == b["push"] and a["status"] == b["status"] == 0
 
 
-def test_result_alone_equals_result_in_the_mix(pm):
+@pytest.mark.parametrize("flags", [{}, dict(early_stop=1, repurpose=1)])
+def test_result_alone_equals_result_in_the_mix(pm, flags):
     reqs = requests()
-    srv = small_server(pm)
+    srv = small_server(pm, **flags)
     alone = [srv.wait(srv.submit(**q)) for q in reqs]
     srv.close()
-    srv = small_server(pm)
+    srv = small_server(pm, **flags)
     ids = [srv.submit(**q) for q in reqs]
     mixed = [srv.wait(i) for i in ids]
     st = srv.stats()
