@@ -542,18 +542,6 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     h = mk(bc[0 * BN + bi], bc[1 * BN + bi], bc[2 * BN + bi]);
     mu = bc[7 * BN + bi];
   }
-  if (lane == 0) {
-    s.pos[PLANE] = make_float4(0, 0, 0, 0);
-    s.col[0][PLANE] = make_float4(1, 0, 0, 0);
-    s.col[1][PLANE] = make_float4(0, 1, 0, 0);
-    s.col[2][PLANE] = make_float4(0, 0, 1, 0);
-    s.half[PLANE] = make_float4(0, 0, 0, 0);
-    s.iwa[PLANE] = make_float4(0, 0, 0, 0);
-    s.iwb[PLANE] = make_float4(0, 0, p.mu_plane, 0);
-    s.vel[PLANE] = make_float4(0, 0, 0, 0);
-    s.ang[PLANE] = make_float4(0, 0, 0, 0);
-    s.cnt[PLANE] = 1;
-  }
   const f3 ph = mk(p.phx, p.phy, p.phz);
 
   // frames of the bodies (centre, rotation, inverse mass / inertia)
@@ -1281,17 +1269,48 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   }
 }
 
+// ------------------------------------------------------------------ block -> work item
+// Workgroups go to the eight XCDs in turn (block i on XCD i mod 8) and each
+// XCD has its own L2.  Neighbouring envs share the cache lines of every SoA
+// row, so XCD x gets one contiguous run of the n items: block i takes item
+// start(i mod 8) + i / 8 (a permutation of 0..n-1 for any n).
+__device__ __forceinline__ int xcd_item(int bid, int n) {
+  constexpr int X = 8;
+  const int q = n / X, r = n - q * X;
+  const int x = bid % X, j = bid / X;
+  return x * q + (x < r ? x : r) + j;
+}
+
 // ------------------------------------------------------------------ the step kernel
 // One wave per environment.  Without a work queue block i runs work item
-// env_base + i; with one, blocks pull work items from the device counter
+// env_base + xcd_item(i); with one, blocks pull work items from the device counter
 // until it passes n_envs (every block reaches that exit).  order[] maps
 // work items to environments (longest horizon first for uneven rollouts).
+// The table's LDS entries: the same for every env, and no phase writes
+// them, so a workgroup sets them once.
+template <int K>
+__device__ __forceinline__ void init_plane(Smem<K>& s, const Params& p) {
+  if (threadIdx.x == 0) {
+    s.pos[PLANE] = make_float4(0, 0, 0, 0);
+    s.col[0][PLANE] = make_float4(1, 0, 0, 0);
+    s.col[1][PLANE] = make_float4(0, 1, 0, 0);
+    s.col[2][PLANE] = make_float4(0, 0, 1, 0);
+    s.half[PLANE] = make_float4(0, 0, 0, 0);
+    s.iwa[PLANE] = make_float4(0, 0, 0, 0);
+    s.iwb[PLANE] = make_float4(0, 0, p.mu_plane, 0);
+    s.vel[PLANE] = make_float4(0, 0, 0, 0);
+    s.ang[PLANE] = make_float4(0, 0, 0, 0);
+    s.cnt[PLANE] = 1;
+  }
+}
+
 template <int K>
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
   __shared__ Smem<K> s;
   __shared__ int next;
+  init_plane(s, g.p);
   const int n_work = g.work_count ? *g.work_count : g.n_envs;
-  int wi = g.queue ? 0 : g.env_base + blockIdx.x;
+  int wi = g.queue ? 0 : g.env_base + xcd_item(blockIdx.x, gridDim.x);
   for (;;) {
     if (g.queue) {
       if (threadIdx.x == 0) next = atomicAdd(g.queue, 1);
@@ -1315,7 +1334,7 @@ __global__ void zero_kernel(int* p, int n) {
 // env e <-> pool slot slots[e] (slot < 0: env left alone).  Pool slot layout
 // [13][pool_stride]; env bodies are the packed rows env_offset[e]...
 __global__ __launch_bounds__(64) void pool_kernel(PoolArgs g) {
-  const int e = blockIdx.x;
+  const int e = xcd_item(blockIdx.x, gridDim.x);
   if (e >= g.n_envs) return;
   const int slot = g.slots[e];
   if (slot < 0 || slot >= g.pool_slots) return;
@@ -1341,7 +1360,7 @@ __device__ __forceinline__ Foot load_foot(const float* st, int SN, int si, const
 }
 
 __global__ __launch_bounds__(64) void reward_kernel(RewardArgs g) {
-  const int e = blockIdx.x;
+  const int e = xcd_item(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x;
   if (e >= g.n_envs) return;
   const int base = g.env_offset[e];
