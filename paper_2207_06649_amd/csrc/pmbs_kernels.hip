@@ -119,7 +119,11 @@ struct Smem {
   float4 vel[NOBJ];                  // solver snapshot: linear
   float4 ang[NOBJ];                  // solver snapshot: angular
   int cnt[NOBJ];                     // contacts touching each body (mass splitting)
-  unsigned short inc[2 * C];         // per-body incidence lists: contact << 1 | side (1 = b)
+  // Per-body incidence lists, each padded to a multiple of 4 entries, as
+  // ready impulse-row codes: byte offset of the row from the first impulse
+  // row | side (1 = b); list 0 for the linear lanes (row P), list 1 for the
+  // angular lanes (row ra x P or rb x P).  Padding codes point at the zero row.
+  unsigned short inc[2][2 * C + 4 * MAXB];
   float lo[3][MAXB], hi[3][MAXB];    // AABBs
   int sorted[MAXB];
   unsigned mask[MAXB];
@@ -131,6 +135,7 @@ struct Smem {
     float4 stage[C][2];              // narrowphase output: (p, sep), (n, -)
     float4 imp[3][C];                // solver exchange: P, ra x P, rb x P
   } u;
+  float4 zero;                       // a row of zeros after the impulse rows (never written)
   union {
     float clip[2][POLY][3][CLIP_GROUPS]; // narrowphase: clip polygons of the eight groups
     unsigned incm[NOBJ][2 * K];          // incidence build: contact bit masks per body
@@ -959,6 +964,9 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     // every contact sets its bit in the masks of its two bodies; a body's
     // list length is its bit count; every contact then writes itself into
     // both lists at its rank among the set bits (contact-index order)
+    const char* imp_base = reinterpret_cast<const char*>(&s.u.imp[0][0]);
+    static_assert(sizeof(s.u) + sizeof(float4) <= 0x10000, "impulse rows and the zero row need 16-bit codes");
+    const unsigned zcode = (unsigned)(reinterpret_cast<const char*>(&s.zero) - imp_base);
     int inc_start = 0, inc_count = 0;
     {
       constexpr int W = 2 * K;  // mask words per body: slot sl, lane half
@@ -983,12 +991,16 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         for (int w = 0; w < W; ++w) cn += __popc(s.x.incm[b][w]);
       }
       int tot;
-      int st0 = wave_excl_scan_bits(part == 0 ? cn : 0, 11, &tot);
+      const int padded = (cn + 3) & ~3;
+      int st0 = wave_excl_scan_bits(part == 0 ? padded : 0, 11, &tot);
       inc_start = __shfl(st0, b, 64);
       inc_count = cn;
       if (active && part == 0) {
         s.cnt[b] = cn;
         s.sorted[b] = inc_start;  // list starts (the sort keys are no longer needed)
+      }
+      if (active) {
+        for (int t = cn; t < padded; ++t) s.inc[part][inc_start + t] = (unsigned short)zcode;
       }
       wave_sync();
 #pragma unroll
@@ -1003,7 +1015,8 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
 #pragma unroll
             for (int w2 = 0; w2 < W; ++w2)
               if (w2 < w) r += __popc(s.x.incm[j][w2]);
-            s.inc[r] = (unsigned short)((c << 1) | side);
+            s.inc[0][r] = (unsigned short)(((unsigned)c * 16u) | side);
+            s.inc[1][r] = (unsigned short)((((1u + side) * (unsigned)C + c) * 16u) | side);
           }
         }
       }
@@ -1025,21 +1038,17 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       iw_o = mk(ia.w, ib.x, ib.y);
     }
     // the first 8 incidences of each body stay in registers for the whole
-    // solve as 16-bit codes: the byte offset of the impulse row this lane
-    // reads (linear lanes P, angular lanes r x P of the body's side) with
-    // the side in bit 0, so a load needs no index arithmetic
+    // solve as their 16-bit row codes, so a load needs no index arithmetic;
+    // the codes past a short list point at the zero row with side 0, whose
+    // term is -0 and leaves every sum unchanged, so no lane needs a select
     unsigned inc_reg[4] = {0u, 0u, 0u, 0u};
     const int n_reg = inc_count < 8 ? inc_count : 8;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      if (k < n_reg) {
-        const unsigned en = s.inc[inc_start + k], side = en & 1u;
-        const unsigned row = part == 0 ? 0u : 1u + side;
-        const unsigned code = ((row * (unsigned)C + (en >> 1)) * 16u) | side;
-        inc_reg[k >> 1] |= code << (16 * (k & 1));
-      }
+      const unsigned code = k < n_reg ? (unsigned)s.inc[part][inc_start + k] : zcode;
+      inc_reg[k >> 1] |= code << (16 * (k & 1));
     }
-    const char* imp_base = reinterpret_cast<const char*>(&s.u.imp[0][0]);
+    const int inc_padded = (inc_count + 3) & ~3;
     // it = -1 applies the warm-start impulses; it >= 0 are the Jacobi iterations
     wave_sync();
     for (int it = -1; it < p.iters; ++it) {
@@ -1089,7 +1098,6 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         // sums in contact-index order; four incidences per step so their
         // LDS loads are in flight together
         f3 acc = mk(0, 0, 0);
-        const int sel0 = part == 0 ? 0 : 1;
 #pragma unroll
         for (int k0 = 0; k0 < 8; k0 += 4) {
           if (k0 < n_reg) {
@@ -1102,32 +1110,24 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              if (k0 + u < n_reg) {
-                const float sg = (code[u] & 1u) ? 1.0f : -1.0f;
-                acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
-              }
+              const float sg = (code[u] & 1u) ? 1.0f : -1.0f;
+              acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
             }
           }
         }
-        int k = n_reg;
-        for (; k + 4 <= inc_count; k += 4) {
-          int en[4];
+        // entries 8.. from the padded list in LDS, four at a time
+        for (int k = 8; k < inc_padded; k += 4) {
+          unsigned code[4];
           float4 val[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) en[u] = s.inc[inc_start + k + u];
+          for (int u = 0; u < 4; ++u) code[u] = s.inc[part][inc_start + k + u];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) val[u] = s.u.imp[part == 0 ? 0 : sel0 + (en[u] & 1)][en[u] >> 1];
+          for (int u = 0; u < 4; ++u) val[u] = *reinterpret_cast<const float4*>(imp_base + (code[u] & 0xfffeu));
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const float sg = (en[u] & 1) ? 1.0f : -1.0f;
+            const float sg = (code[u] & 1u) ? 1.0f : -1.0f;
             acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
           }
-        }
-        for (; k < inc_count; ++k) {
-          const int en = s.inc[inc_start + k];
-          const float4 val = s.u.imp[part == 0 ? 0 : sel0 + (en & 1)][en >> 1];
-          const float sg = (en & 1) ? 1.0f : -1.0f;
-          acc = mk(fmaf(sg, val.x, acc.x), fmaf(sg, val.y, acc.y), fmaf(sg, val.z, acc.z));
         }
         if (part == 0) {
           v = v + acc * invm;
@@ -1301,6 +1301,7 @@ __device__ __forceinline__ void init_plane(Smem<K>& s, const Params& p) {
     s.vel[PLANE] = make_float4(0, 0, 0, 0);
     s.ang[PLANE] = make_float4(0, 0, 0, 0);
     s.cnt[PLANE] = 1;
+    s.zero = make_float4(0, 0, 0, 0);
   }
 }
 
