@@ -203,6 +203,13 @@ __device__ __forceinline__ float sat_max(const Smem<K>& s, int ia, int ib, float
   return best;
 }
 
+// Whole-wave shift by one lane (DPP wave_shl:1): lane l receives lane l + 1;
+// lane 63 receives +inf (a float) or the value's own bits (an int).
+__device__ __forceinline__ float wave_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0x7f800000, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ int wave_next(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+
 // Row broadcast: every lane of a 16-lane row receives lane k of its row.
 template <int k>
 __device__ __forceinline__ int row_bcast(int v) {
@@ -726,35 +733,63 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       // so the ranks stay a permutation whatever the state holds)
       float key = lane < n_obj ? s.lo[0][lane] : INFINITY;
       key = key == key ? key : INFINITY;
+      // lanes past n_obj hold +inf keys and never count, so the loop runs
+      // over fixed lanes (independent readlanes, two counters) with no guard
       const int ikey = __float_as_int(key);
-      int rank = 0;
-      for (int j = 0; j < n_obj; ++j) {
+      int r0 = 0, r1 = 0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
         const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
-        rank += (kj < key || (kj == key && j < lane)) ? 1 : 0;
+        const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
+        if (j & 1) r1 += c;
+        else r0 += c;
       }
+      if (n_obj > 16) {
+#pragma unroll
+        for (int j = 16; j < 32; ++j) {
+          const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
+          const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
+          if (j & 1) r1 += c;
+          else r0 += c;
+        }
+      }
+      const int rank = r0 + r1;
       if (lane < n_obj) s.sorted[rank] = lane;
     }
     wave_sync();
     {
       // sweep: lane r holds the box at sorted position r and compares it with
-      // the boxes d = 1, 2, ... positions later (shuffled down) until every
-      // lane has passed its box's max-x
+      // the boxes d = 1, 2, ... positions later until every lane has passed
+      // its box's max-x; the later boxes' bounds move down one lane per step
+      // (DPP whole-wave shift, no LDS round trip)
       const bool in = lane < n_obj;
       const int oi = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
       const float lox = in ? s.lo[0][oi] : INFINITY, hix = in ? s.hi[0][oi] : -INFINITY;
       const float loy = in ? s.lo[1][oi] : 0.0f, hiy = in ? s.hi[1][oi] : 0.0f;
       const float loz = in ? s.lo[2][oi] : 0.0f, hiz = in ? s.hi[2][oi] : 0.0f;
-      for (int d = 1; d < n_obj; ++d) {
-        const float lox_q = __shfl_down(lox, d, 64);
-        const bool go = lane + d < n_obj && lox_q <= hix;
-        if (__ballot(go) == 0ull) break;
-        const float loy_q = __shfl_down(loy, d, 64), hiy_q = __shfl_down(hiy, d, 64);
-        const float loz_q = __shfl_down(loz, d, 64), hiz_q = __shfl_down(hiz, d, 64);
-        const int oj = __shfl_down(oi, d, 64);
-        if (go && loy <= hiy_q && loy_q <= hiy && loz <= hiz_q && loz_q <= hiz) {
-          const int lo_i = oi < oj ? oi : oj, hi_i = oi < oj ? oj : oi;
-          atomicOr(&s.mask[lo_i], 1u << hi_i);
+      float lox_q = lox, loy_q = loy, hiy_q = hiy, loz_q = loz, hiz_q = hiz;
+      int oj = oi;
+      // two steps per trip: sorted min-x makes a lane that fails at step d
+      // fail at every later step, so a trip whose second step has no lane
+      // left ends the sweep
+      for (int d = 1; d < n_obj; d += 2) {
+        bool more = false;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          lox_q = wave_next(lox_q);
+          loy_q = wave_next(loy_q);
+          hiy_q = wave_next(hiy_q);
+          loz_q = wave_next(loz_q);
+          hiz_q = wave_next(hiz_q);
+          oj = wave_next(oj);
+          const bool go = lane + d + h < n_obj && lox_q <= hix;
+          if (go && loy <= hiy_q && loy_q <= hiy && loz <= hiz_q && loz_q <= hiz) {
+            const int lo_i = oi < oj ? oi : oj, hi_i = oi < oj ? oj : oi;
+            atomicOr(&s.mask[lo_i], 1u << hi_i);
+          }
+          if (h == 1) more = __ballot(go) != 0ull;
         }
+        if (!more) break;
       }
     }
     wave_sync();
