@@ -277,6 +277,9 @@ template <int K>
 __device__ __forceinline__ int clip_group(Smem<K>& s, f3* P, int n, f3 f, f3 dir, float sign, float h, int buf,
                                           int grp, int gl, int lane) {
   const float dc = sign * dot(*P - f, dir) - h;
+  // no point of any group outside this plane: nothing crosses it and every
+  // point is kept in place, so the stage changes nothing
+  if (__ballot(gl < n && !(dc <= 0.0f)) == 0ull) return n;
   const int src = (grp << 3) | (gl == 0 ? (n > 0 ? n - 1 : 0) : gl - 1);
   const f3 Pp = mk(__shfl(P->x, src, 64), __shfl(P->y, src, 64), __shfl(P->z, src, 64));
   const float dp = __shfl(dc, src, 64);
