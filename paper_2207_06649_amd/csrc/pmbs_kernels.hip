@@ -1069,12 +1069,18 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     }
 
     // ---- 7. projected Jacobi, I iterations
-    f3 iw_d = mk(0, 0, 0), iw_o = mk(0, 0, 0);  // Iw^-1 diagonal / off-diagonal (xy, xz, yz)
+    // Each lane carries the one velocity it owns (linear v on part 0,
+    // angular w on part 1) and the matching symmetric inverse mass matrix
+    // (inverse mass times identity, or the world inverse inertia): diagonal
+    // md, off-diagonal mo = (xy, xz, yz).  The update is the same for both.
+    f3 vw = part == 0 ? v : w;
+    f3 md = mk(invm, invm, invm), mo = mk(0, 0, 0);
     if (active && part == 1) {
       float4 ia = s.iwa[b], ib = s.iwb[b];
-      iw_d = mk(ia.x, ia.y, ia.z);
-      iw_o = mk(ia.w, ib.x, ib.y);
+      md = mk(ia.x, ia.y, ia.z);
+      mo = mk(ia.w, ib.x, ib.y);
     }
+    float4* const vw_slot = part == 0 ? &s.vel[b] : &s.ang[b];
     // the first 8 incidences of each body stay in registers for the whole
     // solve as their 16-bit row codes, so a load needs no index arithmetic;
     // the codes past a short list point at the zero row with side 0, whose
@@ -1087,95 +1093,98 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       inc_reg[k >> 1] |= code << (16 * (k & 1));
     }
     const int inc_padded = (inc_count + 3) & ~3;
-    // it = -1 applies the warm-start impulses; it >= 0 are the Jacobi iterations
-    wave_sync();
-    for (int it = -1; it < p.iters; ++it) {
-      if (it >= 0) {
-        if (active) {
-          if (part == 0) st3(&s.vel[b], v);
-          else st3(&s.ang[b], w);
-        }
-        wave_sync();
-      }
+    // per body: impulse sums in contact-index order (four incidences per step
+    // so their LDS loads are in flight together), then vw += M sum
+    auto apply_sums = [&]() {
+      if (!active) return;
+      f3 acc = mk(0, 0, 0);
 #pragma unroll
-      for (int sl = 0; sl < K; ++sl) {
-        const int c = 64 * sl + lane;
-        if (c < nc) {
-          Contact& q = ct[sl];
-          const f3 t2 = q.t2;
-          f3 P;
-          if (it < 0) {
-            P = q.n * q.ln + (q.t1 * q.lt1 + t2 * q.lt2);
-          } else {
-            const int a = q.ab & 255, bb = (q.ab >> 8) & 255;
-            f3 va = xyz(s.vel[a]), wa = xyz(s.ang[a]), vb = xyz(s.vel[bb]), wb = xyz(s.ang[bb]);
-            f3 u = (vb + cross(wb, q.rb)) - (va + cross(wa, q.ra));
-            float ln = fmaxf(q.ln + q.kn * (q.vstar - dot(u, q.n)), 0.0f);
-            float dln = ln - q.ln;
-            q.ln = ln;
-            float lt1 = q.lt1 - q.kt1 * dot(u, q.t1);
-            float lt2 = q.lt2 - q.kt2 * dot(u, t2);
-            float lim = q.mu * ln, mag2 = lt1 * lt1 + lt2 * lt2;
-            if (mag2 > lim * lim) {
-              float sc = lim * rsq(mag2);
-              lt1 *= sc;
-              lt2 *= sc;
-            }
-            float dl1 = lt1 - q.lt1, dl2 = lt2 - q.lt2;
-            q.lt1 = lt1;
-            q.lt2 = lt2;
-            P = q.n * dln + (q.t1 * dl1 + t2 * dl2);
-          }
-          st3(&s.u.imp[0][c], P);
-          st3(&s.u.imp[1][c], cross(q.ra, P));
-          st3(&s.u.imp[2][c], cross(q.rb, P));
-        }
-      }
-      wave_sync();
-      if (active) {
-        // sums in contact-index order; four incidences per step so their
-        // LDS loads are in flight together
-        f3 acc = mk(0, 0, 0);
-#pragma unroll
-        for (int k0 = 0; k0 < 8; k0 += 4) {
-          if (k0 < n_reg) {
-            float4 val[4];
-            unsigned code[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              code[u] = (inc_reg[(k0 + u) >> 1] >> (16 * (u & 1))) & 0xffffu;
-              val[u] = *reinterpret_cast<const float4*>(imp_base + (code[u] & 0xfffeu));
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const float sg = (code[u] & 1u) ? 1.0f : -1.0f;
-              acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
-            }
-          }
-        }
-        // entries 8.. from the padded list in LDS, four at a time
-        for (int k = 8; k < inc_padded; k += 4) {
-          unsigned code[4];
+      for (int k0 = 0; k0 < 8; k0 += 4) {
+        if (k0 < n_reg) {
           float4 val[4];
+          unsigned code[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) code[u] = s.inc[part][inc_start + k + u];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) val[u] = *reinterpret_cast<const float4*>(imp_base + (code[u] & 0xfffeu));
+          for (int u = 0; u < 4; ++u) {
+            code[u] = (inc_reg[(k0 + u) >> 1] >> (16 * (u & 1))) & 0xffffu;
+            val[u] = *reinterpret_cast<const float4*>(imp_base + (code[u] & 0xfffeu));
+          }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const float sg = (code[u] & 1u) ? 1.0f : -1.0f;
             acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
           }
         }
-        if (part == 0) {
-          v = v + acc * invm;
-        } else {
-          w = w + mk(iw_d.x * acc.x + iw_o.x * acc.y + iw_o.y * acc.z,
-                     iw_o.x * acc.x + iw_d.y * acc.y + iw_o.z * acc.z,
-                     iw_o.y * acc.x + iw_o.z * acc.y + iw_d.z * acc.z);
+      }
+      // entries 8.. from the padded list in LDS, four at a time
+      for (int k = 8; k < inc_padded; k += 4) {
+        unsigned code[4];
+        float4 val[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) code[u] = s.inc[part][inc_start + k + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) val[u] = *reinterpret_cast<const float4*>(imp_base + (code[u] & 0xfffeu));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float sg = (code[u] & 1u) ? 1.0f : -1.0f;
+          acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
         }
       }
+      vw = vw + mk(md.x * acc.x + mo.x * acc.y + mo.y * acc.z,
+                   mo.x * acc.x + md.y * acc.y + mo.z * acc.z,
+                   mo.y * acc.x + mo.z * acc.y + md.z * acc.z);
+    };
+    // warm start: the impulses carried over from the previous substep
+    wave_sync();
+#pragma unroll
+    for (int sl = 0; sl < K; ++sl) {
+      const int c = 64 * sl + lane;
+      if (c < nc) {
+        const Contact& q = ct[sl];
+        const f3 P = q.n * q.ln + (q.t1 * q.lt1 + q.t2 * q.lt2);
+        st3(&s.u.imp[0][c], P);
+        st3(&s.u.imp[1][c], cross(q.ra, P));
+        st3(&s.u.imp[2][c], cross(q.rb, P));
+      }
     }
+    wave_sync();
+    apply_sums();
+    for (int it = 0; it < p.iters; ++it) {
+      if (active) st3(vw_slot, vw);
+      wave_sync();
+#pragma unroll
+      for (int sl = 0; sl < K; ++sl) {
+        const int c = 64 * sl + lane;
+        if (c < nc) {
+          Contact& q = ct[sl];
+          const f3 t2 = q.t2;
+          const int a = q.ab & 255, bb = (q.ab >> 8) & 255;
+          f3 va = xyz(s.vel[a]), wa = xyz(s.ang[a]), vb = xyz(s.vel[bb]), wb = xyz(s.ang[bb]);
+          f3 u = (vb + cross(wb, q.rb)) - (va + cross(wa, q.ra));
+          float ln = fmaxf(q.ln + q.kn * (q.vstar - dot(u, q.n)), 0.0f);
+          float dln = ln - q.ln;
+          q.ln = ln;
+          float lt1 = q.lt1 - q.kt1 * dot(u, q.t1);
+          float lt2 = q.lt2 - q.kt2 * dot(u, t2);
+          float lim = q.mu * ln, mag2 = lt1 * lt1 + lt2 * lt2;
+          if (mag2 > lim * lim) {
+            float sc = lim * rsq(mag2);
+            lt1 *= sc;
+            lt2 *= sc;
+          }
+          float dl1 = lt1 - q.lt1, dl2 = lt2 - q.lt2;
+          q.lt1 = lt1;
+          q.lt2 = lt2;
+          const f3 P = q.n * dln + (q.t1 * dl1 + t2 * dl2);
+          st3(&s.u.imp[0][c], P);
+          st3(&s.u.imp[1][c], cross(q.ra, P));
+          st3(&s.u.imp[2][c], cross(q.rb, P));
+        }
+      }
+      wave_sync();
+      apply_sums();
+    }
+    if (part == 0) v = vw;
+    else w = vw;
     // remember this substep's accumulated impulses by key
 #pragma unroll
     for (int sl = 0; sl < K; ++sl) {
