@@ -810,30 +810,37 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     }
     wave_sync();
 
-    // ---- 4a. box-plane contacts (body order, vertex order)
+    // ---- 4a. box-plane contacts (body order, vertex order).  Corner kk
+    // of body b is tested by lane b when kk has an even number of set bits
+    // and by lane b + 32 otherwise, so every face's four corners split two
+    // and two; the body's two flag bytes give each corner its rank.
     int nc_raw;
     {
-      f3 a0 = mk(0, 0, 0), a1 = mk(0, 0, 0), a2 = mk(0, 0, 0);
+      f3 c0 = mk(0, 0, 0), a0 = mk(0, 0, 0), a1 = mk(0, 0, 0), a2 = mk(0, 0, 0);
       unsigned flags = 0;
-      if (active && part == 0) {
+      if (active) {
+        c0 = xyz(s.pos[b]);
         a0 = xyz(s.col[0][b]); a1 = xyz(s.col[1][b]); a2 = xyz(s.col[2][b]);
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-          float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
-          float vz = x.z + (a0.z * sx + a1.z * sy + a2.z * sz);
+        for (int j = 0; j < 4; ++j) {
+          // the j-th corner of this lane's parity class: 0, 3, 5, 6 or 1, 2, 4, 7
+          const int kk = part == 0 ? (0x6530 >> (4 * j)) & 15 : (0x7421 >> (4 * j)) & 15;
+          const float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
+          const float vz = c0.z + (a0.z * sx + a1.z * sy + a2.z * sz);
           if (vz <= p.margin) flags |= 1u << kk;
         }
       }
+      const unsigned both = flags | (unsigned)__shfl_xor((int)flags, 32, 64);
       int total;
-      int off = wave_excl_scan_bits(__popc(flags), 4, &total);
-      int t = 0;
+      const int off0 = wave_excl_scan_bits(part == 0 ? __popc(both) : 0, 4, &total);
+      const int off = __shfl(off0, b, 64);
       while (flags) {
         const int kk = __builtin_ctz(flags);
         flags &= flags - 1;
         float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
-        f3 vtx = x + mk(a0.x * sx + a1.x * sy + a2.x * sz, a0.y * sx + a1.y * sy + a2.y * sz,
-                        a0.z * sx + a1.z * sy + a2.z * sz);
-        const int c = off + t++;
+        f3 vtx = c0 + mk(a0.x * sx + a1.x * sy + a2.x * sz, a0.y * sx + a1.y * sy + a2.y * sz,
+                         a0.z * sx + a1.z * sy + a2.z * sz);
+        const int c = off + __popc(both & ((1u << kk) - 1u));
         if (c < C) {
           s.u.stage[c][0] = f4(vtx - mk(0, 0, 0.5f * vtx.z), vtx.z);
           s.u.stage[c][1] = make_float4(0, 0, 1, 0);
