@@ -203,6 +203,15 @@ __device__ __forceinline__ float sat_max(const Smem<K>& s, int ia, int ib, float
   return best;
 }
 
+// An opaque copy of a value: address arithmetic built from it stays where it
+// is used (otherwise one 64-bit row offset per state row is computed at the
+// start, shared by every later load and store of the rows, and held in
+// registers, or scratch, for the whole kernel).
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // Whole-wave shift by one lane (DPP wave_shl:1): lane l receives lane l + 1;
 // lane 63 receives +inf (a float) or the value's own bits (an int).
 __device__ __forceinline__ float wave_next(float v) {
@@ -1245,13 +1254,13 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     // the expanded child's state goes to its pool slot
     const int cs = (t == 0 && job == 0 && g.child_slot) ? g.child_slot[e] : -1;
     if (cs >= 0 && active) {
-      float* dst = g.pool + (size_t)cs * 13 * PS;
+      float* dst = g.pool + (size_t)cs * 13 * PS + opaque(b);
       if (part == 0) {
-        dst[0 * PS + b] = x.x; dst[1 * PS + b] = x.y; dst[2 * PS + b] = x.z;
-        dst[7 * PS + b] = v.x; dst[8 * PS + b] = v.y; dst[9 * PS + b] = v.z;
+        dst[0 * PS] = x.x; dst[1 * PS] = x.y; dst[2 * PS] = x.z;
+        dst[7 * PS] = v.x; dst[8 * PS] = v.y; dst[9 * PS] = v.z;
       } else {
-        dst[3 * PS + b] = q0; dst[4 * PS + b] = q1; dst[5 * PS + b] = q2; dst[6 * PS + b] = q3;
-        dst[10 * PS + b] = w.x; dst[11 * PS + b] = w.y; dst[12 * PS + b] = w.z;
+        dst[3 * PS] = q0; dst[4 * PS] = q1; dst[5 * PS] = q2; dst[6 * PS] = q3;
+        dst[10 * PS] = w.x; dst[11 * PS] = w.y; dst[12 * PS] = w.z;
       }
     }
     wave_sync();
@@ -1267,13 +1276,13 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   n_push = n_push - t_stop - 1;
   last_r = 0.0f;
   if (active) {
-    const float* st = g.pool + (size_t)g.x_desc[e].x * 13 * PS;
+    const float* st = g.pool + (size_t)g.x_desc[e].x * 13 * PS + opaque(b);
     if (part == 0) {
-      x = mk(st[0 * PS + b], st[1 * PS + b], st[2 * PS + b]);
-      v = mk(st[7 * PS + b], st[8 * PS + b], st[9 * PS + b]);
+      x = mk(st[0 * PS], st[1 * PS], st[2 * PS]);
+      v = mk(st[7 * PS], st[8 * PS], st[9 * PS]);
     } else {
-      q0 = st[3 * PS + b]; q1 = st[4 * PS + b]; q2 = st[5 * PS + b]; q3 = st[6 * PS + b];
-      w = mk(st[10 * PS + b], st[11 * PS + b], st[12 * PS + b]);
+      q0 = st[3 * PS]; q1 = st[4 * PS]; q2 = st[5 * PS]; q3 = st[6 * PS];
+      w = mk(st[10 * PS], st[11 * PS], st[12 * PS]);
     }
   }
   }  // jobs
@@ -1299,7 +1308,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   // ---- write back
   bool bad = false;
   if (active) {
-    const int i = base + b;
+    const int i = opaque(base + b);
     float* st = g.state;
     if (part == 0) {
       st[0 * N + i] = x.x; st[1 * N + i] = x.y; st[2 * N + i] = x.z;
