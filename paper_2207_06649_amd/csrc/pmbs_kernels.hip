@@ -67,30 +67,21 @@ __device__ __forceinline__ float comp(f3 v, int k) {
 }
 
 // ------------------------------------------------------------------ wave helpers
+// Exclusive prefix sum across the wave, and its total: an inclusive scan by
+// DPP row shifts (by 1, 2 and 3, then by 4 and 8 into the upper banks of
+// each 16-lane row) and broadcasts of lanes 15 and 31 into the following
+// rows; no LDS and no ballots.
 __device__ __forceinline__ int wave_excl_scan(int x, int* total) {
-  const int lane = threadIdx.x;
   int v = x;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    int y = __shfl_up(v, d, 64);
-    if (lane >= d) v += y;
-  }
-  *total = __shfl(v, 63, 64);
+  v += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, x, 0x113, 0xf, 0xf, true);   // row_shr:3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xe, true);   // row_shr:4, lanes 4-15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xc, true);   // row_shr:8, lanes 8-15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15, rows 1 and 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31, rows 2 and 3
+  *total = __builtin_amdgcn_readlane(v, 63);
   return v - x;
-}
-
-// Exclusive prefix sum of small non-negative counts (< 2^bits) across the
-// wave: one ballot per bit, counted below each lane with mbcnt (no LDS).
-__device__ __forceinline__ int wave_excl_scan_bits(int x, int bits, int* total) {
-  int prefix = 0, tot = 0;
-  for (int bb = 0; bb < bits; ++bb) {
-    const unsigned long long m = __ballot((x >> bb) & 1);
-    const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-    prefix += below << bb;
-    tot += __popcll(m) << bb;
-  }
-  *total = tot;
-  return prefix;
 }
 
 // Orders the LDS accesses of the wave's lanes around this point.  A
@@ -808,7 +799,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     int n_pairs;
     {
       unsigned m = lane < n_obj ? s.mask[lane] : 0u;
-      int off = wave_excl_scan_bits(__popc(m), 5, &n_pairs);
+      int off = wave_excl_scan(__popc(m), &n_pairs);
       int t = 0;
       while (m) {
         int j = __builtin_ctz(m);
@@ -841,7 +832,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       }
       const unsigned both = flags | (unsigned)__shfl_xor((int)flags, 32, 64);
       int total;
-      const int off0 = wave_excl_scan_bits(part == 0 ? __popc(both) : 0, 4, &total);
+      const int off0 = wave_excl_scan(part == 0 ? __popc(both) : 0, &total);
       const int off = __shfl(off0, b, 64);
       while (flags) {
         const int kk = __builtin_ctz(flags);
@@ -1046,7 +1037,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       }
       int tot;
       const int padded = (cn + 3) & ~3;
-      int st0 = wave_excl_scan_bits(part == 0 ? padded : 0, 11, &tot);
+      int st0 = wave_excl_scan(part == 0 ? padded : 0, &tot);
       inc_start = __shfl(st0, b, 64);
       inc_count = cn;
       if (active && part == 0) {
