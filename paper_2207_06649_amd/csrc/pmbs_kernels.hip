@@ -706,6 +706,8 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
 
   const int n_sub = g.collide_only ? 1 : g.n_substeps;
   int nwarm = 0;  // impulses are carried within one push only
+  // this lane's incidence list range, kept while the contact list is unchanged
+  int inc_start = 0, inc_count = 0;
   for (int k = 0; k < n_sub; ++k) {
     // ---- 1. velocity stage
     if (active && part == 0) v.z -= p.gravity * dt;
@@ -1012,8 +1014,20 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     const char* imp_base = reinterpret_cast<const char*>(&s.u.imp[0][0]);
     static_assert(sizeof(s.u) + sizeof(float4) <= 0x10000, "impulse rows and the zero row need 16-bit codes");
     const unsigned zcode = (unsigned)(reinterpret_cast<const char*>(&s.zero) - imp_base);
-    int inc_start = 0, inc_count = 0;
-    {
+    // A contact list equal to the previous substep's (same count, same keys
+    // in the same order, within one push) has the same incidence lists,
+    // counts and list ranges, which are all still in place: keep them.
+    bool same_list = nc > 0 && nc == nwarm;
+    if (same_list) {
+      bool diff = false;
+#pragma unroll
+      for (int sl = 0; sl < K; ++sl) {
+        const int c = 64 * sl + lane;
+        if (c < nc) diff = diff || contact_key(s.cab[c]) != s.wkey[c];
+      }
+      same_list = __ballot(diff) == 0ull;
+    }
+    if (!same_list) {
       constexpr int W = 2 * K;  // mask words per body: slot sl, lane half
       for (int t = lane; t < NOBJ * W; t += 64) (&s.x.incm[0][0])[t] = 0u;
       wave_sync();
