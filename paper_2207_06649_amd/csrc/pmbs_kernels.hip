@@ -116,7 +116,8 @@ struct Smem {
   // angular lanes (row ra x P or rb x P).  Padding codes point at the zero row.
   unsigned short inc[2][2 * C + 4 * MAXB];
   float lo[3][MAXB], hi[3][MAXB];    // AABBs
-  int sorted[MAXB];
+  int sorted[MAXB];                  // objects in min-x order (kept while still ordered)
+  int lstart[MAXB];                  // incidence list starts
   unsigned mask[MAXB];
   unsigned short pairs[MAX_PAIRS];
   int cab[C];                        // packed a | b << 8 | feature << 16 of each contact
@@ -592,6 +593,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   int n_rewards = 0;
   long long stat_nc = 0, stat_pairs = 0, stat_sub = 0;
   const int n_obj = nb + 1;
+  bool order_kept = false;  // s.sorted holds a permutation of this env's objects
 
   // job 0 is the env's own simulation; job 1 (re-purposing) is one extra
   // simulation of another pair that spends the pushes left when job 0
@@ -733,7 +735,21 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       s.mask[lane] = 0u;
     }
     wave_sync();
-    {
+    // the previous substep's order is still the order when every object
+    // precedes the next one by (key, index); then the ranks need no update
+    bool order_ok = order_kept;
+    if (order_ok) {
+      const bool in = lane < n_obj;
+      const int o = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
+      float kx = in ? s.lo[0][o] : INFINITY;
+      kx = kx == kx ? kx : INFINITY;
+      const float kn = wave_next(kx);
+      const int on = wave_next(o);
+      const bool bad = lane + 1 < n_obj && !(kx < kn || (kx == kn && o < on));
+      order_ok = __ballot(bad) == 0ull;
+    }
+    order_kept = true;
+    if (!order_ok) {
       // rank of each object's min-x key (ties by index; NaN keys sort last,
       // so the ranks stay a permutation whatever the state holds)
       float key = lane < n_obj ? s.lo[0][lane] : INFINITY;
@@ -1056,7 +1072,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       inc_count = cn;
       if (active && part == 0) {
         s.cnt[b] = cn;
-        s.sorted[b] = inc_start;  // list starts (the sort keys are no longer needed)
+        s.lstart[b] = inc_start;
       }
       if (active) {
         for (int t = cn; t < padded; ++t) s.inc[part][inc_start + t] = (unsigned short)zcode;
@@ -1070,7 +1086,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         for (int side = 0; side < 2; ++side) {
           const int j = side ? cb[sl] : ca[sl];
           if (j >= 0) {
-            int r = s.sorted[j] + __popc(s.x.incm[j][w] & (bit - 1u));
+            int r = s.lstart[j] + __popc(s.x.incm[j][w] & (bit - 1u));
 #pragma unroll
             for (int w2 = 0; w2 < W; ++w2)
               if (w2 < w) r += __popc(s.x.incm[j][w2]);
