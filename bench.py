@@ -52,11 +52,18 @@ KERNEL_SOURCES = ("paper_2207_06649_amd/csrc/pmbs_kernels.hip", "paper_2207_0664
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources' code: comments and whitespace removed, so
+    an edit to a comment keeps the recorded counters valid."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            src = f.read()
+        # string and character literals are kept whole; comments go
+        tokens = re.findall(r'"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'|//[^\n]*|/\*.*?\*/|\S+', src, re.S)
+        code = " ".join(t for t in tokens if not t.startswith(("//", "/*")))
+        h.update(rel.encode() + b"\0" + code.encode())
     return h.hexdigest()
 
 

@@ -9,9 +9,10 @@
 //   lane b + 32  owns body b's orientation, angular velocity, world inverse
 //                inertia (so two lanes carry every body)
 //   lane l       holds contacts l, l+64, l+128, ... in VGPR slots (K slots)
-// Shared state goes through LDS: body frames, the broadphase pair list, the
-// contact staging array (reused for the impulse exchange of the solver) and
-// per-lane polygon scratch for face clipping.
+// Shared state goes through LDS: body frames, the broadphase order and pair
+// list, the contact staging array (reused for the impulse exchange of the
+// solver), per-body incidence lists, warm-start keys and impulses, and the
+// clip polygons of face clipping.
 //
 // Per substep (all in one launch, state stays in registers/LDS; HBM is
 // touched once in and once out per call):
