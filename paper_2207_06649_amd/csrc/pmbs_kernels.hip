@@ -57,15 +57,6 @@ __device__ __forceinline__ void st3(float4* d, f3 v) {
 __device__ __forceinline__ float sel(bool c, float a, float b) { return c ? a : b; }
 __device__ __forceinline__ f3 xyz(float4 v) { return {v.x, v.y, v.z}; }
 __device__ __forceinline__ float4 f4(f3 v, float w) { return make_float4(v.x, v.y, v.z, w); }
-__device__ __forceinline__ float comp(f3 v, int k) {
-  float r;
-  switch (k) {
-    case 0: r = v.x; break;
-    case 1: r = v.y; break;
-    default: r = v.z; break;
-  }
-  return r;
-}
 
 // ------------------------------------------------------------------ wave helpers
 // Exclusive prefix sum across the wave, and its total: an inclusive scan by
