@@ -204,6 +204,25 @@ def test_plain_push_full_invariants(pm, seed):
     assert abs(dx_g - dx_o) < 5e-3
 
 
+@pytest.mark.parametrize("seed,n_sub", [(0, 20), (1, 40), (2, 40), (3, 60)])
+def test_contact_onset_short_push(pm, seed, n_sub):
+    """The pusher starts 3 mm from cube 0 and reaches it after about seven
+    substeps: the contact list first stays unchanged (resting plane contacts,
+    so incidence lists and the min-x order carry over between substeps),
+    then changes at the onset and stays again.  Over this short window the
+    FP32 path stays within rounding of the FP64 oracle (about 1e-8 m and
+    1e-7 measured), so the bar is the one-substep bar, 1e-5 m and 1e-5; a
+    stale list or order would exceed it by orders of magnitude."""
+    b = scenes.plain_push_scene(seed)
+    push = touching_push(b, gap=3e-3)
+    g, gs, _ = run_gpu(pm, b, push, n_sub)
+    o, os_, ov = run_oracle(b, push, n_sub)
+    assert gs[0] == 0 and ov[0] == 1
+    compare(g, o, 1e-5, 1e-5)
+    # the push reached cube 0: it moved along the push
+    assert g[0, 0] - b.state[0, 0] > 1e-4
+
+
 def test_invalid_push_discarded(pm):
     b = scenes.plain_push_scene(4)
     c0 = b.state[0, :2]
