@@ -203,22 +203,24 @@ __device__ __forceinline__ float wave_next(float v) {
 }
 __device__ __forceinline__ int wave_next(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
 
-// Row broadcast: every lane of a 16-lane row receives lane k of its row.
-template <int k>
-__device__ __forceinline__ int row_bcast(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x150 + k, 0xf, 0xf, false);
+// Group broadcast: lane j of each 8-lane group to the whole group, as two
+// row broadcasts (DPP row_newbcast) each written only to its half of the
+// 16-lane row (bank masks: lanes 0-7, lanes 8-15).
+template <int j>
+__device__ __forceinline__ int group_bcast(int v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, v, 0x150 + j, 0xf, 0x3, false);
+  return __builtin_amdgcn_update_dpp(lo, v, 0x158 + j, 0xf, 0xc, false);
 }
 
 // Candidate k of an 8-lane group: held by lane k mod 8 of the group, in its
 // first value for k < 8 and its second for k >= 8; an invalid candidate
 // holds -inf (candidate 0, a face of A, is always valid, so -inf never
-// replaces a kept axis).  Lanes with `hi` set are the upper halves of their
-// 16-lane rows.
+// replaces a kept axis).
 template <int k>
-__device__ __forceinline__ void sat_scan_step(float sv0, float sv1, bool hi, float tau_face, float tau_edge, float* bs,
+__device__ __forceinline__ void sat_scan_step(float sv0, float sv1, float tau_face, float tau_edge, float* bs,
                                               int* best) {
   const int sv = __float_as_int(k < 8 ? sv0 : sv1);
-  const float sk = __int_as_float(hi ? row_bcast<8 + (k & 7)>(sv) : row_bcast<k & 7>(sv));
+  const float sk = __int_as_float(group_bcast<k & 7>(sv));
   const float tau = k < 6 ? tau_face : tau_edge;
   if (*best < 0 || sk > *bs + tau) {
     *bs = sk;
@@ -230,22 +232,22 @@ __device__ __forceinline__ void sat_scan_step(float sv0, float sv1, bool hi, flo
 // of B, 6-14 edge crosses) held by the 8 lanes of a group: the kept axis
 // starts at the first candidate and is replaced only when a later valid one
 // exceeds it by tau (face) or tau_edge (edge axes).
-__device__ __forceinline__ void sat_scan8(float sv0, float sv1, bool hi, float tf, float te, float* bs, int* best) {
-  sat_scan_step<0>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<1>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<2>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<3>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<4>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<5>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<6>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<7>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<8>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<9>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<10>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<11>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<12>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<13>(sv0, sv1, hi, tf, te, bs, best);
-  sat_scan_step<14>(sv0, sv1, hi, tf, te, bs, best);
+__device__ __forceinline__ void sat_scan8(float sv0, float sv1, float tf, float te, float* bs, int* best) {
+  sat_scan_step<0>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<1>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<2>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<3>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<4>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<5>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<6>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<7>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<8>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<9>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<10>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<11>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<12>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<13>(sv0, sv1, tf, te, bs, best);
+  sat_scan_step<14>(sv0, sv1, tf, te, bs, best);
 }
 
 // ------------------------------------------------------------------ clipping
@@ -902,7 +904,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       const bool out = (__ballot((ok0 && sv0 > p.margin) || (ok1 && sv1 > p.margin)) & gm) != 0ull;
       float bs = -INFINITY;
       int best = -1;
-      sat_scan8(ok0 ? sv0 : -INFINITY, ok1 ? sv1 : -INFINITY, (lane & 8) != 0, p.tau_face, p.tau_edge, &bs, &best);
+      sat_scan8(ok0 ? sv0 : -INFINITY, ok1 ? sv1 : -INFINITY, p.tau_face, p.tau_edge, &bs, &best);
       if (!has || out) best = -1;
       // every lane of the group holds the pair's axis: its direction again
       f3 n = mk(0, 0, 0);
