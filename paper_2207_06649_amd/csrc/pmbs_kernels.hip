@@ -262,12 +262,22 @@ __device__ __forceinline__ void cl_put(Smem<K>& s, int buf, int i, int grp, f3 v
   s.x.clip[buf][i][2][grp] = v.z;
 }
 
+// Previous lane of each 8-lane group, lane 0 of a group taking lane 7: DPP
+// row_shr:1 and row_ror:9 within the 16-lane rows.
+__device__ __forceinline__ float group_prev(float v, bool first) {
+  const int iv = __float_as_int(v);
+  const int down = __builtin_amdgcn_mov_dpp(iv, 0x111, 0xf, 0xf, false);
+  const int wrap = __builtin_amdgcn_mov_dpp(iv, 0x129, 0xf, 0xf, false);
+  return __int_as_float(first ? wrap : down);
+}
+
 // One Sutherland-Hodgman stage against sign * ((x - f).dir) - h <= 0 for
 // the polygons of all eight groups at once, point i of a group's polygon
-// in lane i of the group.  Lane i handles the edge from point i-1 (the last
-// point for i = 0) to point i: it emits the crossing point if the edge
-// crosses the plane, then point i if inside, at its rank among the group's
-// emissions; at most POLY points are kept.  Called by the whole wave.
+// in lane i of the group (lanes past the last point hold copies of it).
+// Lane i handles the edge from point i-1 (the last point for i = 0) to
+// point i: it emits the crossing point if the edge crosses the plane, then
+// point i if inside, at its rank among the group's emissions; at most POLY
+// points are kept.  Called by the whole wave.
 template <int K>
 __device__ __forceinline__ int clip_group(Smem<K>& s, f3* P, int n, f3 f, f3 dir, float sign, float h, int buf,
                                           int grp, int gl, int lane) {
@@ -275,9 +285,11 @@ __device__ __forceinline__ int clip_group(Smem<K>& s, f3* P, int n, f3 f, f3 dir
   // no point of any group outside this plane: nothing crosses it and every
   // point is kept in place, so the stage changes nothing
   if (__ballot(gl < n && !(dc <= 0.0f)) == 0ull) return n;
-  const int src = (grp << 3) | (gl == 0 ? (n > 0 ? n - 1 : 0) : gl - 1);
-  const f3 Pp = mk(__shfl(P->x, src, 64), __shfl(P->y, src, 64), __shfl(P->z, src, 64));
-  const float dp = __shfl(dc, src, 64);
+  // the previous point: lanes past the last point hold copies of it, so it
+  // is one lane down in the group, and lane 7 for lane 0
+  const bool first = gl == 0;
+  const f3 Pp = mk(group_prev(P->x, first), group_prev(P->y, first), group_prev(P->z, first));
+  const float dp = group_prev(dc, first);
   const bool live = gl < n;
   const bool in_c = dc <= 0.0f, in_p = dp <= 0.0f;
   const bool emit_x = live && (in_c != in_p), emit_c = live && in_c;
@@ -289,7 +301,7 @@ __device__ __forceinline__ int clip_group(Smem<K>& s, f3* P, int n, f3 f, f3 dir
   if (emit_c && q + (emit_x ? 1 : 0) < POLY) cl_put(s, buf, q + (emit_x ? 1 : 0), grp, *P);
   wave_sync();
   const int nn = m < POLY ? m : POLY;
-  if (gl < nn) *P = cl_get(s, buf, gl, grp);
+  if (nn > 0) *P = cl_get(s, buf, gl < nn ? gl : nn - 1, grp);
   return nn;
 }
 
