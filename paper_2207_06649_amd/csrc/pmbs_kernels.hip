@@ -196,6 +196,11 @@ __device__ __forceinline__ int opaque(int x) {
   return x;
 }
 
+// The two halves of the wave, lane by lane (v_permlane32_swap): lane l
+// receives the value of lane l & 31 in lo and of lane 32 + (l & 31) in hi.
+__device__ __forceinline__ int lower_half(int v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false)[0]; }
+__device__ __forceinline__ int upper_half(int v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1]; }
+
 // Whole-wave shift by one lane (DPP wave_shl:1): lane l receives lane l + 1;
 // lane 63 receives +inf (a float) or the value's own bits (an int).
 __device__ __forceinline__ float wave_next(float v) {
@@ -854,10 +859,10 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
           if (vz <= p.margin) flags |= 1u << kk;
         }
       }
-      const unsigned both = flags | (unsigned)__shfl_xor((int)flags, 32, 64);
+      const unsigned both = (unsigned)(lower_half((int)flags) | upper_half((int)flags));
       int total;
       const int off0 = wave_excl_scan(part == 0 ? __popc(both) : 0, &total);
-      const int off = __shfl(off0, b, 64);
+      const int off = lower_half(off0);
       while (flags) {
         const int kk = __builtin_ctz(flags);
         flags &= flags - 1;
@@ -1074,7 +1079,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       int tot;
       const int padded = (cn + 3) & ~3;
       int st0 = wave_excl_scan(part == 0 ? padded : 0, &tot);
-      inc_start = __shfl(st0, b, 64);
+      inc_start = lower_half(st0);
       inc_count = cn;
       if (active && part == 0) {
         s.cnt[b] = cn;
