@@ -197,7 +197,8 @@ __device__ __forceinline__ int opaque(int x) {
 }
 
 // The two halves of the wave, lane by lane (v_permlane32_swap): lane l
-// receives the value of lane l & 31 in lo and of lane 32 + (l & 31) in hi.
+// receives the value of lane l & 31 from lower_half and of lane
+// 32 + (l & 31) from upper_half.
 __device__ __forceinline__ int lower_half(int v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false)[0]; }
 __device__ __forceinline__ int upper_half(int v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1]; }
 
