@@ -71,3 +71,22 @@ def test_server_config_and_workspace_size():
     assert n.value >= 1000 * 31 * 13 * 4
     bad = pmbs.server_config(max_requests=0)
     assert pmbs._server_lib().pmbs_server_query_workspace(C.byref(bad), C.byref(n)) == -1  # invalid argument
+
+
+def test_counter_record_key_ignores_comments(tmp_path, monkeypatch):
+    """The HBM-traffic record is keyed by the kernel sources' code: a comment
+    edit keeps the key, a code edit changes it."""
+    import shutil
+    import bench
+    for rel in bench.KERNEL_SOURCES:
+        dst = tmp_path / rel
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        shutil.copy(os.path.join(bench.ROOT, rel), dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    key = bench.kernel_source_hash()
+    src = tmp_path / bench.KERNEL_SOURCES[0]
+    text = src.read_text()
+    src.write_text("// a new comment line\n" + text.replace("// ", "//  ", 3))
+    assert bench.kernel_source_hash() == key
+    src.write_text(text.replace("constexpr int POLY = 8;", "constexpr int POLY = 9;", 1))
+    assert bench.kernel_source_hash() != key
