@@ -223,6 +223,26 @@ def test_contact_onset_short_push(pm, seed, n_sub):
     assert g[0, 0] - b.state[0, 0] > 1e-4
 
 
+@pytest.mark.parametrize("n_sub", [20, 40, 60])
+def test_box_box_onset_short_push(pm, n_sub):
+    """Two cubes in a row, 3 mm apart, and the pusher 3 mm behind the first:
+    the pusher reaches cube A after about seven substeps and A reaches cube
+    B a few substeps later, so face-face clipping between the cubes starts
+    mid-push and the contact list changes twice.  The FP32 path stays within
+    rounding of the FP64 oracle (about 1e-8 m measured): bar 1e-5 m, 1e-5."""
+    h = 0.02
+    b = single([srow((0.0, 0.0, h)), srow((2 * h + 3e-3, 0.0, h))],
+               [[h, h, h, 0.1, 0.5], [h, h, h, 0.1, 0.5]])
+    x0 = -h - 0.01 - 3e-3
+    push = np.array([[x0, 0.0, x0 + 0.05, 0.0]])
+    g, gs, _ = run_gpu(pm, b, push, n_sub)
+    o, os_, ov = run_oracle(b, push, n_sub)
+    assert gs[0] == 0 and ov[0] == 1
+    compare(g, o, 1e-5, 1e-5)
+    # both cubes were pushed: A by the pusher, B by A
+    assert g[0, 0] > 1e-3 and g[1, 0] - (2 * h + 3e-3) > 1e-3
+
+
 def test_invalid_push_discarded(pm):
     b = scenes.plain_push_scene(4)
     c0 = b.state[0, :2]
