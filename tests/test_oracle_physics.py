@@ -566,3 +566,263 @@ def test_clutter_pushes_keep_penetration_below_1mm():
     far = np.repeat(FAR[None], b.n_envs, 0)
     s2, _, _ = O.step(CFG, b.env_offset, st, b.body, far, 120, n_threads=4)
     assert np.abs(s2[:, 7:10]).max() < 1e-4
+
+
+# ---------------------------------------------------------------- contact bias v*
+# Box-plane contacts of a box resting on its face: four corner contacts, each
+# body's terms multiplied by 4 (mass splitting).  The vertical translation
+# mode then relaxes toward the target velocity v* geometrically: each Jacobi
+# iteration leaves (v - v*) times rho = a/(1+a) with
+# a = 3 (hy^2/(hy^2+hz^2) + hx^2/(hx^2+hz^2)) (the lever arms' torque terms);
+# the impulse stays positive while v < v*, so the clamp never acts, and the
+# symmetric corners give no torque and no friction.
+def _rho(h):
+    hx, hy, hz = h
+    a = 3 * (hy * hy / (hy * hy + hz * hz) + hx * hx / (hx * hx + hz * hz))
+    return a / (1 + a)
+
+
+@pytest.mark.parametrize("gap", [5e-4, 1e-3, 1.9e-3])
+def test_speculative_contact_stops_at_the_plane(gap):
+    """A box falling fast with its face `gap` above the table (inside the
+    2 mm margin, so the corners are speculative contacts with v* = -sep/dt):
+    after the velocity stage v = -v0 - g dt, and the solve leaves
+    v* + (v - v*) rho^I.  With enough iterations the box lands exactly on
+    the table in one substep (z drops by gap); a bias that ignored the gap
+    (v* = 0) or used Baumgarte here would stop it short or let it sink."""
+    h = (0.025, 0.02, 0.015)
+    v0 = 0.5
+    s0 = state_row(x=(0.01, -0.02, h[2] + gap), v=(0, 0, -v0))
+    bd = body_row(h)
+    vs = -gap / DT
+    vpre = -v0 - G * DT
+    s1, _ = O.velocity_solve(CFG, s0[None], bd[None], FAR)
+    assert s1[0, 9] == pytest.approx(vs + (vpre - vs) * _rho(h) ** 10, abs=1e-13)
+    assert np.abs(s1[0, [7, 8, 10, 11, 12]]).max() == 0.0
+    # 200 iterations: converged, the face meets the table after one substep
+    out, _, _ = run(s0, bd, 1, cfg=O.make_config(iters=200))
+    assert out[0, 9] == pytest.approx(vs, abs=1e-12)
+    assert out[0, 2] == pytest.approx(h[2], abs=1e-14)
+
+
+@pytest.mark.parametrize("depth", [3e-4, 5e-4, 1.5e-3, 4e-3])
+def test_baumgarte_bias_pushes_out_beyond_the_slop(depth):
+    """Gravity off, a box sunk `depth` into the table at rest: v* =
+    beta max(depth - slop, 0) / dt (beta 0.2, slop 0.5 mm), so after the
+    solve v_z = v* (1 - rho^I); within the slop nothing moves.  Dropping the
+    slop, the factor beta or the max would change v_z."""
+    h = (0.025, 0.02, 0.015)
+    cfg = O.make_config(gravity=0.0)
+    s0 = state_row(x=(-0.03, 0.02, h[2] - depth))
+    s1, _ = O.velocity_solve(cfg, s0[None], body_row(h)[None], FAR)
+    vs = 0.2 * max(depth - 0.0005, 0.0) / DT
+    assert s1[0, 9] == pytest.approx(vs * (1 - _rho(h) ** 10), abs=1e-15)
+    assert np.abs(s1[0, [7, 8, 10, 11, 12]]).max() == 0.0
+    if depth < 0.0005:
+        assert s1[0, 9] == 0.0
+
+
+# ---------------------------------------------------------------- SAT hysteresis
+@pytest.mark.parametrize("gain,want", [(0.5, 0), (2.0, 1)])
+def test_sat_face_hysteresis(gain, want):
+    """Two axis-aligned 4 cm cubes overlapping by 2 mm along x and by
+    2 mm - gain * tau_face along y (the edge crosses repeat these two face
+    values and never win): the kept axis (A's x face, candidate 0) is
+    replaced by A's y face (candidate 1) only when the gain exceeds
+    tau_face = 1e-5 m.  With the two tolerances swapped, or the comparison
+    reversed, the outcome flips."""
+    h = np.array([0.02, 0.02, 0.02])
+    tau = 1e-5
+    xb = np.array([0.038, 0.038 + gain * tau, 0.5])
+    idx, s = O.sat_axis(CFG, np.array([0, 0, 0.5]), [1, 0, 0, 0], h, xb, [1, 0, 0, 0], h)
+    assert idx == want
+    assert s == pytest.approx(-0.002 + (gain * tau if want == 1 else 0.0), abs=1e-15)
+
+
+def _crossed_cubes(D, h=0.02):
+    """Cube A turned 45 deg about x, cube B turned 45 deg about y, B at
+    height D above A.  By hand, with c = 1/sqrt(2): candidate 0 (A's x) and 4
+    (B's y): -h (1 + sqrt 2); candidates 1, 2, 3, 5 (the tilted faces):
+    c D - h (2 + c); candidate 7 (A's x cross B's y = z): D - 2 sqrt(2) h;
+    the four diagonal crosses: (D - 2 h (1 + sqrt 2)) / sqrt 3."""
+    c = math.sqrt(0.5)
+    qa = np.array([math.cos(math.pi / 8), math.sin(math.pi / 8), 0, 0])
+    qb = np.array([math.cos(math.pi / 8), 0, math.sin(math.pi / 8), 0])
+    s_face = c * D - h * (2 + c)
+    s_edge = D - 2 * math.sqrt(2) * h
+    return qa, qb, s_face, s_edge
+
+
+@pytest.mark.parametrize("gain,want", [(0.5, 1), (2.0, 7)])
+def test_sat_edge_hysteresis(gain, want):
+    """Crossed cubes placed so the vertical edge cross (candidate 7) beats
+    the best face axis (candidate 1, kept over candidate 0 by about
+    2.4 tau_edge) by gain * tau_edge (tau_edge = 5e-4 m): the edge axis is
+    taken only when the gain exceeds tau_edge."""
+    h = 0.02
+    c = math.sqrt(0.5)
+    tau_e = 5e-4
+    # s_edge - s_face = (1 - c) D - h (2 sqrt 2 - 2 - c)
+    D = (h * (2 * math.sqrt(2) - 2 - c) + gain * tau_e) / (1 - c)
+    qa, qb, s_face, s_edge = _crossed_cubes(D, h)
+    assert s_edge - s_face == pytest.approx(gain * tau_e, abs=1e-15)
+    assert s_face - (-h * (1 + math.sqrt(2))) > 1e-5    # candidate 1 replaced candidate 0
+    hh = np.array([h, h, h])
+    idx, s = O.sat_axis(CFG, np.array([0, 0, 0.5]), qa, hh, np.array([0, 0, 0.5 + D]), qb, hh)
+    assert idx == want
+    assert s == pytest.approx(s_edge if want == 7 else s_face, abs=1e-14)
+
+
+@pytest.mark.parametrize("deg,m,sg", [(3, 2, -1), (-3, 2, -1), (87, 1, -1), (-87, 1, 1), (177, 2, 1)])
+def test_incident_face_is_the_most_antiparallel(deg, m, sg):
+    """A wide slab A under a cube B turned `deg` degrees about x, its lowest
+    corner sunk 1 mm into A's top face (the reference face, normal +z).  The
+    incident face is B's face most anti-parallel to +z, worked by hand for
+    each turn: -z at +-3 deg, -y at 87 deg, +y at -87 deg, +z at 177 deg.
+    That face is 3 degrees off flat, so its four corners lie within the 2 mm
+    margin and inside the slab's side planes: they are the four contacts,
+    each moved down by half its separation.  Any other face gives other
+    points."""
+    hs = np.array([0.08, 0.08, 0.01])
+    b = 0.015
+    t = math.radians(deg)
+    qb = np.array([math.cos(t / 2), math.sin(t / 2), 0, 0])
+    R = rotm(qb)
+    fc_rel = R[:, m] * (sg * b)                     # centre of the incident face
+    p, q = (m + 1) % 3, (m + 2) % 3
+    rel = [fc_rel + R[:, p] * (sp * b) + R[:, q] * (sq * b) for sp in (-1, 1) for sq in (-1, 1)]
+    zb = 0.01 - 1e-3 - min(v[2] for v in rel)       # lowest corner 1 mm into the slab
+    xb = np.array([0.004, -0.003, zb])
+    st = np.stack([state_row(x=(0, 0, 0)), state_row(x=xb, q=qb)])
+    bd = np.stack([body_row(hs), body_row((b, b, b))])
+    c, _ = O.collide(CFG, st, bd)
+    cb = c[(c[:, 0] == 0) & (c[:, 1] == 1)]
+    want = sorted(tuple(np.r_[(xb + v)[:2], (xb + v)[2] - 0.5 * ((xb + v)[2] - 0.01)]) for v in rel)
+    got = sorted(tuple(r) for r in cb[:, 2:5])
+    assert len(got) == 4
+    assert np.abs(np.array(got) - np.array(want)).max() < 1e-15
+    assert np.all(cb[:, 7] == 1.0)
+
+
+# ---------------------------------------------------------------- edge-edge clamp
+# Boxes whose contact axis is an edge cross but whose extreme edges' lines
+# meet outside an edge: found by a seeded search and fixed here.
+CLAMPED_EDGE_CASES = [
+    # (ha, qa, hb, qb, xb): A at (0, 0, 0.5)
+    ([0.017414932991273953, 0.015061670780902179, 0.016574933338407066],
+     [0.990725966053111, -0.12453849422542944, -0.019349501582454565, 0.0507722407689798],
+     [0.026370923991877612, 0.01533813970212412, 0.023585684063590562],
+     [0.9155125086650393, -0.23172514231326702, 0.3275832416793309, 0.02880146990352309],
+     [0.03594487488313763, 0.03657031135666958, 0.48453121665425075]),
+    ([0.02424177608023499, 0.026723617898660533, 0.029869604812173416],
+     [0.9123693418764406, 0.12229268021545904, -0.32326728371601576, -0.21937399036471752],
+     [0.021595990462875726, 0.026993608669015526, 0.021477044143535167],
+     [0.2716704427505164, 0.645790693296601, 0.4467530395454545, -0.556382307989867],
+     [0.012799182479883302, -0.0496401325952576, 0.5485648750511334]),
+    ([0.025432471314809028, 0.0182353550387638, 0.01922911809583564],
+     [0.8155895979448917, -0.38389833279152646, -0.3657471772974586, -0.2316563836869548],
+     [0.011212104446687191, 0.02923698853226802, 0.02566350410332506],
+     [0.3901630345448309, 0.6446290274017771, -0.6529729676099169, -0.07650181093612361],
+     [-0.007766332720748408, 0.003545159956618298, 0.5753814297518842]),
+]
+
+
+def _extreme_edge(x, R, h, k, n):
+    """The edge of the box parallel to its axis k that lies furthest along n
+    (enumerated over the four parallel edges): its end points."""
+    best = None
+    for s1 in (-1, 1):
+        for s2 in (-1, 1):
+            o = [a for a in range(3) if a != k]
+            mid = x + R[:, o[0]] * (s1 * h[o[0]]) + R[:, o[1]] * (s2 * h[o[1]])
+            if best is None or mid @ n > best[0]:
+                best = (mid @ n, mid)
+    mid = best[1]
+    return mid - R[:, k] * h[k], mid + R[:, k] * h[k]
+
+
+@pytest.mark.parametrize("case", range(len(CLAMPED_EDGE_CASES)))
+def test_edge_contact_clamped_closest_points(case):
+    """The edge contact sits midway between the closest points of A's edge
+    extreme along +n and B's edge extreme along -n, the segments (not their
+    lines): here the lines' closest points lie outside a segment, so the
+    answer is a clamped point.  Checked against a bounded convex
+    minimisation of |P(s) - Q(t)|^2 over the two segments."""
+    from scipy.optimize import minimize
+    ha, qa, hb, qb, xb = (np.array(v, float) for v in CLAMPED_EDGE_CASES[case])
+    xa = np.array([0.0, 0.0, 0.5])
+    idx, s = O.sat_axis(CFG, xa, qa, ha, xb, qb, hb)
+    assert idx >= 6
+    i, j = (idx - 6) // 3, (idx - 6) % 3
+    RA, RB = rotm(qa), rotm(qb)
+    n = np.cross(RA[:, i], RB[:, j])
+    n /= np.linalg.norm(n)
+    if (xb - xa) @ n < 0:
+        n = -n
+    a0, a1 = _extreme_edge(xa, RA, ha, i, n)
+    b0, b1 = _extreme_edge(xb, RB, hb, j, -n)
+    # the lines' closest points fall outside at least one segment
+    M = np.array([a1 - a0, -(b1 - b0)]).T
+    st_line = np.linalg.lstsq(M, b0 - a0, rcond=None)[0]
+    assert np.any((st_line < 0) | (st_line > 1))
+    f = lambda z: float(np.sum((a0 + z[0] * (a1 - a0) - b0 - z[1] * (b1 - b0)) ** 2))
+    r = minimize(f, x0=[0.5, 0.5], bounds=[(0, 1), (0, 1)], method="L-BFGS-B",
+                 options=dict(ftol=1e-18, gtol=1e-14, maxiter=1000))
+    P = a0 + r.x[0] * (a1 - a0)
+    Q = b0 + r.x[1] * (b1 - b0)
+    st = np.stack([state_row(x=xa, q=qa), state_row(x=xb, q=qb)])
+    bd = np.stack([body_row(ha), body_row(hb)])
+    c, _ = O.collide(CFG, st, bd)
+    assert len(c) == 1
+    assert np.abs(c[0, 2:5] - 0.5 * (P + Q)).max() < 1e-9
+    assert np.abs(c[0, 5:8] - n).max() < 1e-12
+    assert c[0, 8] == pytest.approx(s, abs=1e-15)
+
+
+# ---------------------------------------------------------------- rollout rules
+def _rollout_scene(gap1):
+    """Three upright 4 cm cubes, axis-aligned: the target (0) at the origin,
+    cube 1 `gap1` to its +x side, cube 2 0.2 m away on -y.  Axis-aligned
+    resting cubes that nothing touches keep their footprints exactly (the
+    friction rows see no tangential velocity and the corner torques cancel)."""
+    h = 0.02
+    st = np.stack([state_row(x=(0, 0, h)), state_row(x=(2 * h + gap1, 0, h)), state_row(x=(0, -0.2, h))])
+    bd = np.stack([body_row((h, h, h))] * 3)
+    return st, bd
+
+
+def test_rollout_discarded_later_push_repeats_reward():
+    """Worked by hand.  Push 0 moves cube 2 further away along -y (contour
+    direction 2, starting on its +y side), so the target's nearest
+    neighbour stays cube 1 at 1 cm: r0 = 0.01 / 0.08.  Push 1 is cube 1's
+    direction 4 (start on its -x side): the pusher centre would sit
+    2 + 1 + 0.5 cm from cube 1's centre, inside the target, so it is
+    discarded: no substep runs and r1 repeats r0.  Push 2 (cube 2 again)
+    keeps the same clearance: r2 = r0.  Cubes 0 and 1 keep their footprints
+    (to rounding of their corner positions, below 1e-15)."""
+    st, bd = _rollout_scene(0.01)
+    r = O.rollout(CFG, st, bd, [(2, 2), (1, 4), (2, 2)], 120, 0, 0.08)
+    assert r["applied"] == 3
+    assert list(r["valid"]) == [1, 0, 1]
+    assert r["rewards"] == pytest.approx([0.125, 0.125, 0.125], abs=1e-12)
+    assert np.abs(r["state"][:2, [0, 1, 3, 4, 5, 6]] - st[:2, [0, 1, 3, 4, 5, 6]]).max() < 1e-15
+    assert r["state"][2, 1] < -0.2 - 0.03        # cube 2 was pushed away twice
+
+
+def test_rollout_discarded_first_push_ends_it():
+    """A discarded expansion push (the first) ends the rollout with no reward."""
+    st, bd = _rollout_scene(0.01)
+    r = O.rollout(CFG, st, bd, [(1, 4), (2, 2)], 120, 0, 0.08)
+    assert r["applied"] == 0 and r["valid"][0] == 0
+    assert np.array_equal(r["state"], st)
+
+
+def test_rollout_stops_after_reward_one():
+    """Cube 1 starts 4 cm from the target; pushing it away (direction 4,
+    start on its -x side in the gap, 5 cm toward +x, the last 4.5 cm in
+    contact) opens the gap past the 8 cm gripper width: r0 = 1 and the
+    rollout stops, leaving the second push unapplied."""
+    st, bd = _rollout_scene(0.04)
+    r = O.rollout(CFG, st, bd, [(1, 4), (2, 2)], 120, 0, 0.08)
+    assert r["applied"] == 1 and r["rewards"][0] == 1.0
+    assert r["state"][2, 1] == st[2, 1]          # cube 2 untouched: push 1 never ran
