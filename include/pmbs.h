@@ -44,6 +44,7 @@ typedef int32_t pmbs_status;
 #define PMBS_ERR_HIP (-3)
 #define PMBS_ERR_CAPACITY (-4)
 #define PMBS_ERR_STATE (-5)
+#define PMBS_ERR_HOST_MEMORY (-7) /* a host allocation failed */
 
 /* environment status bits */
 #define PMBS_ENV_CONTACT_OVERFLOW 1u /* more contacts than max_contacts; tail dropped */

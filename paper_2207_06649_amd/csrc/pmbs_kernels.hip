@@ -48,6 +48,17 @@ __device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y 
 __device__ __forceinline__ f3 cross(f3 a, f3 b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
+// Fused forms.  The library is built with contraction limited to single
+// source expressions, so every multiply-add that should be fused across a
+// helper call is written here; the rounding of each result is then fixed by
+// the source alone (the same in every kernel instantiation).
+// a * s + c per component
+__device__ __forceinline__ f3 fma3(f3 a, float s, f3 c) { return {fmaf(a.x, s, c.x), fmaf(a.y, s, c.y), fmaf(a.z, s, c.z)}; }
+// c + a x b
+__device__ __forceinline__ f3 cross_add(f3 a, f3 b, f3 c) {
+  return {fmaf(a.y, b.z, fmaf(-a.z, b.y, c.x)), fmaf(a.z, b.x, fmaf(-a.x, b.z, c.y)),
+          fmaf(a.x, b.y, fmaf(-a.y, b.x, c.z))};
+}
 // xyz of a float4 slot (the w lane is never read)
 __device__ __forceinline__ void st3(float4* d, f3 v) {
   d->x = v.x;
@@ -303,7 +314,7 @@ __device__ __forceinline__ int clip_group(Smem<K>& s, f3* P, int n, f3 f, f3 dir
   const unsigned long long gm = 0xffull << (8 * grp), below = ((1ull << lane) - 1ull) & gm;
   const int q = __popcll(mx & below) + __popcll(mc & below);
   const int m = __popcll(mx & gm) + __popcll(mc & gm);
-  if (emit_x && q < POLY) cl_put(s, buf, q, grp, Pp + (*P - Pp) * (dp * rcp(dp - dc)));
+  if (emit_x && q < POLY) cl_put(s, buf, q, grp, fma3(*P - Pp, dp * rcp(dp - dc), Pp));
   if (emit_c && q + (emit_x ? 1 : 0) < POLY) cl_put(s, buf, q + (emit_x ? 1 : 0), grp, *P);
   wave_sync();
   const int nn = m < POLY ? m : POLY;
@@ -1178,9 +1189,9 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
           acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
         }
       }
-      vw = vw + mk(md.x * acc.x + mo.x * acc.y + mo.y * acc.z,
-                   mo.x * acc.x + md.y * acc.y + mo.z * acc.z,
-                   mo.y * acc.x + mo.z * acc.y + md.z * acc.z);
+      vw = mk(fmaf(md.x, acc.x, fmaf(mo.x, acc.y, fmaf(mo.y, acc.z, vw.x))),
+              fmaf(mo.x, acc.x, fmaf(md.y, acc.y, fmaf(mo.z, acc.z, vw.y))),
+              fmaf(mo.y, acc.x, fmaf(mo.z, acc.y, fmaf(md.z, acc.z, vw.z))));
     };
     // warm start: the impulses carried over from the previous substep
     wave_sync();
@@ -1189,7 +1200,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
       const int c = 64 * sl + lane;
       if (c < nc) {
         const Contact& q = ct[sl];
-        const f3 P = q.n * q.ln + (q.t1 * q.lt1 + q.t2 * q.lt2);
+        const f3 P = fma3(q.n, q.ln, fma3(q.t1, q.lt1, q.t2 * q.lt2));
         st3(&s.u.imp[0][c], P);
         st3(&s.u.imp[1][c], cross(q.ra, P));
         st3(&s.u.imp[2][c], cross(q.rb, P));
@@ -1208,7 +1219,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
           const f3 t2 = q.t2;
           const int a = q.ab & 255, bb = (q.ab >> 8) & 255;
           f3 va = xyz(s.vel[a]), wa = xyz(s.ang[a]), vb = xyz(s.vel[bb]), wb = xyz(s.ang[bb]);
-          f3 u = (vb + cross(wb, q.rb)) - (va + cross(wa, q.ra));
+          f3 u = cross_add(wb, q.rb, vb) - cross_add(wa, q.ra, va);
           float ln = fmaxf(q.ln + q.kn * (q.vstar - dot(u, q.n)), 0.0f);
           float dln = ln - q.ln;
           q.ln = ln;
@@ -1223,7 +1234,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
           float dl1 = lt1 - q.lt1, dl2 = lt2 - q.lt2;
           q.lt1 = lt1;
           q.lt2 = lt2;
-          const f3 P = q.n * dln + (q.t1 * dl1 + t2 * dl2);
+          const f3 P = fma3(q.n, dln, fma3(q.t1, dl1, t2 * dl2));
           st3(&s.u.imp[0][c], P);
           st3(&s.u.imp[1][c], cross(q.ra, P));
           st3(&s.u.imp[2][c], cross(q.rb, P));
@@ -1250,7 +1261,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     // ---- 8. position stage
     if (active) {
       if (part == 0) {
-        x = x + v * dt;
+        x = fma3(v, dt, x);
       } else {
         float dw = -(w.x * q1 + w.y * q2 + w.z * q3);
         float dx = q0 * w.x + (w.y * q3 - w.z * q2);
@@ -1262,7 +1273,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         q0 *= il; q1 *= il; q2 *= il; q3 *= il;
       }
     }
-    xp = xp + vp * dt;
+    xp = fma3(vp, dt, xp);
     wave_sync();
   }
   if (deferred) break;

@@ -466,7 +466,7 @@ pmbs_status pmbs_server_create(const pmbs_server_config* cfg, void* d_workspace,
   if (!out) return fail(PMBS_ERR_INVALID_ARG, "out is null");
   const pmbs_sim_config sc = sim_config_of(*cfg);
   pmbs_server* srv = new (std::nothrow) pmbs_server();
-  if (!srv) return fail(PMBS_ERR_INVALID_ARG, "out of host memory");
+  if (!srv) return fail(PMBS_ERR_HOST_MEMORY, "out of host memory");
   srv->cfg = *cfg;
   if ((s = pmbs_sim_create(&sc, d_workspace, bytes, hip_stream, &srv->sim)) != PMBS_OK) {
     delete srv;

@@ -386,6 +386,7 @@ const char* pmbs_status_string(pmbs_status s) {
     case PMBS_ERR_CAPACITY: return "capacity exceeded";
     case PMBS_ERR_STATE: return "bad state";
     case PMBS_ERR_CANCELLED: return "cancelled";
+    case PMBS_ERR_HOST_MEMORY: return "out of host memory";
     default: return "unknown status";
   }
 }
@@ -440,7 +441,7 @@ pmbs_status pmbs_sim_create(const pmbs_sim_config* cfg, void* d_workspace, size_
   if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
     return fail(PMBS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   pmbs_sim* s = new (std::nothrow) pmbs_sim();
-  if (!s) return fail(PMBS_ERR_INVALID_ARG, "out of host memory");
+  if (!s) return fail(PMBS_ERR_HOST_MEMORY, "out of host memory");
   s->cfg = *cfg;
   s->stream = static_cast<hipStream_t>(hip_stream);
   char* base = static_cast<char*>(d_workspace);

@@ -132,9 +132,9 @@ pmbs_status pmbs_tree_create(const pmbs_tree_config* cfg, int32_t n_objects, flo
   if (cfg->max_depth < 1 || cfg->max_depth > 32 || cfg->n_envs < 1 || cfg->max_nodes < 1 || cfg->n_dirs < 1 ||
       !(cfg->gamma >= 0.0) || !(cfg->c >= 0.0))
     return fail(PMBS_ERR_INVALID_ARG, "bad tree config");
-  pmbs_tree* t = new (std::nothrow) pmbs_tree();
-  if (!t) return fail(PMBS_ERR_INVALID_ARG, "out of host memory");
   if (cfg->sim_depth < 0 || cfg->max_depth + cfg->sim_depth > 64) return fail(PMBS_ERR_INVALID_ARG, "bad sim_depth");
+  pmbs_tree* t = new (std::nothrow) pmbs_tree();
+  if (!t) return fail(PMBS_ERR_HOST_MEMORY, "out of host memory");
   t->cfg = *cfg;
   t->n_actions = n_objects * cfg->n_dirs;
   t->d_tree = cfg->max_depth;

@@ -20,6 +20,7 @@ PMBS_ENV_CONTACT_OVERFLOW = 1
 PMBS_ENV_NONFINITE = 2
 PMBS_ENV_PUSH_INVALID = 4
 PMBS_ERR_CANCELLED = -6
+PMBS_ERR_HOST_MEMORY = -7
 ROLLOUT_WRITE_STATE = 1
 ROLLOUT_QUEUE = 2
 ROLLOUT_GRAPH = 4

@@ -8,6 +8,7 @@ matching class."""
 import numpy as np
 import pytest
 
+from oracle import oracle as O
 from paper_2207_06649_amd import scenes
 
 pytestmark = pytest.mark.gpu
@@ -126,6 +127,17 @@ def test_class_split_matches_plain_launches_bitwise(pm, case):
         assert env_equal(b, e, got, ref128 if small_ok else ref256), e
 
 
+def test_contact_classes_give_identical_rollouts(pm, case):
+    """An env that fits the 128-contact kernel gets bitwise the same rewards,
+    status and child state from the 256-contact kernel: the result does not
+    depend on the class (so neither on the autotuned class threshold)."""
+    b, acts, off, tgt, ref128, ref256 = case
+    fits = [e for e in range(b.n_envs) if not (ref128[2][e] & 1)]
+    assert len(fits) > b.n_envs // 2
+    for e in fits:
+        assert env_equal(b, e, ref128, ref256), e
+
+
 def test_overflow_fallback_reruns_in_the_larger_class(pm, case):
     """Every env in the 128-contact kernel: those that overflow it finish in
     the 256-contact kernel with the plain 256-contact result."""
@@ -229,3 +241,29 @@ def test_two_level_fallback_reaches_the_512_contact_kernel(pm):
     c128 = Run(pm, b, 128).go(acts, off, tgt, SUB, 0)
     c256 = Run(pm, b, 256).go(acts, off, tgt, SUB, 0)
     assert c128[2][-1] & 1 and c256[2][-1] & 1 and not (ref[2][-1] & 1)
+
+
+def test_queued_graph_rollouts_match_the_oracle(pm):
+    """64 uneven envs (5-30 cuboids, 1-5 contour pushes of 20 substeps) in the
+    class-split persistent queues, replayed twice as a graph: every env's
+    reward count matches the FP64 oracle's rollout of the same actions and
+    its rewards agree within 1e-3 (80 um of clearance, inside the
+    multi-substep state bar of 1e-3 m)."""
+    b, acts, off, tgt = uneven_case(17, 64)
+    subs = 20
+    cfg = O.make_config()
+    refs = []
+    for e in range(b.n_envs):
+        lo, hi = b.env_offset[e], b.env_offset[e + 1]
+        od = [(int(a) // 8, int(a) % 8) for a in acts[off[e]:off[e + 1]]]
+        refs.append(O.rollout(cfg, f32(b.state[lo:hi]), f32(b.body[lo:hi]), od, subs, int(tgt[e]), 0.08))
+    r = Run(pm, b, 256)
+    r.sim.set_launch_plan(small_max_bodies=16)
+    for k in range(2):
+        r.rew.fill_(-5.0)
+        rew, cnt, status, _ = r.go(acts, off, tgt, subs, pm.ROLLOUT_QUEUE | pm.ROLLOUT_GRAPH)
+        assert not np.any(status & 3)
+        for e, ref in enumerate(refs):
+            n = ref["applied"]
+            assert cnt[e] == n, (k, e, cnt[e], n)
+            assert np.abs(rew[e, :n] - ref["rewards"]).max(initial=0.0) <= 1e-3, (k, e, rew[e, :n], ref["rewards"])

@@ -52,11 +52,20 @@ def run_oracle(batch, push, n_sub, threads=8):
     return st, status, valid
 
 
-def compare(g, o, pos_tol, q_tol):
+def compare(g, o, pos_tol, q_tol, v_tol):
+    """Position (m), quaternion and velocity bars.  Velocities: linear (m/s)
+    and angular (rad/s) per body, both under v_tol.  After one substep the
+    position bar alone would allow v errors of pos_tol / dt (2.4e-3 m/s),
+    so the velocity bar is set tighter (1e-4); over 240 substeps it is the
+    position bar over the 1 s simulated (1e-3)."""
     dp = np.linalg.norm(g[:, :3] - o[:, :3], axis=1).max()
     dq = qerr(g[:, 3:7], o[:, 3:7]).max()
+    dv = np.linalg.norm(g[:, 7:10] - o[:, 7:10], axis=1).max()
+    dw = np.linalg.norm(g[:, 10:13] - o[:, 10:13], axis=1).max()
     assert dp <= pos_tol, f"position error {dp:.3e} > {pos_tol}"
     assert dq <= q_tol, f"quaternion error {dq:.3e} > {q_tol}"
+    assert dv <= v_tol, f"linear velocity error {dv:.3e} > {v_tol}"
+    assert dw <= v_tol, f"angular velocity error {dw:.3e} > {v_tol}"
     return dp, dq
 
 
@@ -100,7 +109,7 @@ def test_ballistic_and_spin(pm, n_sub, tol):
                [[0.02, 0.02, 0.02, 0.1, 0.5], [0.03, 0.02, 0.01, 0.2, 0.4]])
     g, status, _ = run_gpu(pm, b, FAR, n_sub)
     o, _, _ = run_oracle(b, FAR, n_sub)
-    compare(g, o, tol, tol)
+    compare(g, o, tol, tol, 1e-4 if n_sub == 1 else tol)
     assert status[0] == 0
 
 
@@ -110,7 +119,7 @@ def test_resting_boxes(pm, n_sub, tol):
     b = scenes.clutter_batch(21, 1, 12)
     g, status, _ = run_gpu(pm, b, FAR, n_sub)
     o, _, _ = run_oracle(b, FAR, n_sub)
-    compare(g, o, tol, tol)
+    compare(g, o, tol, tol, 1e-4 if n_sub == 1 else tol)
     assert status[0] == 0
 
 
@@ -181,7 +190,7 @@ def test_plain_push_one_substep(pm, seed):
     push = touching_push(b)
     g, gs, _ = run_gpu(pm, b, push, 1)
     o, os_, ov = run_oracle(b, push, 1)
-    compare(g, o, 1e-5, 1e-5)
+    compare(g, o, 1e-5, 1e-5, 1e-4)
     assert ov[0] == 1 and gs[0] == 0
     oc, _ = O.collide(CFG, f32(b.state), f32(b.body), f32(push[0]))
     assert np.any(oc[:, 1] == 5)
@@ -218,7 +227,7 @@ def test_contact_onset_short_push(pm, seed, n_sub):
     g, gs, _ = run_gpu(pm, b, push, n_sub)
     o, os_, ov = run_oracle(b, push, n_sub)
     assert gs[0] == 0 and ov[0] == 1
-    compare(g, o, 1e-5, 1e-5)
+    compare(g, o, 1e-5, 1e-5, 1e-4)
     # the push reached cube 0: it moved along the push
     assert g[0, 0] - b.state[0, 0] > 1e-4
 
@@ -238,7 +247,7 @@ def test_box_box_onset_short_push(pm, n_sub):
     g, gs, _ = run_gpu(pm, b, push, n_sub)
     o, os_, ov = run_oracle(b, push, n_sub)
     assert gs[0] == 0 and ov[0] == 1
-    compare(g, o, 1e-5, 1e-5)
+    compare(g, o, 1e-5, 1e-5, 1e-4)
     # both cubes were pushed: A by the pusher, B by A
     assert g[0, 0] > 1e-3 and g[1, 0] - (2 * h + 3e-3) > 1e-3
 
@@ -250,7 +259,7 @@ def test_invalid_push_discarded(pm):
     g, gs, _ = run_gpu(pm, b, bad, 10)
     o, _, ov = run_oracle(b, bad, 10)
     assert gs[0] & 4 and ov[0] == 0
-    compare(g, o, 1e-5, 1e-5)
+    compare(g, o, 1e-5, 1e-5, 1e-4)
 
 
 # ------------------------------------------------------------- batched clutter
@@ -259,7 +268,7 @@ def test_batched_clutter_one_substep(pm):
     b = scenes.clutter_batch(1, 1024, 15)
     g, gs, _ = run_gpu(pm, b, b.push, 1)
     o, _, ov = run_oracle(b, b.push, 1)
-    compare(g, o, 1e-5, 1e-5)
+    compare(g, o, 1e-5, 1e-5, 1e-4)
     assert np.array_equal((gs & 4) == 0, ov == 1)
 
 
@@ -268,7 +277,7 @@ def test_uneven_clutter_one_substep(pm):
     b = scenes.clutter_batch(3, 256, (5, 30))
     g, gs, _ = run_gpu(pm, b, b.push, 1, max_contacts=512)
     o, _, ov = run_oracle(b, b.push, 1)
-    compare(g, o, 1e-5, 1e-5)
+    compare(g, o, 1e-5, 1e-5, 1e-4)
     assert np.array_equal((gs & 4) == 0, ov == 1)
 
 
@@ -285,20 +294,73 @@ def test_batched_clutter_120_substeps_invariants(pm):
         assert pen <= 1e-3, (e, pen)
 
 
+def test_clutter_settle_energy(pm):
+    """48 clutter envs (15 cuboids): a 120-substep push, then a settle of 120
+    substeps with the pusher parked far away (one warm-started settle: the
+    state after k settle substeps is the output of a k-substep call from the
+    post-push state).  Friction and inelastic contacts only remove energy;
+    the Baumgarte term lifts a penetrating body by at most beta (pen - slop)
+    per substep; the warm-started 10-iteration solve is not converged and
+    its warm-start impulses can do positive work in a substep where a
+    contact set changes (the FP64 oracle shows up to 3.4e-5 J per substep on
+    these scenes, 1.2e-6 J at 30 iterations, none at 100).  Bars: every
+    settle substep raises an env's energy by at most 1e-4 J plus the
+    Baumgarte allowance sum_i m_i g beta (pen_i - slop)+ (penetration from
+    the oracle's narrowphase on the GPU state); every env ends the settle
+    with less energy than it started with; penetration <= 1 mm
+    throughout."""
+    b = scenes.clutter_batch(1, 48, 15)
+    sim = pm.Sim(max_envs=b.n_envs, max_bodies=b.n_bodies)
+    sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+    sim.step(b.push.astype(np.float32), 120)
+    assert not np.any(sim.env_status() & 3)
+    post = sim.get_state().copy()
+    far = np.tile(FAR, (b.n_envs, 1)).astype(np.float32)
+    beta, slop, grav, ws = 0.2, 0.0005, 9.81, 1e-4
+
+    def energy_and_allowance(g):
+        E, allow = np.zeros(b.n_envs), np.full(b.n_envs, ws)
+        for e in range(b.n_envs):
+            lo, hi = b.env_offset[e], b.env_offset[e + 1]
+            E[e] = O.energy(CFG, g[lo:hi], b.body[lo:hi])
+            c, _ = O.collide(CFG, g[lo:hi], b.body[lo:hi])
+            for i in range(hi - lo):
+                sel = c[(c[:, 0] == i) | (c[:, 1] == i)]
+                if len(sel):
+                    pen = -sel[:, 8].min()
+                    assert pen <= 1e-3, (e, i, pen)
+                    allow[e] += b.body[lo + i, 3] * grav * beta * max(0.0, pen - slop)
+        return E, allow
+
+    E0, allow = energy_and_allowance(post.astype(np.float64))
+    E = E0
+    for k in range(1, 121):
+        sim.set_state(b.env_offset, post, f32(b.body))
+        sim.step(far, k)
+        g = sim.get_state().astype(np.float64)
+        assert np.isfinite(g).all() and not np.any(sim.env_status() & 3)
+        E1, allow1 = energy_and_allowance(g)
+        rise = E1 - (E + allow)
+        assert rise.max() <= 0.0, (k, int(rise.argmax()), rise.max())
+        E, allow = E1, allow1
+    assert np.all(E < E0), (E - E0).max()
+
+
 def test_contact_capacity_classes_agree(pm):
     """The 128-, 256- and 512-contact kernels run the same algorithm in the
-    same order; they differ only by FP32 rounding (each instantiation makes
-    its own fused multiply-add choices): 1 substep within 1e-6 m, 40 pushed
-    substeps within 1e-4 m."""
+    same order, and multiply-adds are fused only where the source says so,
+    so an environment's result does not depend on the class that ran it:
+    bitwise equal states and status words, after 1 and after 40 pushed
+    substeps."""
     b = scenes.clutter_batch(12, 64, 15)
-    for n_sub, tol in ((1, 1e-6), (40, 1e-4)):
+    for n_sub in (1, 40):
         outs = []
         for cap in (128, 256, 512):
             g, gs, _ = run_gpu(pm, b, b.push, n_sub, max_contacts=cap)
             assert not np.any(gs & 1)
-            outs.append(g)
-        for o in outs[1:]:
-            assert np.abs(o[:, :3] - outs[0][:, :3]).max() <= tol
+            outs.append((g, gs.copy()))
+        for o, os_ in outs[1:]:
+            assert np.array_equal(o, outs[0][0]) and np.array_equal(os_, outs[0][1])
 
 
 def grid_pile(n=31, e=0.04):
@@ -324,7 +386,7 @@ def test_contact_overflow_flagged_and_isolated(pm):
     cfg128 = O.make_config(max_contacts=128)
     o, os_, _ = O.step(cfg128, pile.env_offset, f32(pile.state), f32(pile.body), f32(FAR[None]), 1)
     assert os_[0] & 1
-    compare(g[:31], o, 1e-5, 1e-5)
+    compare(g[:31], o, 1e-5, 1e-5, 1e-4)
     alone, _, _ = run_gpu(pm, small, small.push, 1, max_contacts=128)
     assert np.array_equal(g[31:], alone)
 
@@ -342,12 +404,18 @@ def test_headline_shape_sampled_parity(pm):
         be = b.env(e)
         o, _, _ = run_oracle(be, be.push, 1, threads=1)
         lo, hi = b.env_offset[e], b.env_offset[e + 1]
-        compare(g[lo:hi], o, 1e-5, 1e-5)
+        compare(g[lo:hi], o, 1e-5, 1e-5, 1e-4)
     sim.set_state(b.env_offset, f32(b.state), f32(b.body))
     sim.step(b.push.astype(np.float32), 120)
     g = sim.get_state().astype(np.float64)
     st = sim.env_status()
     assert np.isfinite(g).all() and not np.any(st & 3)
+    # penetration (the oracle's FP64 narrowphase on the GPU state) <= 1 mm
+    for e in rng.choice(b.n_envs, 64, replace=False):
+        lo, hi = b.env_offset[e], b.env_offset[e + 1]
+        c, _ = O.collide(CFG, g[lo:hi], b.body[lo:hi])
+        pen = max(0.0, -c[:, 8].min()) if len(c) else 0.0
+        assert pen <= 1e-3, (e, pen)
 
 
 # ------------------------------------------------------------- determinism / packing

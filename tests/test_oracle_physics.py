@@ -436,6 +436,53 @@ def test_push_clutter_penetration_and_energy(seed):
     assert _max_penetration(s, b.body) <= 1e-3
 
 
+def _settle_energies(cfg, b, n_settle=120):
+    """Energy of every env after k = 0..n_settle substeps of one warm-started
+    settle (pusher parked) that follows the batch's 120-substep push, and
+    each env's Baumgarte allowance sum_i m_i g beta (pen_i - slop)+ at the
+    start of substep k+1."""
+    post, status, _ = O.step(cfg, b.env_offset, b.state, b.body, b.push, 120, n_threads=8)
+    assert not np.any(status)
+    far = np.tile(FAR, (b.n_envs, 1))
+    E = np.zeros((n_settle + 1, b.n_envs))
+    allow = np.zeros((n_settle + 1, b.n_envs))
+    for k in range(n_settle + 1):
+        s = post if k == 0 else O.step(cfg, b.env_offset, post, b.body, far, k, n_threads=8)[0]
+        for e in range(b.n_envs):
+            lo, hi = b.env_offset[e], b.env_offset[e + 1]
+            E[k, e] = O.energy(cfg, s[lo:hi], b.body[lo:hi])
+            c, _ = O.collide(cfg, s[lo:hi], b.body[lo:hi])
+            for i in range(hi - lo):
+                sel = c[(c[:, 0] == i) | (c[:, 1] == i)]
+                if len(sel):
+                    pen = -sel[:, 8].min()
+                    assert pen <= 1e-3
+                    allow[k, e] += b.body[lo + i, 3] * G * cfg.beta * max(0.0, pen - cfg.slop)
+    return E, allow
+
+
+def test_clutter_settle_energy_rise_is_solver_convergence():
+    """Energy on clutter after a push (pusher parked, one warm-started
+    settle).  With the configured 10 iterations the warm-start impulses of
+    the previous substep can do positive work where a contact set changes
+    (a box starting to tip), because 10 projected-Jacobi iterations do not
+    converge the solve: such rises stay below 1e-4 J per substep (beyond the
+    Baumgarte allowance) and every env still ends the settle with less
+    energy.  The rises shrink with the iteration count and are gone at 100
+    iterations (<= 1e-6 J, rounding), so they are the solver's residual,
+    not a source term of the transition."""
+    b = scenes.clutter_batch(1, 48, 15)
+    E, allow = _settle_energies(CFG, b)
+    rise = E[1:] - (E[:-1] + allow[:-1])
+    assert rise.max() <= 1e-4
+    assert np.all(E[-1] < E[0])
+    risers = sorted(set(np.nonzero(rise > 1e-6)[1].tolist()))
+    assert len(risers) >= 1   # the scene set exercises the effect
+    sub = scenes.concat([b.env(e) for e in risers])
+    E100, allow100 = _settle_energies(O.make_config(iters=100), sub)
+    assert (E100[1:] - (E100[:-1] + allow100[:-1])).max() <= 1e-6
+
+
 def test_invalid_push_start_is_discarded():
     b = scenes.plain_push_scene(4)
     c0 = b.state[0, :2]
