@@ -222,6 +222,30 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
                                 int32_t inputs_on_device, int32_t n_substeps, float width, float* d_rewards,
                                 int32_t max_h, int32_t* d_reward_count, int32_t flags, const pmbs_repurpose* rp);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): pmbs_sim_rollout
+ * with PMBS_ROLLOUT_QUEUE (flags may add only PMBS_ROLLOUT_WRITE_STATE),
+ * whose staged integer inputs, work lists, queue counters and overflow
+ * lists live in one fixed array of PMBS_STATIC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends, not in the
+ * simulator's workspace.  It calls no allocating routine: no hipMalloc,
+ * hipFree, stream or event creation; the contact classes run one after
+ * another on the simulator's stream (no side stream) with the simulator's
+ * launch plan.  At most PMBS_STATIC_MAX_ENVS envs and
+ * PMBS_STATIC_MAX_ACTIONS actions (PMBS_ERR_CAPACITY beyond).  Host inputs
+ * only; the call waits for its uploads, then returns with the launches
+ * queued.  Results equal pmbs_sim_rollout's bit for bit.  Every call on one
+ * GPU shares that GPU's array (counters are cleared at each call): calls
+ * that overlap on one GPU race; calls from several threads of one process
+ * are serialised by the library.  The simulator's device must be current. */
+#define PMBS_STATIC_MAX_ENVS 8192
+#define PMBS_STATIC_MAX_ACTIONS 65536
+#define PMBS_STATIC_SCRATCH_BYTES (576 * 1024)
+pmbs_status pmbs_sim_rollout_static(pmbs_sim_t* sim, const int32_t* actions, const int32_t* act_offset,
+                                    const int32_t* src_slot, const int32_t* child_slot, const int32_t* target,
+                                    int32_t n_substeps, float width, float* d_rewards, int32_t max_h,
+                                    int32_t* d_reward_count, int32_t flags);
+
 /* Status word per environment, cleared by every step.  A host destination
  * synchronises. */
 pmbs_status pmbs_sim_env_status(pmbs_sim_t* sim, uint32_t* status_out, int32_t dst_is_device);

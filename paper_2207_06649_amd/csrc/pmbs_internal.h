@@ -101,6 +101,14 @@ pmbs_status rewards_from_pool(pmbs_sim_t* sim, const int32_t* slots, const int32
 // the contour push of an action from a host SoA state (double precision)
 void contour_push_host(const pmbs_sim_config& cfg, const float* st, const float* bd, int n, int obj, int dir,
                        int n_dirs, float out[4]);
+// host rollout inputs against the env layout and capacities
+pmbs_status check_rollout_inputs(const pmbs_sim_t* sim, const int32_t* actions, const int32_t* act_offset,
+                                 const int32_t* src_slot, const int32_t* child_slot, const int32_t* target,
+                                 int32_t max_h);
+// queued rollouts: envs with at most this many bodies go to the 128-contact
+// kernel; an env's estimated work (longest first) under the launch plan
+int class_split(const pmbs_sim_t* sim);
+int64_t work_weight(const pmbs_sim_t* sim, const int32_t* act_offset, int e);
 // workgroups of a persistent launch of the given contact class
 int class_grid(pmbs_sim_t* sim, int max_contacts, int blocks_per_cu);
 // the queued rollout launches (all contact classes and fallbacks) on `stream`

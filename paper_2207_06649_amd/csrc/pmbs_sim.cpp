@@ -347,6 +347,38 @@ hipError_t enqueue_queued(pmbs_sim_t* sim, const StepArgs& a, hipStream_t stream
   return e;
 }
 
+pmbs_status check_rollout_inputs(const pmbs_sim_t* sim, const int32_t* actions, const int32_t* act_offset,
+                                 const int32_t* src_slot, const int32_t* child_slot, const int32_t* target,
+                                 int32_t max_h) {
+  const int n = sim->n_envs;
+  if (act_offset[0] != 0) return fail(PMBS_ERR_INVALID_ARG, "act_offset[0] must be 0");
+  for (int e = 0; e < n; ++e) {
+    const int h = act_offset[e + 1] - act_offset[e];
+    if (h < 0 || h > max_h || h > sim->cfg.max_horizon)
+      return fail(PMBS_ERR_CAPACITY, "env %d: horizon %d outside [0, min(max_h, max_horizon)]", e, h);
+    const int nb = sim->host_offset[e + 1] - sim->host_offset[e];
+    for (int k = act_offset[e]; k < act_offset[e + 1]; ++k)
+      if (actions[k] < 0 || actions[k] >= nb * 8)
+        return fail(PMBS_ERR_INVALID_ARG, "env %d: action %d out of range", e, actions[k]);
+    if (target[e] < 0 || target[e] >= nb) return fail(PMBS_ERR_INVALID_ARG, "env %d: target out of range", e);
+    if (src_slot && src_slot[e] >= sim->cfg.pool_slots) return fail(PMBS_ERR_CAPACITY, "env %d: source slot", e);
+    if (sim->pool_layout && src_slot[e] < 0) return fail(PMBS_ERR_INVALID_ARG, "env %d: needs a source slot", e);
+    if (child_slot && child_slot[e] >= sim->cfg.pool_slots) return fail(PMBS_ERR_CAPACITY, "env %d: child slot", e);
+    if ((src_slot && src_slot[e] >= 0) || (child_slot && child_slot[e] >= 0))
+      if (nb > sim->cfg.pool_stride) return fail(PMBS_ERR_CAPACITY, "env %d: %d bodies > pool_stride", e, nb);
+  }
+  return PMBS_OK;
+}
+
+int class_split(const pmbs_sim_t* sim) {
+  return sim->cfg.max_contacts == 128 ? PMBS_MAX_BODIES_PER_ENV : sim->plan.small_max_bodies;
+}
+
+int64_t work_weight(const pmbs_sim_t* sim, const int32_t* act_offset, int e) {
+  const int h = act_offset[e + 1] - act_offset[e], nb = sim->host_offset[e + 1] - sim->host_offset[e];
+  return sim->plan.order == 0 ? h : (int64_t)h * (nb + 4);
+}
+
 StepArgs step_args(pmbs_sim_t* sim) {
   StepArgs a;
   std::memset(&a, 0, sizeof a);  // padding too: launch arguments are compared bytewise
@@ -638,31 +670,17 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
   int total = 0;
   std::vector<int32_t> order, order_large;
   if (!inputs_on_device) {
-    if (act_offset[0] != 0) return fail(PMBS_ERR_INVALID_ARG, "act_offset[0] must be 0");
-    for (int e = 0; e < n; ++e) {
-      const int h = act_offset[e + 1] - act_offset[e];
-      if (h < 0 || h > max_h || h > sim->cfg.max_horizon)
-        return fail(PMBS_ERR_CAPACITY, "env %d: horizon %d outside [0, min(max_h, max_horizon)]", e, h);
-      const int nb = sim->host_offset[e + 1] - sim->host_offset[e];
-      for (int k = act_offset[e]; k < act_offset[e + 1]; ++k)
-        if (actions[k] < 0 || actions[k] >= nb * 8) return fail(PMBS_ERR_INVALID_ARG, "env %d: action %d out of range", e, actions[k]);
-      if (target[e] < 0 || target[e] >= nb) return fail(PMBS_ERR_INVALID_ARG, "env %d: target out of range", e);
-      if (src_slot && src_slot[e] >= sim->cfg.pool_slots) return fail(PMBS_ERR_CAPACITY, "env %d: source slot", e);
-      if (sim->pool_layout && src_slot[e] < 0) return fail(PMBS_ERR_INVALID_ARG, "env %d: needs a source slot", e);
-      if (child_slot && child_slot[e] >= sim->cfg.pool_slots) return fail(PMBS_ERR_CAPACITY, "env %d: child slot", e);
-      if ((src_slot && src_slot[e] >= 0) || (child_slot && child_slot[e] >= 0))
-        if (nb > sim->cfg.pool_stride) return fail(PMBS_ERR_CAPACITY, "env %d: %d bodies > pool_stride", e, nb);
-    }
+    pmbs_status cs = check_rollout_inputs(sim, actions, act_offset, src_slot, child_slot, target, max_h);
+    if (cs != PMBS_OK) return cs;
     total = act_offset[n];
     if (use_queue) {
       // contact class by body count, then largest estimated work first, ties
       // by env index (a deterministic schedule)
-      const int T = sim->cfg.max_contacts == 128 ? PMBS_MAX_BODIES_PER_ENV : sim->plan.small_max_bodies;
+      const int T = class_split(sim);
       std::vector<int64_t> wt(n);
       for (int e = 0; e < n; ++e) {
-        const int h = act_offset[e + 1] - act_offset[e], nb = sim->host_offset[e + 1] - sim->host_offset[e];
-        wt[e] = sim->plan.order == 0 ? h : (int64_t)h * (nb + 4);
-        (nb <= T ? order : order_large).push_back(e);
+        wt[e] = work_weight(sim, act_offset, e);
+        (sim->host_offset[e + 1] - sim->host_offset[e] <= T ? order : order_large).push_back(e);
       }
       auto by_work = [&](int a, int b) { return wt[a] > wt[b]; };
       std::stable_sort(order.begin(), order.end(), by_work);

@@ -95,6 +95,8 @@ def lib():
                                           vp, C.c_int32, C.POINTER(Repurpose)]
         L.pmbs_sim_rollout.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_float, vp, C.c_int32,
                                        vp, C.c_int32]
+        L.pmbs_sim_rollout_static.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, C.c_float, vp, C.c_int32, vp,
+                                              C.c_int32]
         L.pmbs_sim_shape.argtypes = [vp, ip, ip]
         _lib = L
     return _lib
@@ -308,6 +310,21 @@ class Sim:
                                          C.byref(rp)))
         self.sync()
         return rew.cpu().numpy(), cnt.cpu().numpy(), xrew.cpu().numpy(), xcnt.cpu().numpy()
+
+    def rollout_static(self, actions, act_offset, target, n_substeps=120, width=0.08, src_slot=None,
+                       child_slot=None, max_h=None, flags=ROLLOUT_WRITE_STATE, rewards=None, counts=None):
+        """The queued rollout with its scratch in the library's fixed device
+        array (pmbs_sim_rollout_static); rewards / counts are caller-owned
+        device tensors, returned after a synchronisation."""
+        t = self.torch
+        off, acts, tg, mh, ss, cs = self._rollout_inputs(actions, act_offset, target, src_slot, child_slot, max_h)
+        rew = rewards if rewards is not None else t.full((self.n_envs, mh), -1.0, dtype=t.float32, device=self.device)
+        cnt = counts if counts is not None else t.zeros(self.n_envs, dtype=t.int32, device=self.device)
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
+        _check(lib().pmbs_sim_rollout_static(self.handle, ptr(acts), ptr(off), ptr(ss), ptr(cs), ptr(tg),
+                                             int(n_substeps), float(width), _ptr(rew), mh, _ptr(cnt), int(flags)))
+        self.sync()
+        return rew.cpu().numpy(), cnt.cpu().numpy()
 
     def set_launch_plan(self, small_max_bodies=16, small_blocks_per_cu=0, large_blocks_per_cu=0, order=1):
         p = LaunchPlan(small_max_bodies, small_blocks_per_cu, large_blocks_per_cu, order)
