@@ -53,6 +53,9 @@ typedef int32_t pmbs_status;
 
 /* bodies per environment, excluding the pusher */
 #define PMBS_MAX_BODIES_PER_ENV 31
+/* start-pose validity words per state: one bit per sampled contour push
+ * (8 directions per object, Sec. IV-B) */
+#define PMBS_VALID_WORDS 8
 
 const char* pmbs_status_string(pmbs_status s);
 const char* pmbs_last_error(void);
@@ -140,6 +143,9 @@ pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_de
 #define PMBS_ROLLOUT_GRAPH 4       /* with PMBS_ROLLOUT_QUEUE: replay the launches as one captured
                                       hipGraph (captured on first use and again whenever the
                                       launch arguments or the plan change) */
+#define PMBS_ROLLOUT_CHILD_VALID 8 /* an env with a child slot whose first push was valid writes
+                                      the start-pose validity words of the child's state to the
+                                      simulator's validity buffer (pmbs_sim_push_valid) */
 
 /* Batch expansion + batch simulation (Sec. IV-C) in one launch: env e runs
  * the contour pushes actions[act_offset[e] .. act_offset[e+1]) (packed as
@@ -205,7 +211,8 @@ typedef struct pmbs_repurpose {
   const int32_t* src_slot;   /* pool slot of the extra simulation's node */
   const int32_t* action;     /* its first push (obj * 8 + dir) */
   const int32_t* node_id;    /* node id keying its random pushes */
-  const int32_t* replica;    /* replica index keying its random pushes */
+  const int32_t* replica;    /* replica index keying its random pushes (< 2^24) */
+  const int32_t* horizon;    /* pushes at most (its pair's horizon, < 256); NULL: the pushes left */
   const uint64_t* seed;      /* Philox key of its random pushes */
   float* d_rewards;          /* device [n_envs][max_h] */
   int32_t* d_counts;         /* device [n_envs]: rewards written (0: none) */
@@ -224,7 +231,8 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
 
 /* For callers that cannot allocate device memory (code under graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): pmbs_sim_rollout
- * with PMBS_ROLLOUT_QUEUE (flags may add only PMBS_ROLLOUT_WRITE_STATE),
+ * with PMBS_ROLLOUT_QUEUE (flags may add PMBS_ROLLOUT_WRITE_STATE and
+ * PMBS_ROLLOUT_CHILD_VALID),
  * whose staged integer inputs, work lists, queue counters and overflow
  * lists live in one fixed array of PMBS_STATIC_SCRATCH_BYTES that the
  * library holds on every GPU it runs on until the process ends, not in the
@@ -245,6 +253,21 @@ pmbs_status pmbs_sim_rollout_static(pmbs_sim_t* sim, const int32_t* actions, con
                                     const int32_t* src_slot, const int32_t* child_slot, const int32_t* target,
                                     int32_t n_substeps, float width, float* d_rewards, int32_t max_h,
                                     int32_t* d_reward_count, int32_t flags);
+
+/* Start-pose validity of the sampled pushes of every env's state (Sec.
+ * IV-B: the sampled pushes whose start pose collides with an object are
+ * discarded): PMBS_VALID_WORDS words per env into the simulator's validity
+ * buffer, bit a of word a / 32 set when contour push a (obj * 8 + dir) can
+ * start, i.e. when the pusher at its start pose clears every box by the
+ * same test that discards a push as it begins.  src_slot (optional, host
+ * or device per inputs_on_device): env e's state from pool slot
+ * src_slot[e], skipped when < 0; NULL: every env from its own state.
+ * Asynchronous (a host src_slot is uploaded before the call returns). */
+pmbs_status pmbs_sim_valid_pushes(pmbs_sim_t* sim, const int32_t* src_slot, int32_t inputs_on_device);
+
+/* The validity buffer, [n_envs][PMBS_VALID_WORDS]; a host destination
+ * synchronises. */
+pmbs_status pmbs_sim_push_valid(pmbs_sim_t* sim, uint32_t* out, int32_t dst_is_device);
 
 /* Status word per environment, cleared by every step.  A host destination
  * synchronises. */
@@ -308,6 +331,10 @@ typedef struct pmbs_tree_config {
                            dynamic depth of Sec. IV-A (0: off) */
     int32_t repurpose;  /* re-purpose environments whose simulation ends early (Sec. IV-C,
                            batch simulation): see pmbs_tree_extra (0: off) */
+    int32_t discard;    /* discard a node's sampled pushes whose start pose collides before
+                           any selection (Sec. IV-B): pmbs_plan and the server compute the
+                           validity words on the device (1, the default; 0: keep them, a
+                           colliding push is dropped when its simulation starts) */
 } pmbs_tree_config;
 
 typedef struct pmbs_tree pmbs_tree_t;
@@ -355,20 +382,27 @@ pmbs_status pmbs_tree_update(pmbs_tree_t* tree, const float* rewards, int32_t ma
  * pushes left on one extra simulation of the next pair in round-robin
  * order, p' = (p + 1) mod P, as replica R + e (R = ceil(n_envs / P) static
  * replicas): first the pair's action, then random pushes keyed by (node id,
- * action, replica, push index) as for the static replicas.  This returns,
- * for every env of the last selection (host, n_envs entries each), that
- * pair's node pool slot, action, node id and the replica index; the device
+ * action, replica, push index) as for the static replicas, at most p''s own
+ * horizon d_T + d_s - depth (its simulations end at the depth limit,
+ * Sec. IV-A).  This returns, for every env of the last selection (host,
+ * n_envs entries each), that pair's node pool slot, action, node id, the
+ * replica index and (optional, may be NULL) that horizon; the device
  * runs the extra simulation (pmbs_sim_rollout_ex) only when the env stops
  * early. */
 pmbs_status pmbs_tree_extra(const pmbs_tree_t* tree, int32_t* src_slot, int32_t* action, int32_t* node_id,
-                            int32_t* replica);
+                            int32_t* replica, int32_t* horizon);
 
 /* pmbs_tree_update plus the extra simulations' rewards [n_envs][max_h] and
- * counts (0: none ran, or its first push was discarded); a valid extra
- * simulation's return joins its pair's maximum. */
+ * counts (0: none ran, or its first push was discarded; both NULL without
+ * re-purposing); a valid extra simulation's return joins its pair's
+ * maximum.  child_valid (optional, host [n_envs][PMBS_VALID_WORDS]): the
+ * start-pose validity words of the state of each env that made a child
+ * (pmbs_sim_push_valid after a rollout with PMBS_ROLLOUT_CHILD_VALID); the
+ * new node's sampled actions that cannot start are discarded before any
+ * selection (Sec. IV-B). */
 pmbs_status pmbs_tree_update_ex(pmbs_tree_t* tree, const float* rewards, int32_t max_h, const int32_t* counts,
                                 const uint32_t* env_status, const float* extra_rewards, const int32_t* extra_counts,
-                                int32_t* n_children);
+                                const uint32_t* child_valid, int32_t* n_children);
 
 /* Alg. 1 (early_stop): a child whose first reward is 1 stands in for a node
  * the grasp classifier accepts (graspable).  The early-stop level starts at
@@ -380,6 +414,15 @@ pmbs_status pmbs_tree_update_ex(pmbs_tree_t* tree, const float* rewards, int32_t
  * level (optional) receive the current values. */
 pmbs_status pmbs_tree_status(const pmbs_tree_t* tree, int32_t* done, int32_t* level, int32_t* d_tree,
                              int32_t* d_sim);
+
+/* Start-pose validity of a node's sampled pushes (Sec. IV-B: actions that
+ * cannot be executed because of collisions are discarded): bit a of
+ * words[a / 32] set when action a can start (words from
+ * pmbs_sim_valid_pushes / pmbs_sim_push_valid, PMBS_VALID_WORDS of them).
+ * The node keeps only the valid actions, in their shuffled order.  Only
+ * before anything was selected from the node (the root right after
+ * creation); PMBS_ERR_INVALID_ARG otherwise. */
+pmbs_status pmbs_tree_set_valid(pmbs_tree_t* tree, int32_t node_id, const uint32_t* words);
 
 /* The root child with the best average reward Q/N (Sec. III-B); ties to
  * more visits, then the lower action.  action = -1 without children. */
@@ -468,6 +511,7 @@ typedef struct pmbs_server_config {
   int32_t graph;          /* replay the batched launch as a captured graph */
   int32_t early_stop;     /* Alg. 1 early stop in every request's tree (pmbs_tree_status) */
   int32_t repurpose;      /* environment re-purposing in every request (pmbs_tree_extra) */
+  int32_t discard;        /* discard colliding sampled pushes before selection (pmbs_tree_config) */
 } pmbs_server_config;
 
 typedef struct pmbs_request {

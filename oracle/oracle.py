@@ -87,6 +87,7 @@ def lib():
         L.orc_reward.argtypes = [C.c_int32, dp, dp, C.c_int32, C.c_double]
         L.orc_reward.restype = C.c_double
         L.orc_contour_push.argtypes = [cp, dp, dp, C.c_int32, C.c_int32, dp]
+        L.orc_valid_pushes.argtypes = [cp, C.c_int32, dp, dp, C.c_int32, ip]
         L.orc_rollout.argtypes = [cp, C.c_int32, dp, dp, ip, C.c_int32, C.c_int32, C.c_int32,
                                   C.c_int32, C.c_double, dp, ip, dp, ip]
         _lib = L
@@ -206,6 +207,17 @@ def contour_push(cfg, state13, body5, direction: int, n_dirs: int = 8):
     if lib().orc_contour_push(C.byref(cfg), _d(s), _d(b), direction, n_dirs, _d(out)) != 0:
         raise ValueError("bad contour push")
     return out
+
+
+def valid_pushes(cfg, state, body, n_dirs: int = 8) -> np.ndarray:
+    """Start-pose validity (bool [nb * n_dirs]) of every contour push of the
+    state: the pusher at the push's start separated from every box."""
+    st = _f64(state, (-1, 13))
+    bd = _f64(body, (-1, 5))
+    out = np.zeros(st.shape[0] * n_dirs, np.int32)
+    if lib().orc_valid_pushes(C.byref(cfg), st.shape[0], _d(st), _d(bd), n_dirs, _i(out)) != 0:
+        raise ValueError("orc_valid_pushes failed")
+    return out.astype(bool)
 
 
 def rollout(cfg, state, body, obj_dir, substeps: int, target: int, width: float = 0.08,

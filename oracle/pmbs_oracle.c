@@ -891,6 +891,28 @@ int orc_contour_push(const orc_config* cfg, const double* state13, const double*
     return 0;
 }
 
+/* Start-pose validity of every sampled contour push of a state (Sec. IV-B:
+ * the sampled pushes whose start pose collides with an object are
+ * discarded): action a = obj * n_dirs + dir is valid iff push begin finds
+ * the pusher at the push's start separated from every box.  valid_out has
+ * nb * n_dirs entries. */
+int orc_valid_pushes(const orc_config* cfg, int32_t nb, const double* state, const double* body, int32_t n_dirs,
+                     int32_t* valid_out) {
+    if (!check_env(nb) || n_dirs <= 0) return -1;
+    env_t e;
+    if (!env_alloc(&e, 8)) { env_free(&e); return -2; }
+    load(&e, cfg, nb, state, body);
+    for (int obj = 0; obj < nb; ++obj)
+        for (int dir = 0; dir < n_dirs; ++dir) {
+            double push[4];
+            contour_push(cfg, &e.body[obj], dir, n_dirs, push);
+            push_begin(&e, cfg, push);
+            valid_out[obj * n_dirs + dir] = e.valid;
+        }
+    env_free(&e);
+    return 0;
+}
+
 /* Rollout of one env through a sequence of contour pushes (obj, dir) with a
  * reward after every push (Sec. IV-C, batch simulation); stops after the
  * first push whose reward is 1.  A push whose start pose overlaps a box is

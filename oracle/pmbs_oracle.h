@@ -40,6 +40,8 @@ double orc_clearance(int32_t nb, const double* state, const double* body, int32_
 double orc_reward(int32_t nb, const double* state, const double* body, int32_t target, double width);
 int orc_contour_push(const orc_config* cfg, const double* state13, const double* body5, int32_t dir,
                      int32_t n_dirs, double* push);
+int orc_valid_pushes(const orc_config* cfg, int32_t nb, const double* state, const double* body, int32_t n_dirs,
+                     int32_t* valid_out);
 int orc_rollout(const orc_config* cfg, int32_t nb, double* state, const double* body,
                 const int32_t* obj_dir, int32_t n_push, int32_t n_dirs, int32_t substeps,
                 int32_t target, double width, double* rewards, int32_t* valid,

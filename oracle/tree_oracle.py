@@ -34,7 +34,12 @@ What it follows in the paper:
     h - t - 1 pushes of budget left; it spends them on one extra simulation
     of the next pair in round-robin order, p' = (p + 1) mod P, as replica
     R + e (R = ceil(N_e / P) static replicas, e the environment), truncated
-    to the budget.  A valid extra simulation joins pair p''s maximum.
+    to the budget and to p''s own horizon (its simulations end at the depth
+    limit, Sec. IV-A).  A valid extra simulation joins pair p''s maximum.
+  * Optional (discard): the sampled pushes of a node whose start pose
+    collides with an object are discarded when the node is created, before
+    any selection takes one (Sec. IV-B, action sampling); its untried list
+    keeps the valid ones in their shuffled order.
 
 Readings where the paper is silent: a node is
 a leaf for Alg. 2 when its depth is below D and it has an untried action,
@@ -166,12 +171,14 @@ class Planner:
           actions in order, stopping after the first reward of 1; valid is
           whether the first action could start; rewards[t] after push t.
       root_reward(state) -> float
+      valid_actions(state) -> sequence of bool (discard only): whether
+          each sampled action can start from the state.
     """
 
     def __init__(self, env, root_state, n_envs, c=1.4, gamma=0.8, depth=5, seed=0, sim_depth=0, early_stop=False,
-                 repurpose=False):
+                 repurpose=False, discard=False):
         self.env, self.n_envs, self.c, self.gamma, self.D, self.seed = env, n_envs, c, gamma, depth, seed
-        self.Ds, self.early_stop, self.repurpose = sim_depth, early_stop, repurpose
+        self.Ds, self.early_stop, self.repurpose, self.discard = sim_depth, early_stop, repurpose, discard
         self.extra_simulations = 0
         self.es_level = 1
         self.graspable = []
@@ -199,7 +206,11 @@ class Planner:
         nid = self.next_id
         self.next_id += 1
         na = self.env.n_actions(state)
-        n = Node(nid, parent, action, depth, state, reward, shuffled_actions(na, nid, self.seed))
+        untried = shuffled_actions(na, nid, self.seed)
+        if self.discard:
+            ok = self.env.valid_actions(state)
+            untried = [a for a in untried if ok[a]]
+        n = Node(nid, parent, action, depth, state, reward, untried)
         n.terminal = reward >= 1.0
         return n
 
@@ -229,9 +240,9 @@ class Planner:
                 h = self.D + self.Ds - n.depth
                 if not valid or not rewards or rewards[-1] < 1.0 or len(rewards) >= h:
                     continue
-                budget = h - len(rewards)
                 q = (pi + 1) % P
                 nq, aq = pairs[q]
+                budget = min(h - len(rewards), self.D + self.Ds - nq.depth)
                 na = self.env.n_actions(nq.state)
                 acts = [aq] + [rollout_action(nq.id, aq, R + e, t, na, self.seed) for t in range(1, budget)]
                 v2, _, rw2 = self.env.run(nq.state, acts)
@@ -280,6 +291,9 @@ class PhysicsEnv:
 
     def root_reward(self, state):
         return self.O.reward(state, self.body, self.target, self.width)
+
+    def valid_actions(self, state):
+        return self.O.valid_pushes(self.cfg, state, self.body, self.n_dirs)
 
     def run(self, state, actions):
         od = [(a // self.n_dirs, a % self.n_dirs) for a in actions]

@@ -37,6 +37,7 @@ struct pmbs_sim {
   uint32_t* d_x_key;       // [max_envs][2] their Philox keys
   float* d_x_rewards;      // [max_envs][max_horizon] extra simulations' rewards (planner, server)
   int32_t* d_x_counts;     // [max_envs]
+  uint32_t* d_valid;       // [max_envs][PMBS_VALID_WORDS] start-pose validity words
   int cus = 0, occ[3] = {0, 0, 0};   // CUs; resident blocks per CU of the 128/256/512 kernels
   pmbs_launch_plan plan;
   // internal streams and events for the concurrent class launches and graph capture

@@ -51,6 +51,12 @@ struct StepArgs {
   const uint2* x_key;
   float* x_rewards;
   int* x_count;
+  // start-pose validity (Sec. IV-B): env e writes PMBS_VALID_WORDS words at
+  // valid_out[e * PMBS_VALID_WORDS], bit a set when contour push a can
+  // start; in a rollout for the state after the first push of an env with a
+  // child slot (null: none); valid_only: only that, for the loaded state
+  uint32_t* valid_out;
+  int valid_only;
   // work distribution
   const int* order;         // work item -> env (null: identity)
   int* queue;               // device counter (null: one block per work item)

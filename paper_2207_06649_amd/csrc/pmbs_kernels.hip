@@ -169,33 +169,111 @@ __device__ __forceinline__ float radius_along(const Box& b, f3 L) {
   return b.h.x * fabsf(dot(b.a0, L)) + b.h.y * fabsf(dot(b.a1, L)) + b.h.z * fabsf(dot(b.a2, L));
 }
 
-// candidate axis idx: 0-2 faces of A, 3-5 faces of B, 6-14 edge crosses
-// (axes are read from LDS so the loop need not be unrolled)
-template <int K>
-__device__ __forceinline__ bool sat_axis(const Smem<K>& s, int ia, int ib, int idx, float eps, f3* L) {
-  if (idx < 3) { *L = xyz(s.col[idx][ia]); return true; }
-  if (idx < 6) { *L = xyz(s.col[idx - 3][ib]); return true; }
-  f3 v = cross(xyz(s.col[(idx - 6) / 3][ia]), xyz(s.col[(idx - 6) % 3][ib]));
-  float len = sqrtf(dot(v, v));
-  if (len < eps) return false;
-  *L = v * (1.0f / len);
-  return true;
+// Whether the separating-axis test keeps boxes A and B apart: the maximum
+// over the candidate axes (faces of A, faces of B, edge crosses with
+// |a x b| >= eps) of s(L) = |d.L| - r_A(L) - r_B(L) is > 0.  The face axes
+// come first and the edge axes are skipped once a face axis has s > 0 (the
+// maximum is then > 0 whatever they give), so the decision is that of the
+// full maximum.  Every start-pose test goes through this one function.
+__device__ __forceinline__ bool sat_clear(const Box& A, const Box& B, float eps) {
+  const f3 d = B.c - A.c;
+  float best = -INFINITY;
+#pragma unroll
+  for (int idx = 0; idx < 6; ++idx) {
+    const f3 L = idx < 3 ? axis(A, idx) : axis(B, idx - 3);
+    best = fmaxf(best, fabsf(dot(d, L)) - radius_along(A, L) - radius_along(B, L));
+  }
+  if (best > 0.0f) return true;
+#pragma unroll 1
+  for (int idx = 0; idx < 9; ++idx) {
+    const f3 v = cross(axis(A, idx / 3), axis(B, idx % 3));
+    const float len = sqrtf(dot(v, v));
+    if (len < eps) continue;
+    const f3 L = v * (1.0f / len);
+    best = fmaxf(best, fabsf(dot(d, L)) - radius_along(A, L) - radius_along(B, L));
+  }
+  return best > 0.0f;
 }
 
-// max over the candidate axes of s(L) = |d.L| - r_A(L) - r_B(L)
+// The contour push a = obj * n_dirs + dir (Sec. IV-B): direction dir of
+// n_dirs around object obj in its yaw frame, starting beyond the
+// footprint's ray-to-boundary distance by the pusher half width plus the
+// standoff, moving push_length toward the object centre; (x_s, y_s, x_e, y_e).
 template <int K>
-__device__ __forceinline__ float sat_max(const Smem<K>& s, int ia, int ib, float eps) {
-  const Box A = load_box(s, ia), B = load_box(s, ib);
-  f3 d = B.c - A.c;
-  float best = -INFINITY;
-#pragma unroll 1
-  for (int idx = 0; idx < 15; ++idx) {
-    f3 L;
-    if (!sat_axis(s, ia, ib, idx, eps, &L)) continue;
-    float sv = fabsf(dot(d, L)) - radius_along(A, L) - radius_along(B, L);
-    best = fmaxf(best, sv);
+__device__ __forceinline__ float4 contour_start(const Smem<K>& s, int obj, int dir, const Params& p) {
+  const f3 oc = xyz(s.pos[obj]), oa0 = xyz(s.col[0][obj]), oh = xyz(s.half[obj]);
+  const float th = 6.283185307179586f * (float)dir / (float)p.n_dirs;
+  const float cth = cosf(th), sth = sinf(th);
+  const float rx = fabsf(cth) > 0.0f ? oh.x / fabsf(cth) : INFINITY;
+  const float ry = fabsf(sth) > 0.0f ? oh.y / fabsf(sth) : INFINITY;
+  const float ray = fminf(rx, ry);
+  const float yaw = atan2f(oa0.y, oa0.x);
+  const float cy = cosf(yaw), sy = sinf(yaw);
+  const float ddx = cy * cth - sy * sth, ddy = sy * cth + cy * sth;
+  const float off = ray + p.phx + p.push_standoff;
+  const float sxp = oc.x + off * ddx, syp = oc.y + off * ddy;
+  return make_float4(sxp, syp, sxp - p.push_length * ddx, syp - p.push_length * ddy);
+}
+
+// The pusher of a push: unit direction, moving substeps, start centre and
+// its first two rotation columns (yaw along the push).
+struct PusherPose {
+  f3 dir, x, c0, c1;
+  int n_move;
+};
+__device__ __forceinline__ PusherPose pusher_pose(float4 push, const Params& p) {
+  PusherPose r;
+  r.dir = mk(1, 0, 0);
+  const float dx = push.z - push.x, dy = push.w - push.y;
+  const float len = sqrtf(dx * dx + dy * dy);
+  if (len > 0.0f) r.dir = mk(dx / len, dy / len, 0.0f);
+  r.n_move = (int)roundf(len / (p.push_speed * p.dt));
+  r.x = mk(push.x, push.y, p.pusher_z);
+  const float yaw = atan2f(r.dir.y, r.dir.x);
+  const float cy = cosf(0.5f * yaw), sy = sinf(0.5f * yaw);
+  // rotation about z from the half-angle quaternion (cy, 0, 0, sy)
+  r.c0 = mk(1.0f - 2.0f * sy * sy, 2.0f * cy * sy, 0.0f);
+  r.c1 = mk(-2.0f * cy * sy, 1.0f - 2.0f * sy * sy, 0.0f);
+  return r;
+}
+
+__device__ __forceinline__ Box pusher_box(const PusherPose& q, const Params& p) {
+  Box b;
+  b.c = q.x;
+  b.a0 = q.c0;
+  b.a1 = q.c1;
+  b.a2 = mk(0, 0, 1);
+  b.h = mk(p.phx, p.phy, p.phz);
+  return b;
+}
+
+// Start-pose validity of every contour push of the env whose body frames
+// are in LDS (Sec. IV-B: pushes that cannot start because of a collision
+// are discarded): lane l takes actions l, l + 64, ...; an action is valid
+// when its pusher start pose clears every box.  Lane w < PMBS_VALID_WORDS
+// returns word w (bit a mod 32 of word a / 32 set when action a is valid);
+// the other lanes return 0.
+template <int K>
+__device__ __forceinline__ unsigned validity_word(const Smem<K>& s, int nb, const Params& p, int lane) {
+  const int n_act = nb * p.n_dirs;
+  unsigned word = 0u;
+  for (int a0 = 0; a0 < n_act; a0 += 64) {
+    const int a = a0 + lane;
+    bool ok = false;
+    if (a < n_act) {
+      const int obj = a / p.n_dirs, dir = a - obj * p.n_dirs;
+      const Box P = pusher_box(pusher_pose(contour_start(s, obj, dir, p), p), p);
+      ok = true;
+      for (int j = 0; j < nb; ++j)
+        if (ok && !sat_clear(load_box(s, j), P, p.edge_eps)) ok = false;
+    }
+    const unsigned long long m = __ballot(ok);
+    // words 2 * (a0 / 64) and 2 * (a0 / 64) + 1
+    const int w = a0 >> 5;
+    if (lane == w) word = (unsigned)m;
+    if (lane == w + 1) word = (unsigned)(m >> 32);
   }
-  return best;
+  return word;
 }
 
 // An opaque copy of a value: address arithmetic built from it stays where it
@@ -554,7 +632,8 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   const bool rollout = g.actions != nullptr;
   const int act0 = rollout ? g.act_offset[e] : 0;
   int n_push = rollout ? g.act_offset[e + 1] - act0 : 1;
-  const int src = (rollout && g.src_slot) ? g.src_slot[e] : -1;
+  const int src = ((rollout || g.valid_only) && g.src_slot) ? g.src_slot[e] : -1;
+  if (g.valid_only && g.src_slot && src < 0) return;
   const int PS = g.pool_stride;
 
   // ---- load (coalesced SoA): part 0 linear, part 1 angular; from the env
@@ -609,6 +688,15 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     }
   };
 
+  // validity words of the loaded state only
+  if (g.valid_only) {
+    write_body_frames();
+    wave_sync();
+    const unsigned wd = validity_word(s, nb, p, lane);
+    if (lane < PMBS_VALID_WORDS) g.valid_out[(size_t)e * PMBS_VALID_WORDS + lane] = wd;
+    return;
+  }
+
   Contact ct[K];
   bool deferred = false;
   uint32_t status = 0u;
@@ -640,25 +728,12 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     } else {
       const int4 xd = g.x_desc[e];
       act = t == 0 ? xd.y
-                   : philox_action(g.x_key[e], (unsigned)xd.z, (unsigned)xd.y, ((unsigned)xd.w << 8) | (unsigned)t,
-                                   (unsigned)(nb * p.n_dirs));
+                   : philox_action(g.x_key[e], (unsigned)xd.z, (unsigned)xd.y,
+                                   (((unsigned)xd.w & 0xffffffu) << 8) | (unsigned)t, (unsigned)(nb * p.n_dirs));
     }
     const int obj = act / p.n_dirs, dir = act - obj * p.n_dirs;
     have_push = obj >= 0 && obj < nb;
-    if (have_push) {
-      const f3 oc = xyz(s.pos[obj]), oa0 = xyz(s.col[0][obj]), oh = xyz(s.half[obj]);
-      const float th = 6.283185307179586f * (float)dir / (float)p.n_dirs;
-      const float cth = cosf(th), sth = sinf(th);
-      const float rx = fabsf(cth) > 0.0f ? oh.x / fabsf(cth) : INFINITY;
-      const float ry = fabsf(sth) > 0.0f ? oh.y / fabsf(sth) : INFINITY;
-      const float ray = fminf(rx, ry);
-      const float yaw = atan2f(oa0.y, oa0.x);
-      const float cy = cosf(yaw), sy = sinf(yaw);
-      const float ddx = cy * cth - sy * sth, ddy = sy * cth + cy * sth;
-      const float off = ray + p.phx + p.push_standoff;
-      const float sxp = oc.x + off * ddx, syp = oc.y + off * ddy;
-      push = make_float4(sxp, syp, sxp - p.push_length * ddx, syp - p.push_length * ddy);
-    }
+    if (have_push) push = contour_start(s, obj, dir, p);
   } else {
     have_push = g.push != nullptr;
     if (have_push) push = g.push[e];
@@ -668,16 +743,12 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   f3 xp = mk(0, 0, 10.0f);
   f3 pc0 = mk(1, 0, 0), pc1 = mk(0, 1, 0);
   if (have_push) {
-    float dx = push.z - push.x, dy = push.w - push.y;
-    float len = sqrtf(dx * dx + dy * dy);
-    if (len > 0.0f) pdir = mk(dx / len, dy / len, 0.0f);
-    n_move = (int)roundf(len / (p.push_speed * dt));
-    xp = mk(push.x, push.y, p.pusher_z);
-    float yaw = atan2f(pdir.y, pdir.x);
-    float cy = cosf(0.5f * yaw), sy = sinf(0.5f * yaw);
-    // rotation about z from the half-angle quaternion (cy, 0, 0, sy)
-    pc0 = mk(1.0f - 2.0f * sy * sy, 2.0f * cy * sy, 0.0f);
-    pc1 = mk(-2.0f * cy * sy, 1.0f - 2.0f * sy * sy, 0.0f);
+    const PusherPose pq = pusher_pose(push, p);
+    pdir = pq.dir;
+    n_move = pq.n_move;
+    xp = pq.x;
+    pc0 = pq.c0;
+    pc1 = pq.c1;
   }
 
   // the pusher entry (index nb)
@@ -703,14 +774,15 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   // validity of the start pose: SAT separation from every box must be > 0
   bool valid = false;
   if (have_push) {
-    write_pusher(mk(0, 0, 0));
-    wave_sync();
     bool bad = false;
     if (active && part == 0) {
-      bad = !(sat_max(s, b, nb, p.edge_eps) > 0.0f);
+      PusherPose pq;
+      pq.x = xp;
+      pq.c0 = pc0;
+      pq.c1 = pc1;
+      bad = !sat_clear(load_box(s, b), pusher_box(pq, p), p.edge_eps);
     }
     valid = __ballot(bad) == 0;
-    wave_sync();
   }
   if (!valid) {
     xp = mk(0, 0, 10.0f);
@@ -1297,6 +1369,11 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     if (lane == 0) (job ? g.x_rewards : g.rewards)[(size_t)e * g.max_h + t] = r;
     // the expanded child's state goes to its pool slot
     const int cs = (t == 0 && job == 0 && g.child_slot) ? g.child_slot[e] : -1;
+    // the child's sampled pushes that can start (its frames are in LDS)
+    if (cs >= 0 && g.valid_out) {
+      const unsigned wd = validity_word(s, nb, p, lane);
+      if (lane < PMBS_VALID_WORDS) g.valid_out[(size_t)e * PMBS_VALID_WORDS + lane] = wd;
+    }
     if (cs >= 0 && active) {
       float* dst = g.pool + (size_t)cs * 13 * PS + opaque(b);
       if (part == 0) {
@@ -1317,7 +1394,8 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   if (deferred) break;
   // re-purposing: the extra simulation starts from its node's pool slot
   if (job == 1 || !g.x_desc || t_stop < 0 || t_stop + 1 >= n_push) break;
-  n_push = n_push - t_stop - 1;
+  // the pushes left, at most the extra pair's own horizon (top byte of w)
+  n_push = min(n_push - t_stop - 1, (int)((unsigned)g.x_desc[e].w >> 24));
   last_r = 0.0f;
   if (active) {
     const float* st = g.pool + (size_t)g.x_desc[e].x * 13 * PS + opaque(b);

@@ -71,10 +71,21 @@ pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_stat
   std::vector<int32_t> slots(E, -1);
   slots[0] = 0;
   if ((s = pmbs_pool_scatter(sim, slots.data(), 0)) != PMBS_OK) return s;
+  // the root's sampled pushes that cannot start are discarded before any
+  // selection (Sec. IV-B), from the validity words of the device
+  std::vector<uint32_t> valid((size_t)E * PMBS_VALID_WORDS);
+  if (tc.discard) {
+    int32_t nn = 0;
+    if ((s = pmbs_tree_size(tree, &nn, nullptr, nullptr)) != PMBS_OK) return s;
+    if (nn != 1) return fail(PMBS_ERR_INVALID_ARG, "pmbs_plan with discard needs a fresh tree");
+    if ((s = pmbs_sim_valid_pushes(sim, slots.data(), 0)) != PMBS_OK) return s;
+    if ((s = pmbs_sim_push_valid(sim, valid.data(), 0)) != PMBS_OK) return s;
+    if ((s = pmbs_tree_set_valid(tree, 0, valid.data())) != PMBS_OK) return s;
+  }
 
   std::vector<int32_t> actions((size_t)E * D), act_off(E + 1), src(E), child(E), tgt(E, target), counts(E);
   std::vector<float> rewards((size_t)E * D), x_rewards((size_t)E * D);
-  std::vector<int32_t> x_src(E), x_act(E), x_node(E), x_rep(E), x_counts(E);
+  std::vector<int32_t> x_src(E), x_act(E), x_node(E), x_rep(E), x_hor(E), x_counts(E);
   std::vector<uint64_t> x_seed(E, tc.seed);
   std::vector<uint32_t> status(E);
   std::vector<int64_t> stats((size_t)E * 3);
@@ -91,17 +102,21 @@ pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_stat
     if (n_pairs == 0) break;
     pmbs_repurpose rp{};
     if (tc.repurpose) {
-      if ((s = pmbs_tree_extra(tree, x_src.data(), x_act.data(), x_node.data(), x_rep.data())) != PMBS_OK) return s;
+      if ((s = pmbs_tree_extra(tree, x_src.data(), x_act.data(), x_node.data(), x_rep.data(), x_hor.data())) !=
+          PMBS_OK)
+        return s;
       rp.src_slot = x_src.data();
       rp.action = x_act.data();
       rp.node_id = x_node.data();
       rp.replica = x_rep.data();
+      rp.horizon = x_hor.data();
       rp.seed = x_seed.data();
       rp.d_rewards = sim->d_x_rewards;
       rp.d_counts = sim->d_x_counts;
     }
     if ((s = pmbs_sim_rollout_ex(sim, actions.data(), act_off.data(), src.data(), child.data(), tgt.data(), 0,
-                                 n_substeps, width, sim->d_roll_rewards, D, sim->d_roll_counts, PMBS_ROLLOUT_QUEUE,
+                                 n_substeps, width, sim->d_roll_rewards, D, sim->d_roll_counts,
+                                 PMBS_ROLLOUT_QUEUE | (tc.discard ? PMBS_ROLLOUT_CHILD_VALID : 0),
                                  tc.repurpose ? &rp : nullptr)) != PMBS_OK)
       return s;
     hipError_t e = hipMemcpyAsync(rewards.data(), sim->d_roll_rewards, rewards.size() * sizeof(float),
@@ -120,12 +135,15 @@ pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_stat
     if (e == hipSuccess && tc.repurpose)
       e = hipMemcpyAsync(x_counts.data(), sim->d_x_counts, x_counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
                          sim->stream);
+    if (e == hipSuccess && tc.discard)
+      e = hipMemcpyAsync(valid.data(), sim->d_valid, valid.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                         sim->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
     if (e != hipSuccess) return hip_fail(e, "plan readback");
     for (int k = 0; k < E; ++k) env_substeps += stats[(size_t)3 * k + 2];
     if ((s = pmbs_tree_update_ex(tree, rewards.data(), D, counts.data(), status.data(),
                                  tc.repurpose ? x_rewards.data() : nullptr, tc.repurpose ? x_counts.data() : nullptr,
-                                 nullptr)) != PMBS_OK)
+                                 tc.discard ? valid.data() : nullptr, nullptr)) != PMBS_OK)
       return s;
   }
   int32_t a = -1;

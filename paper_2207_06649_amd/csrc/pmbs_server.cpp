@@ -130,10 +130,10 @@ struct pmbs_server {
   std::thread worker;
   // packed launch buffers (worker only)
   std::vector<int32_t> actions, act_off, src, child, target, env_off, bc_base, counts, t_actions, t_off, t_src,
-      t_child, x_src, x_act, x_node, x_rep, x_counts, tx_src, tx_act, tx_node, tx_rep;
+      t_child, x_src, x_act, x_node, x_rep, x_counts, tx_src, tx_act, tx_node, tx_rep, x_hor, tx_hor;
   std::vector<uint64_t> x_seed;
   std::vector<float> rewards, x_rewards;
-  std::vector<uint32_t> status;
+  std::vector<uint32_t> status, valid;
   std::vector<int64_t> stats;
 
   int64_t footprint_of(int32_t max_nodes) const { return (int64_t)max_nodes * 13 * kStride * (int64_t)sizeof(float); }
@@ -241,6 +241,13 @@ pmbs_status pmbs_server::start_requests(const std::vector<Request*>& fresh) {
   if (s != PMBS_OK) return s;
   std::vector<float> root_r(fresh.size());
   if ((s = rewards_from_pool(sim, slots.data(), tg.data(), cfg.width, root_r.data())) != PMBS_OK) return s;
+  // the roots' sampled pushes that can start (Sec. IV-B)
+  std::vector<uint32_t> root_valid;
+  if (cfg.discard) {
+    root_valid.resize(fresh.size() * PMBS_VALID_WORDS);
+    if ((s = pmbs_sim_valid_pushes(sim, slots.data(), 0)) != PMBS_OK) return s;
+    if ((s = pmbs_sim_push_valid(sim, root_valid.data(), 0)) != PMBS_OK) return s;
+  }
   for (size_t i = 0; i < fresh.size(); ++i) {
     Request* r = fresh[i];
     pmbs_tree_config tc;
@@ -254,7 +261,10 @@ pmbs_status pmbs_server::start_requests(const std::vector<Request*>& fresh) {
     tc.seed = r->seed;
     tc.early_stop = cfg.early_stop;
     tc.repurpose = cfg.repurpose;
+    tc.discard = cfg.discard;
     if ((s = pmbs_tree_create(&tc, r->nb, root_r[i], &r->tree)) != PMBS_OK) return s;
+    if (cfg.discard && (s = pmbs_tree_set_valid(r->tree, 0, root_valid.data() + i * PMBS_VALID_WORDS)) != PMBS_OK)
+      return s;
   }
   return PMBS_OK;
 }
@@ -273,6 +283,7 @@ pmbs_status pmbs_server::pass() {
   x_act.clear();
   x_node.clear();
   x_rep.clear();
+  x_hor.clear();
   x_seed.clear();
   std::vector<Request*> done_now, in_launch;
   for (Request* r : active) {
@@ -307,13 +318,16 @@ pmbs_status pmbs_server::pass() {
       tx_act.resize(n_envs);
       tx_node.resize(n_envs);
       tx_rep.resize(n_envs);
-      if ((s = pmbs_tree_extra(r->tree, tx_src.data(), tx_act.data(), tx_node.data(), tx_rep.data())) != PMBS_OK)
+      tx_hor.resize(n_envs);
+      if ((s = pmbs_tree_extra(r->tree, tx_src.data(), tx_act.data(), tx_node.data(), tx_rep.data(),
+                               tx_hor.data())) != PMBS_OK)
         return s;
       for (int e = 0; e < n_envs; ++e) {
         x_src.push_back(r->slot_base + tx_src[e]);
         x_act.push_back(tx_act[e]);
         x_node.push_back(tx_node[e]);
         x_rep.push_back(tx_rep[e]);
+        x_hor.push_back(tx_hor[e]);
         x_seed.push_back(r->seed);
       }
     }
@@ -333,13 +347,14 @@ pmbs_status pmbs_server::pass() {
   if (E == 0) return PMBS_OK;
   pmbs_status s = set_layout(sim, E, env_off.data(), bc_base.data());
   if (s != PMBS_OK) return s;
-  int32_t flags = PMBS_ROLLOUT_QUEUE | (cfg.graph ? PMBS_ROLLOUT_GRAPH : 0);
+  int32_t flags = PMBS_ROLLOUT_QUEUE | (cfg.graph ? PMBS_ROLLOUT_GRAPH : 0) | (cfg.discard ? PMBS_ROLLOUT_CHILD_VALID : 0);
   pmbs_repurpose rp{};
   if (cfg.repurpose) {
     rp.src_slot = x_src.data();
     rp.action = x_act.data();
     rp.node_id = x_node.data();
     rp.replica = x_rep.data();
+    rp.horizon = x_hor.data();
     rp.seed = x_seed.data();
     rp.d_rewards = sim->d_x_rewards;
     rp.d_counts = sim->d_x_counts;
@@ -371,6 +386,12 @@ pmbs_status pmbs_server::pass() {
       e = hipMemcpyAsync(x_counts.data(), sim->d_x_counts, (size_t)E * sizeof(int32_t), hipMemcpyDeviceToHost,
                          sim->stream);
   }
+  if (cfg.discard) {
+    valid.resize((size_t)E * PMBS_VALID_WORDS);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(valid.data(), sim->d_valid, valid.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                         sim->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
   if (e != hipSuccess) return hip_fail(e, "server read-back");
   int64_t total = 0;
@@ -378,7 +399,8 @@ pmbs_status pmbs_server::pass() {
     const int b0 = r->env_begin;
     s = pmbs_tree_update_ex(r->tree, rewards.data() + (size_t)b0 * D, D, counts.data() + b0, status.data() + b0,
                             cfg.repurpose ? x_rewards.data() + (size_t)b0 * D : nullptr,
-                            cfg.repurpose ? x_counts.data() + b0 : nullptr, nullptr);
+                            cfg.repurpose ? x_counts.data() + b0 : nullptr,
+                            cfg.discard ? valid.data() + (size_t)b0 * PMBS_VALID_WORDS : nullptr, nullptr);
     if (s != PMBS_OK) return s;
     int64_t sub = 0;
     for (int k = b0; k < b0 + r->n_envs; ++k) sub += stats[(size_t)3 * k + 2];
@@ -442,6 +464,7 @@ void pmbs_server_config_default(pmbs_server_config* c) {
   c->sim.max_contacts = 256;
   c->max_envs = 4096;
   c->max_requests = 16;
+  c->discard = 1;
   c->pool_slots = 262144;
   c->max_depth = 5;
   c->n_substeps = 120;

@@ -41,7 +41,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
   size_t state, bconst, env_offset, push, status, target, reward, clearance, slots, stats, pool;
   size_t actions, act_offset, src_slot, child_slot, order, roll_rewards, roll_counts;
-  size_t ctl, ovf4, ovf8, bc_base, x_desc, x_key, x_rewards, x_counts, total;
+  size_t ctl, ovf4, ovf8, bc_base, x_desc, x_key, x_rewards, x_counts, valid, total;
 };
 
 static Layout layout_of(const pmbs_sim_config& c) {
@@ -79,6 +79,7 @@ static Layout layout_of(const pmbs_sim_config& c) {
   L.x_key = take(ne * 2 * sizeof(uint32_t));
   L.x_rewards = take(ne * (size_t)c.max_horizon * sizeof(float));
   L.x_counts = take(ne * sizeof(int32_t));
+  L.valid = take(ne * PMBS_VALID_WORDS * sizeof(uint32_t));
   L.total = o;
   return L;
 }
@@ -503,6 +504,7 @@ pmbs_status pmbs_sim_create(const pmbs_sim_config* cfg, void* d_workspace, size_
   s->d_x_key = reinterpret_cast<uint32_t*>(base + L.x_key);
   s->d_x_rewards = reinterpret_cast<float*>(base + L.x_rewards);
   s->d_x_counts = reinterpret_cast<int32_t*>(base + L.x_counts);
+  s->d_valid = reinterpret_cast<uint32_t*>(base + L.valid);
   s->plan.small_max_bodies = 16;
   s->plan.small_blocks_per_cu = 0;
   s->plan.large_blocks_per_cu = 0;
@@ -665,6 +667,8 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
         return fail(PMBS_ERR_CAPACITY, "env %d: extra source slot %d", e, rp->src_slot[e]);
       if (rp->action[e] < 0 || rp->action[e] >= nb * 8 || rp->replica[e] < 0 || rp->replica[e] >= (1 << 24))
         return fail(PMBS_ERR_INVALID_ARG, "env %d: extra action or replica out of range", e);
+      if (rp->horizon && (rp->horizon[e] < 0 || rp->horizon[e] > 255))
+        return fail(PMBS_ERR_INVALID_ARG, "env %d: extra horizon out of range", e);
     }
   }
   int total = 0;
@@ -720,7 +724,7 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
       xdesc[4 * e + 0] = rp->src_slot[e];
       xdesc[4 * e + 1] = rp->action[e];
       xdesc[4 * e + 2] = rp->node_id[e];
-      xdesc[4 * e + 3] = rp->replica[e];
+      xdesc[4 * e + 3] = (int32_t)((uint32_t)rp->replica[e] | ((uint32_t)(rp->horizon ? rp->horizon[e] : 255) << 24));
       xkey[2 * e + 0] = (uint32_t)rp->seed[e];
       xkey[2 * e + 1] = (uint32_t)(rp->seed[e] >> 32);
     }
@@ -750,6 +754,7 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
   a.width = width;
   a.write_state = (flags & PMBS_ROLLOUT_WRITE_STATE) ? 1 : 0;
   a.n_substeps = n_substeps;
+  if (flags & PMBS_ROLLOUT_CHILD_VALID) a.valid_out = sim->d_valid;
   if (!use_queue) {
     hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream);
     if (e != hipSuccess) return hip_fail(e, "rollout launch");
@@ -791,6 +796,52 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
   }
   e = hipGraphLaunch(sim->graph_exec, sim->stream);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_valid_pushes(pmbs_sim_t* sim, const int32_t* src_slot, int32_t inputs_on_device) {
+  if (!sim) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  const int n = sim->n_envs;
+  if (src_slot && !sim->d_pool) return fail(PMBS_ERR_CAPACITY, "pool slots need a pool");
+  if (sim->pool_layout && !src_slot) return fail(PMBS_ERR_INVALID_ARG, "a pool-only layout needs source slots");
+  if (src_slot && !inputs_on_device)
+    for (int e = 0; e < n; ++e) {
+      if (src_slot[e] >= sim->cfg.pool_slots) return fail(PMBS_ERR_CAPACITY, "env %d: source slot", e);
+      if (src_slot[e] >= 0 && sim->host_offset[e + 1] - sim->host_offset[e] > sim->cfg.pool_stride)
+        return fail(PMBS_ERR_CAPACITY, "env %d: bodies > pool_stride", e);
+    }
+  if (n == 0) return PMBS_OK;
+  const int32_t* d_src;
+  pmbs_status st = stage_ints(sim, src_slot, (size_t)n, inputs_on_device, sim->d_src_slot, &d_src);
+  if (st != PMBS_OK) return st;
+  if (src_slot && !inputs_on_device) {
+    hipError_t e = hipStreamSynchronize(sim->stream);
+    if (e != hipSuccess) return hip_fail(e, "validity upload");
+  }
+  StepArgs a = step_args(sim);
+  a.valid_only = 1;
+  a.valid_out = sim->d_valid;
+  a.src_slot = d_src;
+  a.pool = sim->d_pool;
+  a.pool_stride = sim->cfg.pool_stride;
+  if (sim->pool_layout) {
+    a.bc_base = sim->d_bc_base;
+    a.bc_stride = sim->cfg.max_bodies;
+  }
+  a.stats = nullptr;
+  hipError_t e = launch_step(a, 128, sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "validity launch");
+  return PMBS_OK;
+}
+
+pmbs_status pmbs_sim_push_valid(pmbs_sim_t* sim, uint32_t* out, int32_t dst_is_device) {
+  if (!sim || !out) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  const size_t bytes = (size_t)sim->n_envs * PMBS_VALID_WORDS * sizeof(uint32_t);
+  if (!bytes) return PMBS_OK;
+  hipError_t e = hipMemcpyAsync(out, sim->d_valid, bytes, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                sim->stream);
+  if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "validity read-back");
   return PMBS_OK;
 }
 

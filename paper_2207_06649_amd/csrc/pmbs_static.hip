@@ -77,7 +77,8 @@ pmbs_status pmbs_sim_rollout_static(pmbs_sim_t* sim, const int32_t* actions, con
                                     int32_t* d_reward_count, int32_t flags) {
   if (!sim || !actions || !act_offset || !target || !d_rewards) return fail(PMBS_ERR_INVALID_ARG, "null argument");
   if (n_substeps < 0 || !(width > 0)) return fail(PMBS_ERR_INVALID_ARG, "n_substeps must be >= 0 and width > 0");
-  if (flags & ~PMBS_ROLLOUT_WRITE_STATE) return fail(PMBS_ERR_INVALID_ARG, "only PMBS_ROLLOUT_WRITE_STATE applies");
+  if (flags & ~(PMBS_ROLLOUT_WRITE_STATE | PMBS_ROLLOUT_CHILD_VALID))
+    return fail(PMBS_ERR_INVALID_ARG, "only PMBS_ROLLOUT_WRITE_STATE and PMBS_ROLLOUT_CHILD_VALID apply");
   const int n = sim->n_envs;
   if ((src_slot || child_slot) && !sim->d_pool) return fail(PMBS_ERR_CAPACITY, "rollout from/to pool slots needs a pool");
   if (sim->pool_layout && (!src_slot || (flags & PMBS_ROLLOUT_WRITE_STATE)))
@@ -140,6 +141,7 @@ pmbs_status pmbs_sim_rollout_static(pmbs_sim_t* sim, const int32_t* actions, con
   a.width = width;
   a.write_state = (flags & PMBS_ROLLOUT_WRITE_STATE) ? 1 : 0;
   a.n_substeps = n_substeps;
+  if (flags & PMBS_ROLLOUT_CHILD_VALID) a.valid_out = sim->d_valid;
   a.n_envs = 0;  // the queued kernels take their counts from the device
 
   // the contact classes one after another on the caller's stream (no side

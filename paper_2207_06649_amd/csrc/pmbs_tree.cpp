@@ -108,6 +108,17 @@ static double ucb(const Node& ch, const Node& par, double c) {
   return ch.Q / n + c * std::sqrt(2.0 * std::log((double)(par.N + par.Nhat)) / n);
 }
 
+// Sec. IV-B: the node's sampled actions whose start pose collides are
+// discarded; the untried list keeps the valid ones in their shuffled order.
+static void keep_valid(Node* n, const uint32_t* words) {
+  size_t k = 0;
+  for (size_t i = 0; i < n->untried.size(); ++i) {
+    const int32_t a = n->untried[i];
+    if ((words[a >> 5] >> (a & 31)) & 1u) n->untried[k++] = a;
+  }
+  n->untried.resize(k);
+}
+
 }  // namespace pmbs
 
 using namespace pmbs;
@@ -124,6 +135,7 @@ void pmbs_tree_config_default(pmbs_tree_config* c) {
   c->max_nodes = 65536;
   c->n_dirs = 8;
   c->seed = 0;
+  c->discard = 1;
 }
 
 pmbs_status pmbs_tree_create(const pmbs_tree_config* cfg, int32_t n_objects, float root_reward, pmbs_tree_t** out) {
@@ -223,8 +235,20 @@ pmbs_status pmbs_tree_select(pmbs_tree_t* t, int32_t* n_pairs, int32_t* actions,
   return PMBS_OK;
 }
 
+pmbs_status pmbs_tree_set_valid(pmbs_tree_t* t, int32_t id, const uint32_t* words) {
+  if (!t || !words) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (id < 0 || id >= (int32_t)t->nodes.size()) return fail(PMBS_ERR_INVALID_ARG, "node %d out of range", id);
+  if (t->n_actions > 32 * PMBS_VALID_WORDS) return fail(PMBS_ERR_CAPACITY, "more actions than validity bits");
+  Node& n = t->nodes[id];
+  if (n.next_untried != 0 || !n.children.empty())
+    return fail(PMBS_ERR_INVALID_ARG, "node %d has already been selected from", id);
+  keep_valid(&n, words);
+  refresh_sel(t, id);
+  return PMBS_OK;
+}
+
 pmbs_status pmbs_tree_extra(const pmbs_tree_t* t, int32_t* src_slot, int32_t* action, int32_t* node_id,
-                            int32_t* replica) {
+                            int32_t* replica, int32_t* horizon) {
   if (!t || !src_slot || !action || !node_id || !replica) return fail(PMBS_ERR_INVALID_ARG, "null argument");
   if (!t->pending) return fail(PMBS_ERR_INVALID_ARG, "no selection pending");
   const int P = (int)t->pair_node.size(), E = (int)t->env_pair.size();
@@ -236,19 +260,23 @@ pmbs_status pmbs_tree_extra(const pmbs_tree_t* t, int32_t* src_slot, int32_t* ac
     action[e] = t->pair_action[q];
     node_id[e] = n.id;
     replica[e] = R + e;
+    // the extra simulation ends at the depth limit of its own pair (Sec. IV-A)
+    if (horizon) horizon[e] = t->d_tree + t->d_sim - n.depth;
   }
   return PMBS_OK;
 }
 
 pmbs_status pmbs_tree_update(pmbs_tree_t* t, const float* rewards, int32_t max_h, const int32_t* counts,
                              const uint32_t* env_status, int32_t* n_children) {
-  return pmbs_tree_update_ex(t, rewards, max_h, counts, env_status, nullptr, nullptr, n_children);
+  return pmbs_tree_update_ex(t, rewards, max_h, counts, env_status, nullptr, nullptr, nullptr, n_children);
 }
 
 pmbs_status pmbs_tree_update_ex(pmbs_tree_t* t, const float* rewards, int32_t max_h, const int32_t* counts,
                                 const uint32_t* env_status, const float* extra_rewards, const int32_t* extra_counts,
-                                int32_t* n_children) {
+                                const uint32_t* child_valid, int32_t* n_children) {
   if (!t || !rewards || !counts || !env_status) return fail(PMBS_ERR_INVALID_ARG, "null argument");
+  if (child_valid && t->n_actions > 32 * PMBS_VALID_WORDS)
+    return fail(PMBS_ERR_CAPACITY, "more actions than validity bits");
   if ((extra_rewards == nullptr) != (extra_counts == nullptr))
     return fail(PMBS_ERR_INVALID_ARG, "extra rewards and counts go together");
   if (!t->pending) return fail(PMBS_ERR_INVALID_ARG, "no selection pending");
@@ -283,6 +311,11 @@ pmbs_status pmbs_tree_update_ex(pmbs_tree_t* t, const float* rewards, int32_t ma
     const int32_t par = t->pair_node[p];
     const int32_t child = add_node(t, par, t->pair_action[p], t->nodes[par].depth + 1, t->pair_slot[p],
                                    rewards[(size_t)e * max_h]);
+    if (child_valid) {
+      Node& c = t->nodes[child];
+      keep_valid(&c, child_valid + (size_t)e * PMBS_VALID_WORDS);
+      c.sel = !c.terminal && c.expandable(t->d_tree);
+    }
     t->nodes[par].children.push_back(child);
     refresh_sel(t, child);
     if (t->cfg.early_stop && t->nodes[child].terminal) {

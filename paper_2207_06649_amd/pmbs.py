@@ -24,6 +24,8 @@ PMBS_ERR_HOST_MEMORY = -7
 ROLLOUT_WRITE_STATE = 1
 ROLLOUT_QUEUE = 2
 ROLLOUT_GRAPH = 4
+ROLLOUT_CHILD_VALID = 8
+VALID_WORDS = 8
 MAX_BODIES_PER_ENV = 31
 
 
@@ -37,7 +39,7 @@ class LaunchPlan(C.Structure):
 
 class Repurpose(C.Structure):
     _fields_ = [("src_slot", C.c_void_p), ("action", C.c_void_p), ("node_id", C.c_void_p), ("replica", C.c_void_p),
-                ("seed", C.c_void_p), ("d_rewards", C.c_void_p), ("d_counts", C.c_void_p)]
+                ("horizon", C.c_void_p), ("seed", C.c_void_p), ("d_rewards", C.c_void_p), ("d_counts", C.c_void_p)]
 
 
 class SimConfig(C.Structure):
@@ -97,6 +99,8 @@ def lib():
                                        vp, C.c_int32]
         L.pmbs_sim_rollout_static.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, C.c_float, vp, C.c_int32, vp,
                                               C.c_int32]
+        L.pmbs_sim_valid_pushes.argtypes = [vp, vp, C.c_int32]
+        L.pmbs_sim_push_valid.argtypes = [vp, vp, C.c_int32]
         L.pmbs_sim_shape.argtypes = [vp, ip, ip]
         _lib = L
     return _lib
@@ -300,16 +304,33 @@ class Sim:
             return rew.cpu().numpy(), cnt.cpu().numpy()
         # re-purposing: descriptors (host, per env) and the extra outputs
         xs = {k: np.ascontiguousarray(repurpose[k], np.int32) for k in ("src_slot", "action", "node_id", "replica")}
+        hor = repurpose.get("horizon")
+        hor = None if hor is None else np.ascontiguousarray(hor, np.int32)
         seed = np.ascontiguousarray(np.broadcast_to(np.asarray(repurpose["seed"], np.uint64), (self.n_envs,)))
         xrew = t.full((self.n_envs, mh), -1.0, dtype=t.float32, device=self.device)
         xcnt = t.zeros(self.n_envs, dtype=t.int32, device=self.device)
-        rp = Repurpose(ptr(xs["src_slot"]), ptr(xs["action"]), ptr(xs["node_id"]), ptr(xs["replica"]), ptr(seed),
-                       _ptr(xrew), _ptr(xcnt))
+        rp = Repurpose(ptr(xs["src_slot"]), ptr(xs["action"]), ptr(xs["node_id"]), ptr(xs["replica"]), ptr(hor),
+                       ptr(seed), _ptr(xrew), _ptr(xcnt))
         _check(lib().pmbs_sim_rollout_ex(self.handle, ptr(acts), ptr(off), ptr(ss), ptr(cs), ptr(tg), 0,
                                          int(n_substeps), float(width), _ptr(rew), mh, _ptr(cnt), int(flags),
                                          C.byref(rp)))
         self.sync()
         return rew.cpu().numpy(), cnt.cpu().numpy(), xrew.cpu().numpy(), xcnt.cpu().numpy()
+
+    def valid_pushes(self, src_slot=None) -> np.ndarray:
+        """Start-pose validity words [n_envs, VALID_WORDS] of every env's
+        state (pool slot src_slot[e] when given; < 0 skips the env)."""
+        ptr = None
+        if src_slot is not None:
+            ss = np.ascontiguousarray(src_slot, np.int32)
+            ptr = ss.ctypes.data_as(C.c_void_p)
+        _check(lib().pmbs_sim_valid_pushes(self.handle, ptr, 0))
+        return self.push_valid()
+
+    def push_valid(self) -> np.ndarray:
+        out = np.zeros((self.n_envs, VALID_WORDS), np.uint32)
+        _check(lib().pmbs_sim_push_valid(self.handle, out.ctypes.data_as(C.c_void_p), 0))
+        return out
 
     def rollout_static(self, actions, act_offset, target, n_substeps=120, width=0.08, src_slot=None,
                        child_slot=None, max_h=None, flags=ROLLOUT_WRITE_STATE, rewards=None, counts=None):
@@ -359,7 +380,7 @@ class Sim:
 class TreeConfig(C.Structure):
     _fields_ = [("c", C.c_double), ("gamma", C.c_double), ("max_depth", C.c_int32), ("n_envs", C.c_int32),
                 ("max_nodes", C.c_int32), ("n_dirs", C.c_int32), ("seed", C.c_uint64), ("sim_depth", C.c_int32),
-                ("early_stop", C.c_int32), ("repurpose", C.c_int32)]
+                ("early_stop", C.c_int32), ("repurpose", C.c_int32), ("discard", C.c_int32)]
 
 
 class NodeInfo(C.Structure):
@@ -389,8 +410,9 @@ def _tree_lib():
         L.pmbs_tree_node.argtypes = [vp, C.c_int32, C.POINTER(NodeInfo)]
         L.pmbs_tree_size.argtypes = [vp, vp, vp, vp]
         L.pmbs_tree_status.argtypes = [vp, vp, vp, vp, vp]
-        L.pmbs_tree_extra.argtypes = [vp, vp, vp, vp, vp]
-        L.pmbs_tree_update_ex.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, vp]
+        L.pmbs_tree_extra.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.pmbs_tree_update_ex.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp]
+        L.pmbs_tree_set_valid.argtypes = [vp, C.c_int32, vp]
         L.pmbs_plan.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_float,
                                 C.POINTER(PlanResult)]
         L._tree_ready = True
@@ -441,23 +463,32 @@ class Tree:
                     actions=self._acts[:self._off[E]].copy() if E else np.zeros(0, np.int32),
                     src_slot=self._src[:E].copy(), child_slot=self._child[:E].copy())
 
-    def update(self, rewards, counts, status, extra_rewards=None, extra_counts=None):
+    def update(self, rewards, counts, status, extra_rewards=None, extra_counts=None, child_valid=None):
+        """child_valid: uint32 [n_envs, VALID_WORDS] validity words of each
+        env's child state (the new nodes discard their colliding pushes)."""
         rw = np.ascontiguousarray(rewards, np.float32)
         ct = np.ascontiguousarray(counts, np.int32)
         stt = np.ascontiguousarray(status, np.uint32)
         xr = None if extra_rewards is None else np.ascontiguousarray(extra_rewards, np.float32)
         xc = None if extra_counts is None else np.ascontiguousarray(extra_counts, np.int32)
+        cv = None if child_valid is None else np.ascontiguousarray(child_valid, np.uint32).reshape(-1, VALID_WORDS)
         made = C.c_int32(0)
         _check(_tree_lib().pmbs_tree_update_ex(self.handle, _np_ptr(rw), rw.shape[1], _np_ptr(ct), _np_ptr(stt),
                                                None if xr is None else _np_ptr(xr),
-                                               None if xc is None else _np_ptr(xc), C.byref(made)))
+                                               None if xc is None else _np_ptr(xc),
+                                               None if cv is None else _np_ptr(cv), C.byref(made)))
         return made.value
+
+    def set_valid(self, node: int, words):
+        """Discards the node's sampled actions whose bit is clear."""
+        w = np.ascontiguousarray(words, np.uint32).reshape(VALID_WORDS)
+        _check(_tree_lib().pmbs_tree_set_valid(self.handle, int(node), _np_ptr(w)))
 
     def extra(self, n_envs: int) -> dict:
         """Re-purposing descriptors of the last selection (per env)."""
-        out = {k: np.zeros(n_envs, np.int32) for k in ("src_slot", "action", "node_id", "replica")}
-        _check(_tree_lib().pmbs_tree_extra(self.handle, *(_np_ptr(out[k]) for k in ("src_slot", "action", "node_id",
-                                                                                     "replica"))))
+        keys = ("src_slot", "action", "node_id", "replica", "horizon")
+        out = {k: np.zeros(n_envs, np.int32) for k in keys}
+        _check(_tree_lib().pmbs_tree_extra(self.handle, *(_np_ptr(out[k]) for k in keys)))
         return out
 
     def best(self):
@@ -530,7 +561,8 @@ class ServerConfig(C.Structure):
     _fields_ = [("sim", SimConfig), ("max_envs", C.c_int32), ("max_requests", C.c_int32),
                 ("pool_slots", C.c_int32), ("max_depth", C.c_int32), ("n_substeps", C.c_int32),
                 ("width", C.c_float), ("c", C.c_double), ("gamma", C.c_double), ("hbm_budget", C.c_int64),
-                ("graph", C.c_int32), ("early_stop", C.c_int32), ("repurpose", C.c_int32)]
+                ("graph", C.c_int32), ("early_stop", C.c_int32), ("repurpose", C.c_int32),
+                ("discard", C.c_int32)]
 
 
 class Request(C.Structure):

@@ -45,9 +45,13 @@ def near_clear_scene():
     return st, bd
 
 
-@pytest.mark.parametrize("seed,n_envs,depth,iters,early,rep", [
-    (3, 12, 2, 2, 0, 0), (5, 24, 3, 3, 0, 0), (1, 24, 3, 6, 1, 0), (1, 24, 3, 3, 0, 1)])
-def test_plan_matches_oracle_planner(pm, seed, n_envs, depth, iters, early, rep):
+@pytest.mark.parametrize("seed,n_envs,depth,iters,early,rep,disc", [
+    (3, 12, 2, 2, 0, 0, 1), (5, 24, 3, 3, 0, 0, 1), (1, 24, 3, 6, 1, 0, 1), (1, 24, 3, 3, 0, 1, 1),
+    (5, 24, 3, 3, 0, 0, 0)])
+def test_plan_matches_oracle_planner(pm, seed, n_envs, depth, iters, early, rep, disc):
+    """disc: colliding sampled pushes discarded at node creation (Sec. IV-B)
+    on both sides, from the device's validity words and the oracle's FP64
+    start-pose test; 0 keeps them until their simulation starts."""
     if early or rep:
         st, bd = (f32(a) for a in near_clear_scene())
     else:
@@ -56,10 +60,11 @@ def test_plan_matches_oracle_planner(pm, seed, n_envs, depth, iters, early, rep)
     n = len(bd)
     sim = make_sim(pm, n_envs, n, 4096, depth)
     tree = pm.Tree(n, O.reward(st, bd, 0, 0.08), n_envs=n_envs, max_depth=depth, seed=seed, max_nodes=4096,
-                   early_stop=early, repurpose=rep)
+                   early_stop=early, repurpose=rep, discard=disc)
     res = pm.plan(sim, tree, st, bd, 0, iters, n_substeps=60)
     env = T.PhysicsEnv(O.make_config(), bd, target=0, substeps=60)
-    p = T.Planner(env, st, n_envs=n_envs, depth=depth, seed=seed, early_stop=bool(early), repurpose=bool(rep))
+    p = T.Planner(env, st, n_envs=n_envs, depth=depth, seed=seed, early_stop=bool(early), repurpose=bool(rep),
+                  discard=bool(disc))
     a_ref, v_ref = p.plan(iters)
     if rep:
         assert p.extra_simulations > 0   # the case does re-purpose environments

@@ -172,3 +172,80 @@ def test_repurposed_envs_run_extra_simulations(pm):
         else:
             assert xcnt[e] == 0
     assert ran >= 1   # at least one extra simulation drew random pushes
+
+
+def bits(words, n_act):
+    w = np.asarray(words, np.uint32)
+    return np.array([(int(w[a >> 5]) >> (a & 31)) & 1 for a in range(n_act)], bool)
+
+
+def oracle_validity(st, bd, tol=1e-5):
+    """FP64 start-pose validity of every contour push of a state, and which
+    pushes are decided by a margin of at least tol m (the FP32 and FP64
+    decisions must agree there)."""
+    ok = O.valid_pushes(CFG, st, bd)
+    sure = np.ones_like(ok)
+    for a in range(len(ok)):
+        obj, d = divmod(a, 8)
+        push = O.contour_push(CFG, st[obj], bd[obj], d, 8)
+        yaw = np.arctan2(push[3] - push[1], push[2] - push[0])
+        xp = np.array([push[0], push[1], CFG.pusher_z])
+        qp = np.array([np.cos(yaw / 2), 0, 0, np.sin(yaw / 2)])
+        hp = np.array(CFG.pusher_half[:])
+        sep = [O.sat_max_separation(CFG, st[j, :3], st[j, 3:7], bd[j, :3], xp, qp, hp) for j in range(len(st))]
+        sure[a] = min(abs(s) for s in sep) >= tol
+    return ok, sure
+
+
+def test_valid_pushes_match_the_oracle(pm):
+    """Start-pose validity words of every env's state (Sec. IV-B: colliding
+    sampled pushes are discarded): equal to the FP64 oracle's test for every
+    push decided by at least 10 um, from env states and from pool slots."""
+    b = scenes.clutter_batch(23, 8, (5, 30), region=0.22)
+    sim = pm.Sim(max_envs=b.n_envs, max_bodies=b.n_bodies, max_contacts=256, pool_slots=2 * b.n_envs,
+                 pool_stride=31, max_horizon=2)
+    sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+    words = sim.valid_pushes()
+    n_bad = n_sure = 0
+    for e in range(b.n_envs):
+        lo, hi = b.env_offset[e], b.env_offset[e + 1]
+        ok, sure = oracle_validity(f32(b.state[lo:hi]), f32(b.body[lo:hi]))
+        got = bits(words[e], len(ok))
+        assert np.array_equal(got[sure], ok[sure]), e
+        assert not bits(words[e], 248)[len(ok):].any()
+        n_bad += int((~ok).sum())
+        n_sure += int(sure.sum())
+    assert n_bad > 20 and n_sure > 0.95 * sum(8 * c for c in b.counts())
+    sim.pool_scatter(np.arange(b.n_envs, dtype=np.int32))
+    slots = np.arange(b.n_envs, dtype=np.int32)
+    assert np.array_equal(sim.valid_pushes(src_slot=slots), words)
+
+
+def test_rollout_child_validity_words(pm):
+    """A rollout with PMBS_ROLLOUT_CHILD_VALID writes, for every env with a
+    child slot and a valid first push, the validity words of the child's
+    state: bitwise those of a valid-only launch on the child's pool slot,
+    and the oracle's test on that state wherever it is decided by 10 um."""
+    b, acts, off, tgt = rollout_case(31, 24, (5, 20), [1, 2], substeps=20, region=0.25)
+    E = b.n_envs
+    sim = pm.Sim(max_envs=E, max_bodies=b.n_bodies, max_contacts=256, pool_slots=2 * E, pool_stride=31,
+                 max_horizon=2)
+    sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+    src = np.arange(E, dtype=np.int32)
+    child = src + E
+    child[::3] = -1
+    sim.pool_scatter(src)
+    sim.rollout(acts, off, tgt, n_substeps=20, src_slot=src, child_slot=child, max_h=2,
+                flags=pm.ROLLOUT_QUEUE | pm.ROLLOUT_CHILD_VALID)
+    status = sim.env_status()
+    words = sim.push_valid().copy()
+    made = [e for e in range(E) if child[e] >= 0 and not (status[e] & pm.PMBS_ENV_PUSH_INVALID)]
+    assert len(made) >= 8
+    again = sim.valid_pushes(src_slot=np.where(np.isin(np.arange(E), made), child, -1).astype(np.int32))
+    sim.pool_gather(np.where(child >= 0, child, -1).astype(np.int32))
+    st = sim.get_state().astype(np.float64)
+    for e in made:
+        assert np.array_equal(again[e], words[e]), e
+        lo, hi = b.env_offset[e], b.env_offset[e + 1]
+        ok, sure = oracle_validity(st[lo:hi], f32(b.body[lo:hi]))
+        assert np.array_equal(bits(words[e], len(ok))[sure], ok[sure]), e

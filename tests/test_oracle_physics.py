@@ -873,3 +873,57 @@ def test_rollout_stops_after_reward_one():
     r = O.rollout(CFG, st, bd, [(1, 4), (2, 2)], 120, 0, 0.08)
     assert r["applied"] == 1 and r["rewards"][0] == 1.0
     assert r["state"][2, 1] == st[2, 1]          # cube 2 untouched: push 1 never ran
+
+
+# ---------------------------------------------------------------- start-pose validity (Sec. IV-B)
+def test_valid_pushes_two_cubes_hand_worked():
+    """Cubes of 5 cm at x = 0 and x = 6 cm (1 cm gap).  A's contour push
+    along +x starts at x = 2.5 + 1 + 0.5 = 4 cm, so the 2 cm pusher spans
+    x in [3, 5] cm and overlaps B (from 3.5 cm); its 45-degree pushes start
+    at 5.04 cm along the diagonal, where the pusher (a diamond of half
+    diagonal 1.41 cm in the plane) holds B's corner (3.5, +-2.5) cm at L1
+    distance 1.12 cm.  The mirror images hold for B; every other push is
+    clear by more than 2 mm.  A lone cube has no invalid push."""
+    h = (0.025, 0.025, 0.025)
+    st = np.stack([state_row(x=(0.0, 0.0, 0.025)), state_row(x=(0.06, 0.0, 0.025))])
+    bd = np.stack([body_row(h), body_row(h)])
+    v = O.valid_pushes(CFG, st, bd)
+    want = np.ones(16, bool)
+    want[[0, 1, 7]] = False          # A toward B
+    want[[8 + 3, 8 + 4, 8 + 5]] = False  # B toward A
+    assert np.array_equal(v, want), v.reshape(2, 8)
+    assert O.valid_pushes(CFG, st[:1], bd[:1]).all()
+
+
+def _pusher_pose(push):
+    d = np.array([push[2] - push[0], push[3] - push[1]])
+    yaw = math.atan2(d[1], d[0])
+    x = np.array([push[0], push[1], CFG.pusher_z])
+    return x, np.array([math.cos(yaw / 2), 0, 0, math.sin(yaw / 2)]), np.array(CFG.pusher_half[:])
+
+
+@pytest.mark.parametrize("seed", [3, 8])
+def test_valid_pushes_match_brute_force_overlap(seed):
+    """On clutter, a push is valid exactly when the pusher box at its start
+    pose (start point at the pusher height, yawed along the push) intersects
+    no object, by brute-force vertex and edge tests; cases within 1e-9 m of
+    touching are skipped."""
+    b = scenes.clutter_batch(seed, 1, 12, region=0.2)
+    st, bd = b.state, b.body
+    v = O.valid_pushes(CFG, st, bd)
+    n_bad = n_checked = 0
+    for a in range(len(v)):
+        obj, d = divmod(a, 8)
+        push = O.contour_push(CFG, st[obj], bd[obj], d)
+        xp, qp, hp = _pusher_pose(push)
+        hits, near = [], False
+        for j in range(len(st)):
+            s = O.sat_max_separation(CFG, st[j, :3], st[j, 3:7], bd[j, :3], xp, qp, hp)
+            near = near or abs(s) < 1e-9
+            hits.append(_brute_intersect(st[j, :3], st[j, 3:7], bd[j, :3], xp, qp, hp))
+        if near:
+            continue
+        n_checked += 1
+        assert v[a] == (not any(hits)), a
+        n_bad += not v[a]
+    assert n_checked > 80 and 5 < n_bad < n_checked

@@ -293,3 +293,52 @@ def test_repurposed_environment_runs_an_extra_replica_of_the_next_pair():
     q = T.Planner(ToyEnv(k=2, lock=(a0,), base=base), (), n_envs=2, depth=3, seed=seed, repurpose=False)
     q.iterate()
     assert q.extra_simulations == 0 and {c.action: c for c in q.root.children}[a1].Q == 0.0
+
+
+def test_discarded_actions_are_never_selected():
+    """Sec. IV-B order, worked by hand: sampled actions that cannot start are
+    removed when the node is created, before selection.  Four actions, action
+    1 invalid, four environments, depth 1: the batch holds the three valid
+    actions as unique pairs and the fourth environment replicates the first
+    pair (leaf parallelisation); no environment is spent on action 1.
+    Without the discard step action 1 takes a pair and an environment and
+    is dropped only when its simulation starts."""
+    class Env(ToyEnv):
+        def valid_actions(self, state):
+            return [self.valid(state, a) for a in range(self.k)]
+
+    env = Env(k=4, lock=(9,), valid=lambda s, a: a != 1)
+    p = T.Planner(env, (), n_envs=4, depth=1, seed=2, discard=True)
+    assert sorted(p.root.untried) == [0, 2, 3]
+    probe = T.Planner(Env(k=4, lock=(9,), valid=lambda s, a: a != 1), (), n_envs=4, depth=1, seed=2, discard=True)
+    pairs, envs = T.select_batch(probe.root, 4, probe.c, probe.D)
+    assert sorted(a for _, a in pairs) == [0, 2, 3]
+    assert envs == [(0, 0), (1, 0), (2, 0), (0, 1)]
+    p.iterate()
+    assert len(env.calls) == 4 and all(c[1][0] != 1 for c in env.calls)
+    assert sorted(ch.action for ch in p.root.children) == [0, 2, 3] and p.root.N == 3
+    q = T.Planner(Env(k=4, lock=(9,), valid=lambda s, a: a != 1), (), n_envs=4, depth=1, seed=2)
+    q.iterate()
+    assert any(c[1][0] == 1 for c in q.env.calls) and q.root.N == 3
+
+
+def test_repurposed_extra_simulation_stops_at_its_pairs_depth_limit():
+    """Worked by hand: depth limit 4, two pairs in one batch, (root, 0) at
+    depth 0 and (c2, 1) at depth 2.  The root pair's environment reaches
+    reward 1 on its first push with three of its four pushes left, but the
+    extra simulation of (c2, 1) may go only D - 2 = 2 pushes deep: it runs
+    the pair's action and one random push, not three pushes."""
+    env = ToyEnv(k=2, lock=(0,))
+    p = T.Planner(env, (), n_envs=2, depth=4, seed=1, repurpose=True)
+    root = p.root
+    c1 = T.Node(1, root, 1, 1, (1,), 0.0, [])
+    c2 = T.Node(2, c1, 1, 2, (1, 1), 0.0, [1])
+    root.children, c1.children = [c1], [c2]
+    root.untried = [0]
+    for n in (root, c1, c2):
+        n.N, n.Q = 1, 0.0
+    p.next_id = 3
+    p.iterate()
+    assert p.extra_simulations == 1
+    state, acts = env.calls[-1]
+    assert state == (1, 1) and len(acts) == 2 and acts[0] == 1
