@@ -26,18 +26,28 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (counts packed FP32: two operations per lane per cycle)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6   # the same without packed FP32 (256 CUs x 2.4 GHz x 128 flop/cycle)
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 
 
 def flops_per_env_substep(nc: float, npairs: float, nb: float, iters: int) -> float:
-    """Algorithmic FP32 operations of one substep of one environment
-    (FMA = 2): per Jacobi iteration 108 per contact (relative velocity,
-    normal and friction-cone update, impulse and its two torques, per-body
-    sums) and 21 per body (velocity updates); per substep 230 per contact
-    (lever arms, tangent basis, three split effective masses, bias), 880 per
-    candidate pair (15-axis SAT) and 190 per body (integration, frames,
-    world inverse inertia, AABB, plane vertices)."""
+    """Algorithmic FP32 operations of one substep of one environment, the
+    work model F = N_c (250 + 144 I) + 300 n_b + 500 N_cand + 1000 (FMA = 2):
+    per contact and Jacobi iteration 144 (relative velocity at both lever
+    arms, normal and friction-cone update, impulse, its two torques, the
+    per-body sums and velocity updates), per contact 250 of preparation
+    (lever arms, tangent basis, three effective masses, bias), per body 300
+    (velocity and position stages, frames, world inverse inertia, AABB,
+    plane vertices), per candidate pair 500 (separating-axis test) and
+    1000 per environment (sort and sweep, push begin)."""
+    return nc * (250.0 + 144.0 * iters) + 300.0 * nb + 500.0 * npairs + 1000.0
+
+
+def flops_counted(nc: float, npairs: float, nb: float, iters: int) -> float:
+    """The same work counted from the kernel's own arithmetic (FMA = 2):
+    per Jacobi iteration 108 per contact and 21 per body; per substep 230
+    per contact, 880 per candidate pair (15 axes) and 190 per body."""
     return iters * (108.0 * nc + 21.0 * nb) + 230.0 * nc + 880.0 * npairs + 190.0 * nb
 
 
@@ -154,6 +164,44 @@ def plan_latency(pmbs, scenes, args) -> dict:
                    "projected_s_same_simulations": round(projected, 3)},
         "speedup_vs_serial": round(projected / float(np.percentile(t, 50)), 2),
     }
+
+
+def batched_1024(pmbs, scenes, args) -> dict:
+    """The batched-step workload at 1024 envs x 15 cuboids (seed 1): the same
+    step (pool gather + fused push step + reward) timed over args.steps."""
+    import torch
+    b = scenes.clutter_batch(1, args.small_envs, args.bodies)
+    E = b.n_envs
+    dev = torch.device("cuda:0")
+    sim = pmbs.Sim(max_envs=E, max_bodies=b.n_bodies, pool_slots=E, pool_stride=int(b.counts().max()))
+    sim.set_state(b.env_offset, b.state, b.body)
+    slots = torch.arange(E, dtype=torch.int32, device=dev)
+    sim.pool_scatter(slots)
+    push = torch.tensor(b.push.astype(np.float32), device=dev).contiguous()
+    target = torch.zeros(E, dtype=torch.int32, device=dev)
+    rew = torch.empty(E, dtype=torch.float32, device=dev)
+    clr = torch.empty(E, dtype=torch.float32, device=dev)
+
+    def one():
+        sim.pool_gather(slots)
+        sim.step(push, args.substeps)
+        sim.eval_reward(target, 0.08, rew, clr, sync=False)
+
+    for _ in range(args.warmup):
+        one()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record(sim.stream)
+    for _ in range(args.steps):
+        one()
+    ev[1].record(sim.stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    status = sim.env_status()
+    return {"workload": f"{E} envs x {args.bodies} cuboids, one 5 cm circle push each, {args.substeps} substeps "
+                        "(seed 1)",
+            "env_substeps_per_s": round(E * args.substeps / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+            "valid_pushes": int(np.sum((status & pmbs.PMBS_ENV_PUSH_INVALID) == 0))}
 
 
 def plain_per_push(sim, acts, off, tgt, n_substeps, width=0.08, rewards=None, counts=None):
@@ -349,6 +397,8 @@ def main() -> int:
     ap.add_argument("--uneven-envs", type=int, default=4096, help="envs of the uneven batch (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=24, help="requests of the serving runs (0: skip)")
     ap.add_argument("--uneven-reps", type=int, default=4)
+    ap.add_argument("--small-envs", type=int, default=1024, help="envs of the 1024 x 15 batched line (0: skip)")
+    ap.add_argument("--no-peaks", dest="peaks", action="store_false", help="skip the FMA / copy peak probes")
     ap.add_argument("--copy-mb", type=int, default=256,
                     help="size of a plain device copy run after the timed region (counter calibration)")
     args = ap.parse_args()
@@ -406,6 +456,10 @@ def main() -> int:
     status = sim.env_status()
     stats = sim.stats().astype(np.float64)[:, :2]
     n_valid = int(np.sum((status & pmbs.PMBS_ENV_PUSH_INVALID) == 0))
+    # push mix: a valid push that moved some box by more than 1 mm touched it
+    after = sim.get_state()
+    moved = np.linalg.norm(after[:, :3] - batch.state[:, :3].astype(np.float32), axis=1) > 1e-3
+    n_touch = int(np.add.reduceat(moved.astype(np.int64), batch.env_offset[:-1]).astype(bool).sum())
     n_overflow = int(np.sum((status & pmbs.PMBS_ENV_CONTACT_OVERFLOW) != 0))
     if np.any(status & (pmbs.PMBS_ENV_NONFINITE | pmbs.PMBS_ENV_CONTACT_OVERFLOW)):
         print("# warning: non-finite or overflowing environments", file=sys.stderr)
@@ -417,6 +471,7 @@ def main() -> int:
     f_unit = flops_per_env_substep(nc, npairs, nb, iters)
     flops_launch = f_unit * env_substeps
     achieved_tflops = flops_launch / (k_avg_ms * 1e-3) / 1e12
+    f_counted = flops_counted(nc, npairs, nb, iters)
     bytes_launch = hbm_bytes_per_call(N, E)
     achieved_gbs = bytes_launch / (k_avg_ms * 1e-3) / 1e9
 
@@ -430,6 +485,8 @@ def main() -> int:
 
     ms_per_step = total_ms / args.steps
     value = env_substeps * args.steps / (total_ms * 1e-3)
+    peaks = pmbs.measure_peaks() if args.peaks else None
+    configs1 = batched_1024(pmbs, scenes, args) if args.small_envs > 0 else None
     out = {
         "metric": "env-substeps/sec (4096 envs x 15 boxes) + %HBM peak; p50/p99 MCTS plan latency",
         "value": round(value, 1),
@@ -450,6 +507,7 @@ def main() -> int:
             "envs": E, "bodies_per_env": args.bodies, "substeps": args.substeps,
             "solver_iters": iters, "seed": args.seed, "valid_pushes": n_valid,
             "max_contacts": int(sim.cfg.max_contacts), "overflow_envs": n_overflow,
+            "push_mix": {"discarded": E - n_valid, "valid_touching": n_touch, "valid_missing": n_valid - n_touch},
         },
         "roofline": {
             "kernel": "step_kernel",
@@ -461,6 +519,11 @@ def main() -> int:
             "traffic": measured_traffic(E, args.bodies, args.substeps),
             "kernel_ms": round(k_avg_ms, 4),
             "flop_per_env_substep": round(f_unit, 1),
+            "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+            "frac_nonpacked": round(achieved_tflops / PEAK_FP32_NONPACKED_TFLOPS, 5),
+            "measured_fma_peak": peaks["fma_tflops"] if peaks else None,
+            "frac_measured_peak": round(achieved_tflops / peaks["fma_tflops"], 5) if peaks else None,
+            "flop_per_env_substep_counted": round(f_counted, 1),
             "contacts_per_env_substep": round(nc, 3),
             "pairs_per_env_substep": round(npairs, 3),
         },
@@ -470,8 +533,13 @@ def main() -> int:
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(achieved_gbs / PEAK_HBM_GBS, 6),
+            "measured_copy_peak": peaks["copy_gbs"] if peaks else None,
         },
     }
+    if peaks:
+        out["peaks"] = peaks
+    if configs1:
+        out["batched_1024"] = configs1
 
     if args.plan_scenes > 0:
         out["plan"] = plan_latency(pmbs, scenes, args)

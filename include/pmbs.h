@@ -308,6 +308,17 @@ pmbs_status pmbs_sim_stats(pmbs_sim_t* sim, int64_t* out);
 pmbs_status pmbs_pool_gather(pmbs_sim_t* sim, const int32_t* slots, int32_t slots_is_device);
 pmbs_status pmbs_pool_scatter(pmbs_sim_t* sim, const int32_t* slots, int32_t slots_is_device);
 
+/* Achievable-peak probes (measurement only): pmbs_probe_fma launches
+ * `blocks` workgroups of 256 lanes, each lane running 16 independent chains
+ * of `iters` FP32 multiply-adds (non-packed, as every kernel of the library
+ * is built), writing one sum per lane to d_sink (float32 [blocks * 256]);
+ * *flop (optional) receives the operations it performs (2 per multiply-add).
+ * pmbs_probe_copy copies `bytes` (a multiple of 16, 16-byte aligned
+ * buffers) from d_src to d_dst with a grid-stride 16-byte copy.  Both are
+ * asynchronous on hip_stream; the caller times them with its own events. */
+pmbs_status pmbs_probe_fma(float* d_sink, int32_t blocks, int32_t iters, void* hip_stream, double* flop);
+pmbs_status pmbs_probe_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream);
+
 /* Waits for all work enqueued on the simulator's stream. */
 pmbs_status pmbs_sim_sync(pmbs_sim_t* sim);
 

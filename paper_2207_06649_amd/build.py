@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmbs.so")
 
-SOURCES = ["pmbs_kernels.hip", "pmbs_sim.cpp", "pmbs_tree.cpp", "pmbs_plan.cpp", "pmbs_tune.cpp", "pmbs_server.cpp", "pmbs_brute.cpp", "pmbs_static.hip"]
+SOURCES = ["pmbs_kernels.hip", "pmbs_sim.cpp", "pmbs_tree.cpp", "pmbs_plan.cpp", "pmbs_tune.cpp", "pmbs_server.cpp", "pmbs_brute.cpp", "pmbs_static.hip", "pmbs_probe.hip"]
 
 # No packed FP32 (v_pk_*_f32) code generation anywhere in the device code.
 # Multiply-adds are fused only within one source expression (and where fmaf

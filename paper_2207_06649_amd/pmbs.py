@@ -101,6 +101,8 @@ def lib():
                                               C.c_int32]
         L.pmbs_sim_valid_pushes.argtypes = [vp, vp, C.c_int32]
         L.pmbs_sim_push_valid.argtypes = [vp, vp, C.c_int32]
+        L.pmbs_probe_fma.argtypes = [vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_double)]
+        L.pmbs_probe_copy.argtypes = [vp, vp, C.c_size_t, vp]
         L.pmbs_sim_shape.argtypes = [vp, ip, ip]
         _lib = L
     return _lib
@@ -677,3 +679,40 @@ class Server:
     def __del__(self):
         if getattr(self, "_L", None) is not None:
             self.close()
+
+
+def measure_peaks(device: str = "cuda:0", copy_mb: int = 1024, reps: int = 5) -> dict:
+    """Achievable FP32 multiply-add rate (TFLOP/s, non-packed) and device
+    copy bandwidth (GB/s, bytes read + written) of the GPU, best of reps."""
+    import torch
+    dev = torch.device(device)
+    st = torch.cuda.current_stream(dev)
+    L = lib()
+    props = torch.cuda.get_device_properties(dev)
+    blocks = props.multi_processor_count * 8
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    flop = C.c_double(0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best_fma = 0.0
+    for k in range(reps + 1):
+        ev[0].record(st)
+        _check(L.pmbs_probe_fma(_ptr(sink), blocks, 20000, C.c_void_p(st.cuda_stream), C.byref(flop)))
+        ev[1].record(st)
+        torch.cuda.synchronize(dev)
+        if k:
+            best_fma = max(best_fma, flop.value / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e12)
+    n = copy_mb * (1 << 20)
+    src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    best_copy = 0.0
+    for k in range(reps + 1):
+        ev[0].record(st)
+        _check(L.pmbs_probe_copy(_ptr(src), _ptr(dst), n, C.c_void_p(st.cuda_stream)))
+        ev[1].record(st)
+        torch.cuda.synchronize(dev)
+        if k:
+            best_copy = max(best_copy, 2.0 * n / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9)
+    del src, dst, sink
+    return {"fma_tflops": round(best_fma, 2), "copy_gbs": round(best_copy, 1),
+            "fma_probe": f"{blocks} x 256 lanes, 16 chains x 20000 FP32 multiply-adds each",
+            "copy_probe": f"{copy_mb} MiB device copy (read + write counted)"}
