@@ -322,10 +322,13 @@ def serving(pmbs, scenes, args) -> dict:
     iterations, depth <= 5, 120 substeps per push.  Continuous batching
     (every request in flight advances one iteration per packed,
     graph-replayed launch; admission by free env slots, request slots and
-    node-pool bytes) against the plain form: one request at a time in
-    arrival order, each with its own batched launches.  Capacity comes from
-    a saturated run (all requests at t = 0); latency from a Poisson run at
-    0.7x the plain form's capacity (or the nominal 50/s if that is lower)."""
+    node-pool bytes; two launch lanes, so one lane's tree work overlaps the
+    other lane's device work) against the plain form: one request at a
+    time in arrival order, each with its own batched launches.  Capacity
+    comes from saturated runs (all requests at t = 0; continuous batching
+    also with one lane); latency from Poisson runs at 0.7x each form's own
+    capacity, and of continuous batching at the plain form's rate too (the
+    nominal 50 requests/s saturates both forms)."""
     rng = np.random.default_rng([4, 2024])
     n = args.serve_requests
     reqs = []
@@ -336,9 +339,9 @@ def serving(pmbs, scenes, args) -> dict:
                          iterations=int(rng.integers(10, 31)), seed=1000 + k))
     gaps = rng.exponential(1.0, size=n)
 
-    def run(continuous: bool, rate: float | None) -> dict:
+    def run(continuous: bool, rate: float | None, lanes: int = 2) -> dict:
         srv = pmbs.Server(max_envs=4096, max_requests=16 if continuous else 1, pool_slots=262144,
-                          n_substeps=args.substeps, graph=1 if continuous else 0)
+                          n_substeps=args.substeps, graph=1 if continuous else 0, lanes=lanes if continuous else 1)
         t0 = time.perf_counter()
         arrivals = np.cumsum(gaps / rate) - gaps[0] / rate if rate else np.zeros(n)
         ids = []
@@ -353,7 +356,8 @@ def serving(pmbs, scenes, args) -> dict:
         srv.close()
         lat = np.array([r["latency_seconds"] for r in res])
         useful = sum(r["env_substeps"] for r in res)
-        return {"requests": n, "wall_s": round(wall, 3), "env_substeps_per_s": round(useful / wall, 1),
+        return {"requests": n, "offered_per_s": round(rate, 3) if rate else None, "wall_s": round(wall, 3),
+                "env_substeps_per_s": round(useful / wall, 1),
                 "requests_per_s": round(n / wall, 3), "p50_s": round(float(np.percentile(lat, 50)), 4),
                 "p99_s": round(float(np.percentile(lat, 99)), 4), "launches": st["launches"],
                 "peak_in_flight": st["peak_in_flight"], "peak_held_mb": round(st["peak_held_bytes"] / 2**20, 1),
@@ -364,18 +368,23 @@ def serving(pmbs, scenes, args) -> dict:
     print(f"# serving plain saturated: {plain_sat['requests_per_s']} req/s", file=sys.stderr, flush=True)
     cont_sat = run(True, None)
     print(f"# serving continuous saturated: {cont_sat['requests_per_s']} req/s", file=sys.stderr, flush=True)
-    rate = min(50.0, 0.7 * plain_sat["requests_per_s"])
-    plain = run(False, rate)
-    cont = run(True, rate)
-    same = all(a == b for a, b in zip(plain.pop("results"), cont.pop("results")))
-    for d in (plain_sat, cont_sat):
-        d.pop("results")
+    cont1_sat = run(True, None, lanes=1)
+    print(f"# serving continuous, one lane, saturated: {cont1_sat['requests_per_s']} req/s", file=sys.stderr,
+          flush=True)
+    rate_plain = min(50.0, 0.7 * plain_sat["requests_per_s"])
+    rate_cont = min(50.0, 0.7 * cont_sat["requests_per_s"])
+    plain = run(False, rate_plain)
+    cont = run(True, rate_cont)
+    cont_same_rate = run(True, rate_plain)
+    res = [d.pop("results") for d in (plain, cont, cont_same_rate, plain_sat, cont_sat, cont1_sat)]
+    same = all(r == res[0] for r in res[1:])
     return {
         "workload": f"{n} requests: 5-30 cuboids (target at the centre, 0.4 m square), leaves U{{64,256,1024}}, "
                     f"10-30 iterations, depth <= 5, {args.substeps} substeps per push",
-        "offered_rate_per_s": round(rate, 3),
-        "continuous": cont, "plain_per_request": plain,
-        "capacity": {"continuous": cont_sat, "plain_per_request": plain_sat},
+        "nominal_rate_per_s": 50.0,
+        "nominal_rate_saturates_both": bool(cont_sat["requests_per_s"] < 50.0 and plain_sat["requests_per_s"] < 50.0),
+        "continuous": cont, "plain_per_request": plain, "continuous_at_plain_rate": cont_same_rate,
+        "capacity": {"continuous": cont_sat, "continuous_one_lane": cont1_sat, "plain_per_request": plain_sat},
         "same_results_alone_and_mixed": same,
     }
 
@@ -395,7 +404,7 @@ def main() -> int:
     ap.add_argument("--plan-leaves", type=int, default=256)
     ap.add_argument("--serial-iters", type=int, default=64, help="one-leaf iterations timed for the serial baseline")
     ap.add_argument("--uneven-envs", type=int, default=4096, help="envs of the uneven batch (0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=24, help="requests of the serving runs (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=48, help="requests of the serving runs (0: skip)")
     ap.add_argument("--uneven-reps", type=int, default=4)
     ap.add_argument("--small-envs", type=int, default=1024, help="envs of the 1024 x 15 batched line (0: skip)")
     ap.add_argument("--no-peaks", dest="peaks", action="store_false", help="skip the FMA / copy peak probes")

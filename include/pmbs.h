@@ -523,6 +523,8 @@ typedef struct pmbs_server_config {
   int32_t early_stop;     /* Alg. 1 early stop in every request's tree (pmbs_tree_status) */
   int32_t repurpose;      /* environment re-purposing in every request (pmbs_tree_extra) */
   int32_t discard;        /* discard colliding sampled pushes before selection (pmbs_tree_config) */
+  int32_t lanes;          /* launch lanes (2: while one lane's launch runs, the other lane's trees are
+                             updated and its next launch is queued; 1: one launch at a time) */
 } pmbs_server_config;
 
 typedef struct pmbs_request {
@@ -557,7 +559,7 @@ typedef struct pmbs_server_stats {
  * simulator defaults with max_contacts 256. */
 void pmbs_server_config_default(pmbs_server_config* cfg);
 /* Device bytes of the server's workspace (node pool of pool_slots x 31
- * bodies x 52 B plus the simulator's buffers). */
+ * bodies x 52 B plus the staging buffers of each launch lane). */
 pmbs_status pmbs_server_query_workspace(const pmbs_server_config* cfg, size_t* bytes);
 /* Starts the worker thread on the calling thread's current device; the
  * workspace (device, 256-byte aligned) and stream are the caller's until

@@ -110,6 +110,9 @@ pmbs_status check_rollout_inputs(const pmbs_sim_t* sim, const int32_t* actions, 
 // kernel; an env's estimated work (longest first) under the launch plan
 int class_split(const pmbs_sim_t* sim);
 int64_t work_weight(const pmbs_sim_t* sim, const int32_t* act_offset, int e);
+// sim uses from's node pool and body table (same max_bodies) instead of its
+// own: two simulators on separate streams working on one set of tree nodes
+void share_pool(pmbs_sim_t* sim, const pmbs_sim_t* from);
 // workgroups of a persistent launch of the given contact class
 int class_grid(pmbs_sim_t* sim, int max_contacts, int blocks_per_cu);
 // the queued rollout launches (all contact classes and fallbacks) on `stream`

@@ -380,6 +380,13 @@ int64_t work_weight(const pmbs_sim_t* sim, const int32_t* act_offset, int e) {
   return sim->plan.order == 0 ? h : (int64_t)h * (nb + 4);
 }
 
+void share_pool(pmbs_sim_t* sim, const pmbs_sim_t* from) {
+  sim->d_pool = from->d_pool;
+  sim->d_bconst = from->d_bconst;
+  sim->cfg.pool_slots = from->cfg.pool_slots;
+  sim->cfg.pool_stride = from->cfg.pool_stride;
+}
+
 StepArgs step_args(pmbs_sim_t* sim) {
   StepArgs a;
   std::memset(&a, 0, sizeof a);  // padding too: launch arguments are compared bytewise

@@ -564,7 +564,7 @@ class ServerConfig(C.Structure):
                 ("pool_slots", C.c_int32), ("max_depth", C.c_int32), ("n_substeps", C.c_int32),
                 ("width", C.c_float), ("c", C.c_double), ("gamma", C.c_double), ("hbm_budget", C.c_int64),
                 ("graph", C.c_int32), ("early_stop", C.c_int32), ("repurpose", C.c_int32),
-                ("discard", C.c_int32)]
+                ("discard", C.c_int32), ("lanes", C.c_int32)]
 
 
 class Request(C.Structure):

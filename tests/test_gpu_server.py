@@ -55,6 +55,23 @@ def test_result_alone_equals_result_in_the_mix(pm, flags):
         assert same(a, m), (a, m)
 
 
+def test_two_lanes_give_the_one_lane_results(pm):
+    """Two launch lanes (one lane's trees updated while the other lane's
+    launch runs, both lanes' launches overlapping on the device) give every
+    request bitwise the result of one lane, with re-purposing and discards."""
+    reqs = requests() + requests()[:2]
+    res = {}
+    for lanes in (1, 2):
+        srv = small_server(pm, lanes=lanes, repurpose=1)
+        ids = [srv.submit(**q) for q in reqs]
+        res[lanes] = [srv.wait(i) for i in ids]
+        st = srv.stats()
+        srv.close()
+        assert st["completed"] == len(reqs)
+    for a, b in zip(res[1], res[2]):
+        assert same(a, b), (a, b)
+
+
 def test_server_matches_the_single_request_planner(pm):
     """pmbs_plan on a simulator of the same contact classes gives bitwise the
     server's result (the server packs scenes by body-table rows and pool
