@@ -181,9 +181,15 @@ typedef struct pmbs_launch_plan {
   int32_t small_blocks_per_cu; /* persistent workgroups per CU, 0: as many as fit */
   int32_t large_blocks_per_cu;
   int32_t order;               /* 0: horizon first; 1: horizon x (bodies + 4) first */
+  int32_t small_waves;         /* workgroup shape of the 128-contact class: waves per environment (1 or
+                                  2: a second wave takes half the contact slots and every second
+                                  narrowphase pass; bitwise the same result) */
+  int32_t large_waves;         /* the same for the 256-contact class (and its overflow re-runs) */
 } pmbs_launch_plan;
 
-/* Defaults: small_max_bodies 16, blocks per CU 0, order 1. */
+/* Defaults: small_max_bodies 16, blocks per CU 0, order 1, one wave per
+ * environment.  Launches outside the work queues (step, plain rollouts)
+ * use the waves of the simulator's own contact class. */
 pmbs_status pmbs_sim_set_launch_plan(pmbs_sim_t* sim, const pmbs_launch_plan* plan);
 pmbs_status pmbs_sim_get_launch_plan(const pmbs_sim_t* sim, pmbs_launch_plan* plan);
 

@@ -38,7 +38,8 @@ struct pmbs_sim {
   float* d_x_rewards;      // [max_envs][max_horizon] extra simulations' rewards (planner, server)
   int32_t* d_x_counts;     // [max_envs]
   uint32_t* d_valid;       // [max_envs][PMBS_VALID_WORDS] start-pose validity words
-  int cus = 0, occ[3] = {0, 0, 0};   // CUs; resident blocks per CU of the 128/256/512 kernels
+  int cus = 0, occ[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // CUs; resident blocks per CU of the
+                                                      // 128/256/512 kernels, 1 or 2 waves per env
   pmbs_launch_plan plan;
   // internal streams and events for the concurrent class launches and graph capture
   hipStream_t side = nullptr, cap = nullptr;
@@ -47,6 +48,7 @@ struct pmbs_sim {
   hipGraphExec_t graph_exec = nullptr;
   pmbs::StepArgs graph_args;
   pmbs_launch_plan graph_plan;
+  int graph_valid = 0;   // the captured sequence ends with the children's validity launch
   int32_t n_envs, n_bodies;
   std::vector<int32_t> host_offset;
   bool pool_layout = false;   // envs live only in pool slots, body constants at d_bc_base rows
@@ -113,9 +115,14 @@ int64_t work_weight(const pmbs_sim_t* sim, const int32_t* act_offset, int e);
 // sim uses from's node pool and body table (same max_bodies) instead of its
 // own: two simulators on separate streams working on one set of tree nodes
 void share_pool(pmbs_sim_t* sim, const pmbs_sim_t* from);
-// workgroups of a persistent launch of the given contact class
-int class_grid(pmbs_sim_t* sim, int max_contacts, int blocks_per_cu);
-// the queued rollout launches (all contact classes and fallbacks) on `stream`
+// waves per environment of a contact class under the launch plan
+int plan_waves(const pmbs_sim_t* sim, int max_contacts);
+// workgroups of a persistent launch of the given contact class and shape
+int class_grid(pmbs_sim_t* sim, int max_contacts, int blocks_per_cu, int waves);
+// the queued rollout launches (all contact classes and fallbacks) on
+// `stream`, then the children's validity words when va is given
 hipError_t enqueue_queued(pmbs_sim_t* sim, const StepArgs& a, hipStream_t stream, bool skip_empty, int n_small,
-                          int n_large);
+                          int n_large, const ValidArgs* va);
+// validity launch arguments over the simulator's env layout
+ValidArgs valid_args(pmbs_sim_t* sim, const int32_t* d_src_slot);
 }  // namespace pmbs

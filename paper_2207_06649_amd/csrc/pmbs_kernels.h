@@ -51,12 +51,6 @@ struct StepArgs {
   const uint2* x_key;
   float* x_rewards;
   int* x_count;
-  // start-pose validity (Sec. IV-B): env e writes PMBS_VALID_WORDS words at
-  // valid_out[e * PMBS_VALID_WORDS], bit a set when contour push a can
-  // start; in a rollout for the state after the first push of an env with a
-  // child slot (null: none); valid_only: only that, for the loaded state
-  uint32_t* valid_out;
-  int valid_only;
   // work distribution
   const int* order;         // work item -> env (null: identity)
   int* queue;               // device counter (null: one block per work item)
@@ -66,6 +60,24 @@ struct StepArgs {
   // larger class (null: it finishes with the overflow status bit)
   int* overflow_list;
   int* overflow_count;
+  Params p;
+};
+
+// Start-pose validity of the contour pushes of every env (Sec. IV-B): env e
+// writes PMBS_VALID_WORDS words at out[e * PMBS_VALID_WORDS], bit a set when
+// push a can start, from its state (or pool slot src_slot[e]; < 0 skips it).
+struct ValidArgs {
+  const float* state;       // SoA [13][stride]
+  const float* bconst;      // SoA [8][rows]
+  const int* env_offset;
+  const int* src_slot;      // null: every env from its state
+  const float* pool;
+  const int* bc_base;       // null: constants at the env's own rows
+  uint32_t* out;
+  // env count: count[0] + count[1] read on the device when count is given
+  // (a captured graph replays with the counts of each call), else n_envs
+  const int* count;
+  int n_envs, stride, pool_stride, bc_stride;
   Params p;
 };
 
@@ -96,13 +108,16 @@ struct PoolArgs {
 };
 
 hipError_t launch_pool(const PoolArgs& a, hipStream_t stream);
-int step_blocks_per_cu(int max_contacts);
-// one workgroup per env (no queue)
-hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream);
+// resident workgroups per CU of a contact class with 1 or 2 waves per env
+int step_blocks_per_cu(int max_contacts, int waves);
+// one workgroup per env (no queue), of 1 or 2 waves
+hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream, int waves = 1);
 // persistent queue launch of one contact class without resetting the queue
 // counter (the caller clears it, e.g. with launch_zero)
-hipError_t launch_step_class(const StepArgs& a, int max_contacts, hipStream_t stream, int grid);
+hipError_t launch_step_class(const StepArgs& a, int max_contacts, hipStream_t stream, int grid, int waves = 1);
 hipError_t launch_zero(int* p, int n, hipStream_t stream);
 hipError_t launch_reward(const RewardArgs& a, hipStream_t stream);
+// one workgroup per env, or a fixed grid looping over the device-held count
+hipError_t launch_valid(const ValidArgs& a, hipStream_t stream, int grid = 0);
 
 }  // namespace pmbs

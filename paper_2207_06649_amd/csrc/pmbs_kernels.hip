@@ -102,7 +102,7 @@ __device__ __forceinline__ void wave_sync() {
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-template <int K>
+template <int K, int W>
 struct Smem {
   static constexpr int C = 64 * K;
   float4 pos[NOBJ];                  // centre
@@ -132,9 +132,14 @@ struct Smem {
   } u;
   float4 zero;                       // a row of zeros after the impulse rows (never written)
   union {
-    float clip[2][POLY][3][CLIP_GROUPS]; // narrowphase: clip polygons of the eight groups
-    unsigned incm[NOBJ][2 * K];          // incidence build: contact bit masks per body
+    float clip[W][2][POLY][3][CLIP_GROUPS]; // narrowphase: clip polygons of each wave's eight groups
+    unsigned incm[NOBJ][2 * K];             // incidence build: contact bit masks per body
   } x;
+  // counts the waves of an environment exchange: candidate pairs, table
+  // contacts, and each wave's kept contacts of a narrowphase round (by the
+  // round's parity)
+  int sh_pairs, sh_plane;
+  int rcount[2][W];
 };
 
 // Contact key (a+1, b, feature) with the table as a = -1: strictly
@@ -154,8 +159,8 @@ struct Box {
 __device__ __forceinline__ f3 axis(const Box& b, int k) { return sel(k == 0, b.a0, sel(k == 1, b.a1, b.a2)); }
 __device__ __forceinline__ float hcomp(const Box& b, int k) { return sel(k == 0, b.h.x, sel(k == 1, b.h.y, b.h.z)); }
 
-template <int K>
-__device__ __forceinline__ Box load_box(const Smem<K>& s, int i) {
+template <class S>
+__device__ __forceinline__ Box load_box(const S& s, int i) {
   Box b;
   b.c = xyz(s.pos[i]);
   b.a0 = xyz(s.col[0][i]);
@@ -199,8 +204,8 @@ __device__ __forceinline__ bool sat_clear(const Box& A, const Box& B, float eps)
 // n_dirs around object obj in its yaw frame, starting beyond the
 // footprint's ray-to-boundary distance by the pusher half width plus the
 // standoff, moving push_length toward the object centre; (x_s, y_s, x_e, y_e).
-template <int K>
-__device__ __forceinline__ float4 contour_start(const Smem<K>& s, int obj, int dir, const Params& p) {
+template <class S>
+__device__ __forceinline__ float4 contour_start(const S& s, int obj, int dir, const Params& p) {
   const f3 oc = xyz(s.pos[obj]), oa0 = xyz(s.col[0][obj]), oh = xyz(s.half[obj]);
   const float th = 6.283185307179586f * (float)dir / (float)p.n_dirs;
   const float cth = cosf(th), sth = sinf(th);
@@ -253,8 +258,8 @@ __device__ __forceinline__ Box pusher_box(const PusherPose& q, const Params& p) 
 // when its pusher start pose clears every box.  Lane w < PMBS_VALID_WORDS
 // returns word w (bit a mod 32 of word a / 32 set when action a is valid);
 // the other lanes return 0.
-template <int K>
-__device__ __forceinline__ unsigned validity_word(const Smem<K>& s, int nb, const Params& p, int lane) {
+template <class S>
+__device__ __forceinline__ unsigned validity_word(const S& s, int nb, const Params& p, int lane) {
   const int n_act = nb * p.n_dirs;
   unsigned word = 0u;
   for (int a0 = 0; a0 < n_act; a0 += 64) {
@@ -346,15 +351,16 @@ __device__ __forceinline__ void sat_scan8(float sv0, float sv1, float tf, float 
 }
 
 // ------------------------------------------------------------------ clipping
-template <int K>
-__device__ __forceinline__ f3 cl_get(const Smem<K>& s, int buf, int i, int grp) {
-  return mk(s.x.clip[buf][i][0][grp], s.x.clip[buf][i][1][grp], s.x.clip[buf][i][2][grp]);
+// the clip buffers of wave wid
+template <class S>
+__device__ __forceinline__ f3 cl_get(const S& s, int wid, int buf, int i, int grp) {
+  return mk(s.x.clip[wid][buf][i][0][grp], s.x.clip[wid][buf][i][1][grp], s.x.clip[wid][buf][i][2][grp]);
 }
-template <int K>
-__device__ __forceinline__ void cl_put(Smem<K>& s, int buf, int i, int grp, f3 v) {
-  s.x.clip[buf][i][0][grp] = v.x;
-  s.x.clip[buf][i][1][grp] = v.y;
-  s.x.clip[buf][i][2][grp] = v.z;
+template <class S>
+__device__ __forceinline__ void cl_put(S& s, int wid, int buf, int i, int grp, f3 v) {
+  s.x.clip[wid][buf][i][0][grp] = v.x;
+  s.x.clip[wid][buf][i][1][grp] = v.y;
+  s.x.clip[wid][buf][i][2][grp] = v.z;
 }
 
 // Previous lane of each 8-lane group, lane 0 of a group taking lane 7: DPP
@@ -373,9 +379,9 @@ __device__ __forceinline__ float group_prev(float v, bool first) {
 // point i: it emits the crossing point if the edge crosses the plane, then
 // point i if inside, at its rank among the group's emissions; at most POLY
 // points are kept.  Called by the whole wave.
-template <int K>
-__device__ __forceinline__ int clip_group(Smem<K>& s, f3* P, int n, f3 f, f3 dir, float sign, float h, int buf,
-                                          int grp, int gl, int lane) {
+template <class S>
+__device__ __forceinline__ int clip_group(S& s, f3* P, int n, f3 f, f3 dir, float sign, float h, int buf,
+                                          int grp, int gl, int lane, int wid) {
   const float dc = sign * dot(*P - f, dir) - h;
   // no point of any group outside this plane: nothing crosses it and every
   // point is kept in place, so the stage changes nothing
@@ -392,29 +398,29 @@ __device__ __forceinline__ int clip_group(Smem<K>& s, f3* P, int n, f3 f, f3 dir
   const unsigned long long gm = 0xffull << (8 * grp), below = ((1ull << lane) - 1ull) & gm;
   const int q = __popcll(mx & below) + __popcll(mc & below);
   const int m = __popcll(mx & gm) + __popcll(mc & gm);
-  if (emit_x && q < POLY) cl_put(s, buf, q, grp, fma3(*P - Pp, dp * rcp(dp - dc), Pp));
-  if (emit_c && q + (emit_x ? 1 : 0) < POLY) cl_put(s, buf, q + (emit_x ? 1 : 0), grp, *P);
+  if (emit_x && q < POLY) cl_put(s, wid, buf, q, grp, fma3(*P - Pp, dp * rcp(dp - dc), Pp));
+  if (emit_c && q + (emit_x ? 1 : 0) < POLY) cl_put(s, wid, buf, q + (emit_x ? 1 : 0), grp, *P);
   wave_sync();
   const int nn = m < POLY ? m : POLY;
-  if (nn > 0) *P = cl_get(s, buf, gl < nn ? gl : nn - 1, grp);
+  if (nn > 0) *P = cl_get(s, wid, buf, gl < nn ? gl : nn - 1, grp);
   return nn;
 }
 
 // Axis k and half extent k of LDS body i (dynamic k reads LDS, so no
 // register array is indexed at run time).
-template <int K>
-__device__ __forceinline__ f3 lds_axis(const Smem<K>& s, int i, int k) {
+template <class S>
+__device__ __forceinline__ f3 lds_axis(const S& s, int i, int k) {
   return xyz(s.col[k][i]);
 }
-template <int K>
-__device__ __forceinline__ float lds_half(const Smem<K>& s, int i, int k) {
+template <class S>
+__device__ __forceinline__ float lds_half(const S& s, int i, int k) {
   return reinterpret_cast<const float*>(&s.half[i])[k];
 }
 
 // Edge-axis contact: closest points of the two extreme edges parallel to the
 // axis's edge directions (A extreme along +n, B along -n; sign 0 -> +).
-template <int K>
-__device__ __forceinline__ f3 edge_point(const Smem<K>& s, int ia, int ib, int idx, f3 n) {
+template <class S>
+__device__ __forceinline__ f3 edge_point(const S& s, int ia, int ib, int idx, f3 n) {
   const int i = (idx - 6) / 3, j = (idx - 6) % 3;
   f3 pa = xyz(s.pos[ia]), pb = xyz(s.pos[ib]);
 #pragma unroll
@@ -451,8 +457,8 @@ struct Contact {
   float ln, lt1, lt2;
 };
 
-template <int K>
-__device__ __forceinline__ float eff_mass_side(const Smem<K>& s, int i, f3 r, f3 d) {
+template <class S>
+__device__ __forceinline__ float eff_mass_side(const S& s, int i, f3 r, f3 d) {
   f3 cr = cross(r, d);
   float4 ia = s.iwa[i], ib = s.iwb[i];
   // symmetric Iw^-1 times cr
@@ -462,8 +468,8 @@ __device__ __forceinline__ float eff_mass_side(const Smem<K>& s, int i, f3 r, f3
   return s.half[i].w + dot(cr, m);
 }
 
-template <int K>
-__device__ __forceinline__ void prep_contact(const Smem<K>& s, int c, const Params& p, int nwarm, Contact* ct) {
+template <class S>
+__device__ __forceinline__ void prep_contact(const S& s, int c, const Params& p, int nwarm, Contact* ct) {
   float4 s0 = s.u.stage[c][0], s1 = s.u.stage[c][1];
   f3 pt = xyz(s0);
   float sep = s0.w;
@@ -615,25 +621,46 @@ __device__ __forceinline__ int philox_action(uint2 key, unsigned c0, unsigned c1
 }
 
 // ------------------------------------------------------------------ one environment
+// Orders LDS accesses across the waves of an environment's workgroup (a
+// barrier) when there is more than one, else within the wave.
+template <int W>
+__device__ __forceinline__ void sync_all() {
+  if constexpr (W > 1) __syncthreads();
+  else wave_sync();
+}
+
 // Runs env e through its pushes: one explicit push (step mode) or a list of
 // contour pushes (rollout mode, with a reward after each push).
-template <int K>
-__device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int e) {
-  constexpr int C = Smem<K>::C;
+//
+// With W > 1 waves per environment, wave 0 (the lead) runs every phase as a
+// single wave does and owns the bodies; the other waves take the contact
+// slots sl with sl % W == their index (in prep, warm start, the Jacobi
+// contact updates and the warm-start memory) and every W-th narrowphase
+// pass of eight pairs.  Each contact's arithmetic and every per-body sum
+// are those of one wave, in the same order, so the result is bitwise that
+// of W = 1.  Uniform decisions (push validity, rewards, overflow) are taken
+// by every wave from the same LDS data, so all waves run the same loops and
+// meet at the same barriers.
+template <int K, int W>
+__device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const int e) {
+  constexpr int C = Smem<K, W>::C;
+  constexpr int KW = K / W;  // contact slots per wave
+  static_assert(K % W == 0, "contact slots split evenly over the waves");
   const Params& p = g.p;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wid = W > 1 ? (int)(threadIdx.x >> 6) : 0;
+  const bool lead = wid == 0;
   const int b = lane & 31;
   const int part = lane >> 5;
   const int base = g.env_offset[e];
   const int nb = g.env_offset[e + 1] - base;
-  const bool active = b < nb;
+  const bool active = lead && b < nb;  // a lane of the lead wave that owns a body
   const int N = g.stride;
   const float dt = p.dt;
   const bool rollout = g.actions != nullptr;
   const int act0 = rollout ? g.act_offset[e] : 0;
   int n_push = rollout ? g.act_offset[e + 1] - act0 : 1;
-  const int src = ((rollout || g.valid_only) && g.src_slot) ? g.src_slot[e] : -1;
-  if (g.valid_only && g.src_slot && src < 0) return;
+  const int src = (rollout && g.src_slot) ? g.src_slot[e] : -1;
   const int PS = g.pool_stride;
 
   // ---- load (coalesced SoA): part 0 linear, part 1 angular; from the env
@@ -669,12 +696,14 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         s.pos[b] = f4(x, 0.0f);
         s.half[b] = f4(h, invm);
       } else {
-        float r00 = 1 - 2 * (q2 * q2 + q3 * q3), r01 = 2 * (q1 * q2 - q0 * q3), r02 = 2 * (q1 * q3 + q0 * q2);
-        float r10 = 2 * (q1 * q2 + q0 * q3), r11 = 1 - 2 * (q1 * q1 + q3 * q3), r12 = 2 * (q2 * q3 - q0 * q1);
-        float r20 = 2 * (q1 * q3 - q0 * q2), r21 = 2 * (q2 * q3 + q0 * q1), r22 = 1 - 2 * (q1 * q1 + q2 * q2);
-        s.col[0][b] = make_float4(r00, r10, r20, 0.0f);
-        s.col[1][b] = make_float4(r01, r11, r21, 0.0f);
-        s.col[2][b] = make_float4(r02, r12, r22, 0.0f);
+        f3 c0, c1, c2;
+        quat_cols(q0, q1, q2, q3, &c0, &c1, &c2);
+        const float r00 = c0.x, r01 = c1.x, r02 = c2.x;
+        const float r10 = c0.y, r11 = c1.y, r12 = c2.y;
+        const float r20 = c0.z, r21 = c1.z, r22 = c2.z;
+        s.col[0][b] = f4(c0, 0.0f);
+        s.col[1][b] = f4(c1, 0.0f);
+        s.col[2][b] = f4(c2, 0.0f);
         // Iw^-1 = R diag(invI) R^T
         float xx = r00 * invI.x * r00 + r01 * invI.y * r01 + r02 * invI.z * r02;
         float yy = r10 * invI.x * r10 + r11 * invI.y * r11 + r12 * invI.z * r12;
@@ -688,16 +717,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     }
   };
 
-  // validity words of the loaded state only
-  if (g.valid_only) {
-    write_body_frames();
-    wave_sync();
-    const unsigned wd = validity_word(s, nb, p, lane);
-    if (lane < PMBS_VALID_WORDS) g.valid_out[(size_t)e * PMBS_VALID_WORDS + lane] = wd;
-    return;
-  }
-
-  Contact ct[K];
+  Contact ct[KW];
   bool deferred = false;
   uint32_t status = 0u;
   float last_r = 0.0f;
@@ -712,9 +732,9 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   int t_stop = -1, n_rewards_x = 0;
   for (int job = 0; job < 2; ++job) {
   for (int t = 0; t < n_push; ++t) {
-  // ---- push begin (uniform across the wave)
+  // ---- push begin (uniform across the workgroup)
   write_body_frames();
-  wave_sync();
+  sync_all<W>();
   bool have_push;
   float4 push = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   if (rollout) {
@@ -753,7 +773,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
 
   // the pusher entry (index nb)
   auto write_pusher = [&](f3 vp) {
-    if (lane == 32) {
+    if (lead && lane == 32) {
       s.pos[nb] = f4(xp, 0.0f);
       s.col[0][nb] = f4(pc0, 0.0f);
       s.col[1][nb] = f4(pc1, 0.0f);
@@ -775,7 +795,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   bool valid = false;
   if (have_push) {
     bool bad = false;
-    if (active && part == 0) {
+    if (b < nb && part == 0) {   // every wave tests the boxes from LDS: the same decision
       PusherPose pq;
       pq.x = xp;
       pq.c0 = pc0;
@@ -795,7 +815,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     // a discarded expansion push ends the rollout; a discarded random push
     // leaves the state and repeats the previous reward
     if (t == 0) break;
-    if (lane == 0) (job ? g.x_rewards : g.rewards)[(size_t)e * g.max_h + t] = last_r;
+    if (lead && lane == 0) (job ? g.x_rewards : g.rewards)[(size_t)e * g.max_h + t] = last_r;
     if (job == 0) n_rewards = t + 1;
     else n_rewards_x = t + 1;
     continue;
@@ -816,161 +836,174 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     write_frames(vp);
     wave_sync();
 
-    // ---- 3. broadphase: AABBs, rank sort on min-x, sweep
-    if (lane < n_obj) {
-      f3 c = xyz(s.pos[lane]);
-      f3 a0 = xyz(s.col[0][lane]), a1 = xyz(s.col[1][lane]), a2 = xyz(s.col[2][lane]);
-      f3 hh = xyz(s.half[lane]);
-      float ex = fabsf(a0.x) * hh.x + fabsf(a1.x) * hh.y + fabsf(a2.x) * hh.z + p.margin;
-      float ey = fabsf(a0.y) * hh.x + fabsf(a1.y) * hh.y + fabsf(a2.y) * hh.z + p.margin;
-      float ez = fabsf(a0.z) * hh.x + fabsf(a1.z) * hh.y + fabsf(a2.z) * hh.z + p.margin;
-      s.lo[0][lane] = c.x - ex; s.hi[0][lane] = c.x + ex;
-      s.lo[1][lane] = c.y - ey; s.hi[1][lane] = c.y + ey;
-      s.lo[2][lane] = c.z - ez; s.hi[2][lane] = c.z + ez;
-      s.mask[lane] = 0u;
-    }
-    wave_sync();
-    // the previous substep's order is still the order when every object
-    // precedes the next one by (key, index); then the ranks need no update
-    bool order_ok = order_kept;
-    if (order_ok) {
-      const bool in = lane < n_obj;
-      const int o = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
-      float kx = in ? s.lo[0][o] : INFINITY;
-      kx = kx == kx ? kx : INFINITY;
-      const float kn = wave_next(kx);
-      const int on = wave_next(o);
-      const bool bad = lane + 1 < n_obj && !(kx < kn || (kx == kn && o < on));
-      order_ok = __ballot(bad) == 0ull;
-    }
-    order_kept = true;
-    if (!order_ok) {
-      // rank of each object's min-x key (ties by index; NaN keys sort last,
-      // so the ranks stay a permutation whatever the state holds)
-      float key = lane < n_obj ? s.lo[0][lane] : INFINITY;
-      key = key == key ? key : INFINITY;
-      // lanes past n_obj hold +inf keys and never count, so the loop runs
-      // over fixed lanes (independent readlanes, two counters) with no guard
-      const int ikey = __float_as_int(key);
-      int r0 = 0, r1 = 0;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
-        const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
-        if (j & 1) r1 += c;
-        else r0 += c;
+    // ---- 3.-4a. broadphase and table contacts: the lead wave only
+    int n_pairs = 0, nc_raw = 0;
+    if (lead) {
+      // ---- 3. broadphase: AABBs, rank sort on min-x, sweep
+      if (lane < n_obj) {
+        f3 c = xyz(s.pos[lane]);
+        f3 a0 = xyz(s.col[0][lane]), a1 = xyz(s.col[1][lane]), a2 = xyz(s.col[2][lane]);
+        f3 hh = xyz(s.half[lane]);
+        float ex = fabsf(a0.x) * hh.x + fabsf(a1.x) * hh.y + fabsf(a2.x) * hh.z + p.margin;
+        float ey = fabsf(a0.y) * hh.x + fabsf(a1.y) * hh.y + fabsf(a2.y) * hh.z + p.margin;
+        float ez = fabsf(a0.z) * hh.x + fabsf(a1.z) * hh.y + fabsf(a2.z) * hh.z + p.margin;
+        s.lo[0][lane] = c.x - ex; s.hi[0][lane] = c.x + ex;
+        s.lo[1][lane] = c.y - ey; s.hi[1][lane] = c.y + ey;
+        s.lo[2][lane] = c.z - ez; s.hi[2][lane] = c.z + ez;
+        s.mask[lane] = 0u;
       }
-      if (n_obj > 16) {
-#pragma unroll
-        for (int j = 16; j < 32; ++j) {
+      wave_sync();
+      // the previous substep's order is still the order when every object
+      // precedes the next one by (key, index); then the ranks need no update
+      bool order_ok = order_kept;
+      if (order_ok) {
+        const bool in = lane < n_obj;
+        const int o = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
+        float kx = in ? s.lo[0][o] : INFINITY;
+        kx = kx == kx ? kx : INFINITY;
+        const float kn = wave_next(kx);
+        const int on = wave_next(o);
+        const bool bad = lane + 1 < n_obj && !(kx < kn || (kx == kn && o < on));
+        order_ok = __ballot(bad) == 0ull;
+      }
+      order_kept = true;
+      if (!order_ok) {
+        // rank of each object's min-x key (ties by index; NaN keys sort last,
+        // so the ranks stay a permutation whatever the state holds)
+        float key = lane < n_obj ? s.lo[0][lane] : INFINITY;
+        key = key == key ? key : INFINITY;
+        // lanes past n_obj hold +inf keys and never count, so the loop runs
+        // over fixed lanes (independent readlanes, two counters) with no guard
+        const int ikey = __float_as_int(key);
+        int r0 = 0, r1 = 0;
+  #pragma unroll
+        for (int j = 0; j < 16; ++j) {
           const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
           const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
           if (j & 1) r1 += c;
           else r0 += c;
         }
-      }
-      const int rank = r0 + r1;
-      if (lane < n_obj) s.sorted[rank] = lane;
-    }
-    wave_sync();
-    {
-      // sweep: lane r holds the box at sorted position r and compares it with
-      // the boxes d = 1, 2, ... positions later until every lane has passed
-      // its box's max-x; the later boxes' bounds move down one lane per step
-      // (DPP whole-wave shift, no LDS round trip)
-      const bool in = lane < n_obj;
-      const int oi = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
-      const float lox = in ? s.lo[0][oi] : INFINITY, hix = in ? s.hi[0][oi] : -INFINITY;
-      const float loy = in ? s.lo[1][oi] : 0.0f, hiy = in ? s.hi[1][oi] : 0.0f;
-      const float loz = in ? s.lo[2][oi] : 0.0f, hiz = in ? s.hi[2][oi] : 0.0f;
-      float lox_q = lox, loy_q = loy, hiy_q = hiy, loz_q = loz, hiz_q = hiz;
-      int oj = oi;
-      // two steps per trip: sorted min-x makes a lane that fails at step d
-      // fail at every later step, so a trip whose second step has no lane
-      // left ends the sweep
-      for (int d = 1; d < n_obj; d += 2) {
-        bool more = false;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          lox_q = wave_next(lox_q);
-          loy_q = wave_next(loy_q);
-          hiy_q = wave_next(hiy_q);
-          loz_q = wave_next(loz_q);
-          hiz_q = wave_next(hiz_q);
-          oj = wave_next(oj);
-          const bool go = lane + d + h < n_obj && lox_q <= hix;
-          if (go && loy <= hiy_q && loy_q <= hiy && loz <= hiz_q && loz_q <= hiz) {
-            const int lo_i = oi < oj ? oi : oj, hi_i = oi < oj ? oj : oi;
-            atomicOr(&s.mask[lo_i], 1u << hi_i);
+        if (n_obj > 16) {
+  #pragma unroll
+          for (int j = 16; j < 32; ++j) {
+            const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
+            const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
+            if (j & 1) r1 += c;
+            else r0 += c;
           }
-          if (h == 1) more = __ballot(go) != 0ull;
         }
-        if (!more) break;
+        const int rank = r0 + r1;
+        if (lane < n_obj) s.sorted[rank] = lane;
       }
-    }
-    wave_sync();
-    int n_pairs;
-    {
-      unsigned m = lane < n_obj ? s.mask[lane] : 0u;
-      int off = wave_excl_scan(__popc(m), &n_pairs);
-      int t = 0;
-      while (m) {
-        int j = __builtin_ctz(m);
-        m &= m - 1;
-        if (off + t < MAX_PAIRS) s.pairs[off + t] = (unsigned short)((lane << 8) | j);
-        ++t;
+      wave_sync();
+      {
+        // sweep: lane r holds the box at sorted position r and compares it with
+        // the boxes d = 1, 2, ... positions later until every lane has passed
+        // its box's max-x; the later boxes' bounds move down one lane per step
+        // (DPP whole-wave shift, no LDS round trip)
+        const bool in = lane < n_obj;
+        const int oi = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
+        const float lox = in ? s.lo[0][oi] : INFINITY, hix = in ? s.hi[0][oi] : -INFINITY;
+        const float loy = in ? s.lo[1][oi] : 0.0f, hiy = in ? s.hi[1][oi] : 0.0f;
+        const float loz = in ? s.lo[2][oi] : 0.0f, hiz = in ? s.hi[2][oi] : 0.0f;
+        float lox_q = lox, loy_q = loy, hiy_q = hiy, loz_q = loz, hiz_q = hiz;
+        int oj = oi;
+        // two steps per trip: sorted min-x makes a lane that fails at step d
+        // fail at every later step, so a trip whose second step has no lane
+        // left ends the sweep
+        for (int d = 1; d < n_obj; d += 2) {
+          bool more = false;
+  #pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            lox_q = wave_next(lox_q);
+            loy_q = wave_next(loy_q);
+            hiy_q = wave_next(hiy_q);
+            loz_q = wave_next(loz_q);
+            hiz_q = wave_next(hiz_q);
+            oj = wave_next(oj);
+            const bool go = lane + d + h < n_obj && lox_q <= hix;
+            if (go && loy <= hiy_q && loy_q <= hiy && loz <= hiz_q && loz_q <= hiz) {
+              const int lo_i = oi < oj ? oi : oj, hi_i = oi < oj ? oj : oi;
+              atomicOr(&s.mask[lo_i], 1u << hi_i);
+            }
+            if (h == 1) more = __ballot(go) != 0ull;
+          }
+          if (!more) break;
+        }
       }
-    }
-    wave_sync();
+      wave_sync();
+      {
+        unsigned m = lane < n_obj ? s.mask[lane] : 0u;
+        int off = wave_excl_scan(__popc(m), &n_pairs);
+        int t = 0;
+        while (m) {
+          int j = __builtin_ctz(m);
+          m &= m - 1;
+          if (off + t < MAX_PAIRS) s.pairs[off + t] = (unsigned short)((lane << 8) | j);
+          ++t;
+        }
+      }
+      wave_sync();
 
-    // ---- 4a. box-plane contacts (body order, vertex order).  Corner kk
-    // of body b is tested by lane b when kk has an even number of set bits
-    // and by lane b + 32 otherwise, so every face's four corners split two
-    // and two; the body's two flag bytes give each corner its rank.
-    int nc_raw;
-    {
-      f3 c0 = mk(0, 0, 0), a0 = mk(0, 0, 0), a1 = mk(0, 0, 0), a2 = mk(0, 0, 0);
-      unsigned flags = 0;
-      if (active) {
-        c0 = xyz(s.pos[b]);
-        a0 = xyz(s.col[0][b]); a1 = xyz(s.col[1][b]); a2 = xyz(s.col[2][b]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          // the j-th corner of this lane's parity class: 0, 3, 5, 6 or 1, 2, 4, 7
-          const int kk = part == 0 ? (0x6530 >> (4 * j)) & 15 : (0x7421 >> (4 * j)) & 15;
-          const float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
-          const float vz = c0.z + (a0.z * sx + a1.z * sy + a2.z * sz);
-          if (vz <= p.margin) flags |= 1u << kk;
+      // ---- 4a. box-plane contacts (body order, vertex order).  Corner kk
+      // of body b is tested by lane b when kk has an even number of set bits
+      // and by lane b + 32 otherwise, so every face's four corners split two
+      // and two; the body's two flag bytes give each corner its rank.
+      {
+        f3 c0 = mk(0, 0, 0), a0 = mk(0, 0, 0), a1 = mk(0, 0, 0), a2 = mk(0, 0, 0);
+        unsigned flags = 0;
+        if (active) {
+          c0 = xyz(s.pos[b]);
+          a0 = xyz(s.col[0][b]); a1 = xyz(s.col[1][b]); a2 = xyz(s.col[2][b]);
+  #pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            // the j-th corner of this lane's parity class: 0, 3, 5, 6 or 1, 2, 4, 7
+            const int kk = part == 0 ? (0x6530 >> (4 * j)) & 15 : (0x7421 >> (4 * j)) & 15;
+            const float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
+            const float vz = c0.z + (a0.z * sx + a1.z * sy + a2.z * sz);
+            if (vz <= p.margin) flags |= 1u << kk;
+          }
         }
-      }
-      const unsigned both = (unsigned)(lower_half((int)flags) | upper_half((int)flags));
-      int total;
-      const int off0 = wave_excl_scan(part == 0 ? __popc(both) : 0, &total);
-      const int off = lower_half(off0);
-      while (flags) {
-        const int kk = __builtin_ctz(flags);
-        flags &= flags - 1;
-        float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
-        f3 vtx = c0 + mk(a0.x * sx + a1.x * sy + a2.x * sz, a0.y * sx + a1.y * sy + a2.y * sz,
-                         a0.z * sx + a1.z * sy + a2.z * sz);
-        const int c = off + __popc(both & ((1u << kk) - 1u));
-        if (c < C) {
-          s.u.stage[c][0] = f4(vtx - mk(0, 0, 0.5f * vtx.z), vtx.z);
-          s.u.stage[c][1] = make_float4(0, 0, 1, 0);
-          s.cab[c] = PLANE | (b << 8) | (kk << 16);
+        const unsigned both = (unsigned)(lower_half((int)flags) | upper_half((int)flags));
+        int total;
+        const int off0 = wave_excl_scan(part == 0 ? __popc(both) : 0, &total);
+        const int off = lower_half(off0);
+        while (flags) {
+          const int kk = __builtin_ctz(flags);
+          flags &= flags - 1;
+          float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
+          f3 vtx = c0 + mk(a0.x * sx + a1.x * sy + a2.x * sz, a0.y * sx + a1.y * sy + a2.y * sz,
+                           a0.z * sx + a1.z * sy + a2.z * sz);
+          const int c = off + __popc(both & ((1u << kk) - 1u));
+          if (c < C) {
+            s.u.stage[c][0] = f4(vtx - mk(0, 0, 0.5f * vtx.z), vtx.z);
+            s.u.stage[c][1] = make_float4(0, 0, 1, 0);
+            s.cab[c] = PLANE | (b << 8) | (kk << 16);
+          }
         }
+        nc_raw = total;
       }
-      nc_raw = total;
+    }
+    if constexpr (W > 1) {
+      // every wave needs the pair list, the frames and the table contacts
+      if (lead && lane == 0) {
+        s.sh_pairs = n_pairs;
+        s.sh_plane = nc_raw;
+      }
+      __syncthreads();
+      n_pairs = s.sh_pairs;
+      nc_raw = s.sh_plane;
     }
 
     // ---- 4b. box-box and pusher-box contacts, pairs in lexicographic order.
     // Eight pairs per pass, one 8-lane group each: lane k of a group
     // evaluates candidate axes k and k + 8, the group scans the candidates in
     // order (row broadcasts), and the incident face is clipped with one
-    // polygon point per lane.
-    for (int r0 = 0; r0 < n_pairs; r0 += 8) {
+    // polygon point per lane.  With W waves a round is W passes, wave w
+    // taking pairs r0 + 8 w ..; the round's contacts keep the pass order.
+    for (int r0 = 0; r0 < n_pairs; r0 += 8 * W) {
       const int grp = lane >> 3, gl = lane & 7;
-      const int pi = r0 + grp;
+      const int pi = r0 + 8 * wid + grp;
       const bool has = pi < n_pairs && pi < MAX_PAIRS;
       int ia = 0, ib = 1;
       if (has) {
@@ -1063,16 +1096,30 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         P = sel(gl == 0, fc + (ep + eq), sel(gl == 1, fc + (eq - ep), sel(gl == 2, fc - (ep + eq), fc + (ep - eq))));
         np = 4;
       }
-      np = clip_group(s, &P, np, fref, u, 1.0f, hu, 0, grp, gl, lane);
-      np = clip_group(s, &P, np, fref, u, -1.0f, hu, 1, grp, gl, lane);
-      np = clip_group(s, &P, np, fref, w, 1.0f, hw, 0, grp, gl, lane);
-      np = clip_group(s, &P, np, fref, w, -1.0f, hw, 1, grp, gl, lane);
+      np = clip_group(s, &P, np, fref, u, 1.0f, hu, 0, grp, gl, lane, wid);
+      np = clip_group(s, &P, np, fref, u, -1.0f, hu, 1, grp, gl, lane, wid);
+      np = clip_group(s, &P, np, fref, w, 1.0f, hw, 0, grp, gl, lane, wid);
+      np = clip_group(s, &P, np, fref, w, -1.0f, hw, 1, grp, gl, lane, wid);
       // contacts: kept polygon points (face) or one edge-edge point
       const float psep = dot(nref, P - fref);
       const bool keep = face ? (gl < np && psep <= p.margin) : (best >= 6 && gl == 0);
       const unsigned long long km = __ballot(keep);
       const unsigned long long below = (1ull << lane) - 1ull;
-      const int off = nc_raw + __popcll(km & below);
+      int before = 0, round_total = __popcll(km);
+      if constexpr (W > 1) {
+        // kept contacts of every wave's pass: the earlier passes come first
+        const int par = (r0 / (8 * W)) & 1;
+        if (lane == 0) s.rcount[par][wid] = round_total;
+        __syncthreads();
+        round_total = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < W; ++w2) {
+          const int m = s.rcount[par][w2];
+          before += w2 < wid ? m : 0;
+          round_total += m;
+        }
+      }
+      const int off = nc_raw + before + __popcll(km & below);
       if (keep && off < C) {
         const int ab = ia | (ib << 8);
         if (face) {
@@ -1085,7 +1132,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
           s.cab[off] = ab;
         }
       }
-      nc_raw += __popcll(km);
+      nc_raw += round_total;
     }
     if (nc_raw > C) {
       status |= PMBS_ENV_CONTACT_OVERFLOW;
@@ -1099,12 +1146,12 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     stat_nc += nc;
     stat_pairs += n_pairs;
     stat_sub += 1;
-    wave_sync();
+    sync_all<W>();   // every wave's contacts are in the staging array
 
     if (g.collide_only) {
-      if (lane == 0) g.dbg_count[e] = nc;
+      if (lead && lane == 0) g.dbg_count[e] = nc;
       float* out = g.dbg_contacts + (size_t)e * C * 9;
-      for (int c = lane; c < nc; c += 64) {
+      for (int c = lane; lead && c < nc; c += 64) {
         float4 s0 = s.u.stage[c][0], s1 = s.u.stage[c][1];
         int ab = s.cab[c];
         int a = ab & 255, bb = (ab >> 8) & 255;
@@ -1114,7 +1161,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         out[c * 9 + 5] = s1.x; out[c * 9 + 6] = s1.y; out[c * 9 + 7] = s1.z;
         out[c * 9 + 8] = s0.w;
       }
-      if (lane == 0) g.env_status[e] = status;
+      if (lead && lane == 0) g.env_status[e] = status;
       return;
     }
 
@@ -1128,76 +1175,79 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     // A contact list equal to the previous substep's (same count, same keys
     // in the same order, within one push) has the same incidence lists,
     // counts and list ranges, which are all still in place: keep them.
-    bool same_list = nc > 0 && nc == nwarm;
-    if (same_list) {
-      bool diff = false;
-#pragma unroll
-      for (int sl = 0; sl < K; ++sl) {
-        const int c = 64 * sl + lane;
-        if (c < nc) diff = diff || contact_key(s.cab[c]) != s.wkey[c];
+    // the lead wave keeps or rebuilds the lists over every contact slot
+    if (lead) {
+      bool same_list = nc > 0 && nc == nwarm;
+      if (same_list) {
+        bool diff = false;
+  #pragma unroll
+        for (int sl = 0; sl < K; ++sl) {
+          const int c = 64 * sl + lane;
+          if (c < nc) diff = diff || contact_key(s.cab[c]) != s.wkey[c];
+        }
+        same_list = __ballot(diff) == 0ull;
       }
-      same_list = __ballot(diff) == 0ull;
-    }
-    if (!same_list) {
-      constexpr int W = 2 * K;  // mask words per body: slot sl, lane half
-      for (int t = lane; t < NOBJ * W; t += 64) (&s.x.incm[0][0])[t] = 0u;
-      wave_sync();
-      int ca[K], cb[K];
-      const unsigned bit = 1u << (lane & 31);
-#pragma unroll
-      for (int sl = 0; sl < K; ++sl) {
-        const int c = 64 * sl + lane;
-        const int ab = c < nc ? s.cab[c] : -1;
-        ca[sl] = c < nc && (ab & 255) < nb ? (ab & 255) : -1;
-        cb[sl] = c < nc && ((ab >> 8) & 255) < nb ? ((ab >> 8) & 255) : -1;
-        const int w = 2 * sl + (lane >> 5);
-        if (ca[sl] >= 0) atomicOr(&s.x.incm[ca[sl]][w], bit);
-        if (cb[sl] >= 0) atomicOr(&s.x.incm[cb[sl]][w], bit);
-      }
-      wave_sync();
-      int cn = 0;
-      if (active) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) cn += __popc(s.x.incm[b][w]);
-      }
-      int tot;
-      const int padded = (cn + 3) & ~3;
-      int st0 = wave_excl_scan(part == 0 ? padded : 0, &tot);
-      inc_start = lower_half(st0);
-      inc_count = cn;
-      if (active && part == 0) {
-        s.cnt[b] = cn;
-        s.lstart[b] = inc_start;
-      }
-      if (active) {
-        for (int t = cn; t < padded; ++t) s.inc[part][inc_start + t] = (unsigned short)zcode;
-      }
-      wave_sync();
-#pragma unroll
-      for (int sl = 0; sl < K; ++sl) {
-        const int c = 64 * sl + lane;
-        const int w = 2 * sl + (lane >> 5);
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          const int j = side ? cb[sl] : ca[sl];
-          if (j >= 0) {
-            int r = s.lstart[j] + __popc(s.x.incm[j][w] & (bit - 1u));
-#pragma unroll
-            for (int w2 = 0; w2 < W; ++w2)
-              if (w2 < w) r += __popc(s.x.incm[j][w2]);
-            s.inc[0][r] = (unsigned short)(((unsigned)c * 16u) | side);
-            s.inc[1][r] = (unsigned short)((((1u + side) * (unsigned)C + c) * 16u) | side);
+      if (!same_list) {
+        constexpr int MW = 2 * K;  // mask words per body: slot sl, lane half
+        for (int t = lane; t < NOBJ * MW; t += 64) (&s.x.incm[0][0])[t] = 0u;
+        wave_sync();
+        int ca[K], cb[K];
+        const unsigned bit = 1u << (lane & 31);
+  #pragma unroll
+        for (int sl = 0; sl < K; ++sl) {
+          const int c = 64 * sl + lane;
+          const int ab = c < nc ? s.cab[c] : -1;
+          ca[sl] = c < nc && (ab & 255) < nb ? (ab & 255) : -1;
+          cb[sl] = c < nc && ((ab >> 8) & 255) < nb ? ((ab >> 8) & 255) : -1;
+          const int w = 2 * sl + (lane >> 5);
+          if (ca[sl] >= 0) atomicOr(&s.x.incm[ca[sl]][w], bit);
+          if (cb[sl] >= 0) atomicOr(&s.x.incm[cb[sl]][w], bit);
+        }
+        wave_sync();
+        int cn = 0;
+        if (active) {
+  #pragma unroll
+          for (int w = 0; w < MW; ++w) cn += __popc(s.x.incm[b][w]);
+        }
+        int tot;
+        const int padded = (cn + 3) & ~3;
+        int st0 = wave_excl_scan(part == 0 ? padded : 0, &tot);
+        inc_start = lower_half(st0);
+        inc_count = cn;
+        if (active && part == 0) {
+          s.cnt[b] = cn;
+          s.lstart[b] = inc_start;
+        }
+        if (active) {
+          for (int t = cn; t < padded; ++t) s.inc[part][inc_start + t] = (unsigned short)zcode;
+        }
+        wave_sync();
+  #pragma unroll
+        for (int sl = 0; sl < K; ++sl) {
+          const int c = 64 * sl + lane;
+          const int w = 2 * sl + (lane >> 5);
+  #pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int j = side ? cb[sl] : ca[sl];
+            if (j >= 0) {
+              int r = s.lstart[j] + __popc(s.x.incm[j][w] & (bit - 1u));
+  #pragma unroll
+              for (int w2 = 0; w2 < MW; ++w2)
+                if (w2 < w) r += __popc(s.x.incm[j][w2]);
+              s.inc[0][r] = (unsigned short)(((unsigned)c * 16u) | side);
+              s.inc[1][r] = (unsigned short)((((1u + side) * (unsigned)C + c) * 16u) | side);
+            }
           }
         }
       }
     }
-    wave_sync();
+    sync_all<W>();   // counts and lists before any wave's prep
 
-    // ---- 6. contact prep into VGPR slots
+    // ---- 6. contact prep into VGPR slots (slot sl on wave sl % W)
 #pragma unroll
-    for (int sl = 0; sl < K; ++sl) {
-      const int c = 64 * sl + lane;
-      if (c < nc) prep_contact(s, c, p, nwarm, &ct[sl]);
+    for (int ls = 0; ls < KW; ++ls) {
+      const int c = 64 * (ls * W + wid) + lane;
+      if (c < nc) prep_contact(s, c, p, nwarm, &ct[ls]);
     }
 
     // ---- 7. projected Jacobi, I iterations
@@ -1265,29 +1315,30 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
               fmaf(mo.x, acc.x, fmaf(md.y, acc.y, fmaf(mo.z, acc.z, vw.y))),
               fmaf(mo.y, acc.x, fmaf(mo.z, acc.y, fmaf(md.z, acc.z, vw.z))));
     };
-    // warm start: the impulses carried over from the previous substep
-    wave_sync();
+    // warm start: the impulses carried over from the previous substep (the
+    // impulse rows share LDS with the staging array every prep has read)
+    sync_all<W>();
 #pragma unroll
-    for (int sl = 0; sl < K; ++sl) {
-      const int c = 64 * sl + lane;
+    for (int ls = 0; ls < KW; ++ls) {
+      const int c = 64 * (ls * W + wid) + lane;
       if (c < nc) {
-        const Contact& q = ct[sl];
+        const Contact& q = ct[ls];
         const f3 P = fma3(q.n, q.ln, fma3(q.t1, q.lt1, q.t2 * q.lt2));
         st3(&s.u.imp[0][c], P);
         st3(&s.u.imp[1][c], cross(q.ra, P));
         st3(&s.u.imp[2][c], cross(q.rb, P));
       }
     }
-    wave_sync();
+    sync_all<W>();
     apply_sums();
     for (int it = 0; it < p.iters; ++it) {
       if (active) st3(vw_slot, vw);
-      wave_sync();
+      sync_all<W>();   // the iteration-start velocities, and every wave done with the rows
 #pragma unroll
-      for (int sl = 0; sl < K; ++sl) {
-        const int c = 64 * sl + lane;
+      for (int ls = 0; ls < KW; ++ls) {
+        const int c = 64 * (ls * W + wid) + lane;
         if (c < nc) {
-          Contact& q = ct[sl];
+          Contact& q = ct[ls];
           const f3 t2 = q.t2;
           const int a = q.ab & 255, bb = (q.ab >> 8) & 255;
           f3 va = xyz(s.vel[a]), wa = xyz(s.ang[a]), vb = xyz(s.vel[bb]), wb = xyz(s.ang[bb]);
@@ -1312,20 +1363,20 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
           st3(&s.u.imp[2][c], cross(q.rb, P));
         }
       }
-      wave_sync();
+      sync_all<W>();   // every wave's impulse rows
       apply_sums();
     }
     if (part == 0) v = vw;
     else w = vw;
     // remember this substep's accumulated impulses by key
 #pragma unroll
-    for (int sl = 0; sl < K; ++sl) {
-      const int c = 64 * sl + lane;
+    for (int ls = 0; ls < KW; ++ls) {
+      const int c = 64 * (ls * W + wid) + lane;
       if (c < nc) {
-        s.wkey[c] = contact_key(ct[sl].ab);
-        s.wl[0][c] = ct[sl].ln;
-        s.wl[1][c] = ct[sl].lt1;
-        s.wl[2][c] = ct[sl].lt2;
+        s.wkey[c] = contact_key(ct[ls].ab);
+        s.wl[0][c] = ct[ls].ln;
+        s.wl[1][c] = ct[ls].lt1;
+        s.wl[2][c] = ct[ls].lt2;
       }
     }
     nwarm = nc;
@@ -1351,14 +1402,18 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   if (deferred) break;
 
   if (rollout) {
-    // ---- reward after the push: clearance of the target's footprint
+    // ---- reward after the push: clearance of the target's footprint, by
+    // every wave from the frames in LDS (the same stopping decision)
     write_body_frames();
-    wave_sync();
+    sync_all<W>();
     const int tg = g.target[e];
     float d = INFINITY;
-    if (active && part == 0 && b != tg && tg >= 0 && tg < nb) {
+    if (b < nb && part == 0 && b != tg && tg >= 0 && tg < nb) {
       const Foot T = foot_of(xyz(s.pos[tg]), xyz(s.col[0][tg]), xyz(s.col[1][tg]), xyz(s.col[2][tg]), xyz(s.half[tg]));
-      const Foot J = foot_of(x, xyz(s.col[0][b]), xyz(s.col[1][b]), xyz(s.col[2][b]), h);
+      // the lead wave's registers hold this body's centre and half extents,
+      // the LDS frames the same values for the other waves
+      const Foot J = W == 1 ? foot_of(x, xyz(s.col[0][b]), xyz(s.col[1][b]), xyz(s.col[2][b]), h)
+                            : foot_of(xyz(s.pos[b]), xyz(s.col[0][b]), xyz(s.col[1][b]), xyz(s.col[2][b]), xyz(s.half[b]));
       d = foot_distance(T, J);
     }
     for (int o = 32; o > 0; o >>= 1) d = fminf(d, __shfl_xor(d, o, 64));
@@ -1366,14 +1421,9 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
     last_r = r;
     if (job == 0) n_rewards = t + 1;
     else n_rewards_x = t + 1;
-    if (lane == 0) (job ? g.x_rewards : g.rewards)[(size_t)e * g.max_h + t] = r;
+    if (lead && lane == 0) (job ? g.x_rewards : g.rewards)[(size_t)e * g.max_h + t] = r;
     // the expanded child's state goes to its pool slot
     const int cs = (t == 0 && job == 0 && g.child_slot) ? g.child_slot[e] : -1;
-    // the child's sampled pushes that can start (its frames are in LDS)
-    if (cs >= 0 && g.valid_out) {
-      const unsigned wd = validity_word(s, nb, p, lane);
-      if (lane < PMBS_VALID_WORDS) g.valid_out[(size_t)e * PMBS_VALID_WORDS + lane] = wd;
-    }
     if (cs >= 0 && active) {
       float* dst = g.pool + (size_t)cs * 13 * PS + opaque(b);
       if (part == 0) {
@@ -1384,7 +1434,7 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
         dst[10 * PS] = w.x; dst[11 * PS] = w.y; dst[12 * PS] = w.z;
       }
     }
-    wave_sync();
+    sync_all<W>();   // every wave has read the frames before they change
     if (r >= 1.0f) {
       if (job == 0) t_stop = t;
       break;
@@ -1410,9 +1460,11 @@ __device__ __forceinline__ void run_env(Smem<K>& s, const StepArgs& g, const int
   }  // jobs
 
   if (deferred) {
-    if (lane == 0) g.overflow_list[atomicAdd(g.overflow_count, 1)] = e;
+    if (lead && lane == 0) g.overflow_list[atomicAdd(g.overflow_count, 1)] = e;
     return;
   }
+  // outputs: the lead wave's
+  if (!lead) return;
   if (rollout && lane == 0 && g.reward_count) g.reward_count[e] = n_rewards;
   if (rollout && lane == 0 && g.x_count) g.x_count[e] = n_rewards_x;
   if (rollout && !g.write_state) {
@@ -1473,8 +1525,8 @@ __device__ __forceinline__ int xcd_item(int bid, int n) {
 // work items to environments (longest horizon first for uneven rollouts).
 // The table's LDS entries: the same for every env, and no phase writes
 // them, so a workgroup sets them once.
-template <int K>
-__device__ __forceinline__ void init_plane(Smem<K>& s, const Params& p) {
+template <class S>
+__device__ __forceinline__ void init_plane(S& s, const Params& p) {
   if (threadIdx.x == 0) {
     s.pos[PLANE] = make_float4(0, 0, 0, 0);
     s.col[0][PLANE] = make_float4(1, 0, 0, 0);
@@ -1490,9 +1542,9 @@ __device__ __forceinline__ void init_plane(Smem<K>& s, const Params& p) {
   }
 }
 
-template <int K>
-__global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
-  __shared__ Smem<K> s;
+template <int K, int W>
+__global__ __launch_bounds__(64 * W, 2) void step_kernel(StepArgs g) {
+  __shared__ Smem<K, W> s;
   __shared__ int next;
   init_plane(s, g.p);
   const int n_work = g.work_count ? *g.work_count : g.n_envs;
@@ -1505,7 +1557,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs g) {
       __syncthreads();
     }
     if (wi >= n_work) break;
-    run_env<K>(s, g, g.order ? g.order[wi] : wi);   // the only call site: one inlined copy
+    run_env<K, W>(s, g, g.order ? g.order[wi] : wi);   // the only call site: one inlined copy
     if (!g.queue) break;
     __syncthreads();
   }
@@ -1576,30 +1628,80 @@ __global__ __launch_bounds__(64) void reward_kernel(RewardArgs g) {
   }
 }
 
+// ------------------------------------------------------------------ start-pose validity
+// Frames of one environment's boxes, as the step kernel holds them in LDS.
+struct Frames {
+  float4 pos[MAXB];
+  float4 col[3][MAXB];
+  float4 half[MAXB];
+};
+
+// One wave per environment: the boxes' frames from the env state (or pool
+// slot src_slot[e]; < 0 skips the env) computed as the step kernel computes
+// them, then the validity words of every contour push by the step kernel's
+// own start-pose test.  Workgroups loop over the envs (the count may come
+// from device memory).
+__global__ __launch_bounds__(64) void valid_kernel(ValidArgs g) {
+  __shared__ Frames s;
+  const int n = g.count ? g.count[0] + g.count[1] : g.n_envs;
+  const int lane = threadIdx.x;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const int src = g.src_slot ? g.src_slot[e] : -1;
+    if (g.src_slot && src < 0) continue;
+    const int base = g.env_offset[e];
+    const int nb = g.env_offset[e + 1] - base;
+    if (lane < nb) {
+      const float* st = src >= 0 ? g.pool + (size_t)src * 13 * g.pool_stride : g.state;
+      const int SN = src >= 0 ? g.pool_stride : g.stride;
+      const int si = src >= 0 ? lane : base + lane;
+      const int BN = g.bc_base ? g.bc_stride : g.stride;
+      const int bi = g.bc_base ? g.bc_base[e] + lane : base + lane;
+      f3 c0, c1, c2;
+      quat_cols(st[3 * SN + si], st[4 * SN + si], st[5 * SN + si], st[6 * SN + si], &c0, &c1, &c2);
+      s.pos[lane] = make_float4(st[0 * SN + si], st[1 * SN + si], st[2 * SN + si], 0.0f);
+      s.col[0][lane] = f4(c0, 0.0f);
+      s.col[1][lane] = f4(c1, 0.0f);
+      s.col[2][lane] = f4(c2, 0.0f);
+      s.half[lane] = make_float4(g.bconst[0 * BN + bi], g.bconst[1 * BN + bi], g.bconst[2 * BN + bi], 0.0f);
+    }
+    wave_sync();
+    const unsigned wd = validity_word(s, nb, g.p, lane);
+    if (lane < PMBS_VALID_WORDS) g.out[(size_t)e * PMBS_VALID_WORDS + lane] = wd;
+    wave_sync();   // the frames are read before the next env's overwrite them
+  }
+}
+
 // ------------------------------------------------------------------ launchers
-hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream) {
-  const int n = a.n_envs - a.env_base;
-  if (n <= 0) return hipSuccess;
+hipError_t launch_valid(const ValidArgs& a, hipStream_t stream, int grid) {
+  const int g = grid > 0 ? grid : a.n_envs;
+  if (g <= 0) return hipSuccess;
+  hipLaunchKernelGGL(valid_kernel, dim3(g), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
+
+// The kernel of a contact class (128, 256 or 512 contacts: 2, 4 or 8 VGPR
+// slots per lane) and workgroup shape (1 or 2 waves per environment).
+template <int W>
+static hipError_t launch_class(const StepArgs& a, int max_contacts, hipStream_t stream, int grid) {
   if (max_contacts <= 128) {
-    hipLaunchKernelGGL(step_kernel<2>, dim3(n), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL((step_kernel<2, W>), dim3(grid), dim3(64 * W), 0, stream, a);
   } else if (max_contacts <= 256) {
-    hipLaunchKernelGGL(step_kernel<4>, dim3(n), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL((step_kernel<4, W>), dim3(grid), dim3(64 * W), 0, stream, a);
   } else {
-    hipLaunchKernelGGL(step_kernel<8>, dim3(n), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL((step_kernel<8, W>), dim3(grid), dim3(64 * W), 0, stream, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step_class(const StepArgs& a, int max_contacts, hipStream_t stream, int grid) {
+hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream, int waves) {
+  const int n = a.n_envs - a.env_base;
+  if (n <= 0) return hipSuccess;
+  return waves == 2 ? launch_class<2>(a, max_contacts, stream, n) : launch_class<1>(a, max_contacts, stream, n);
+}
+
+hipError_t launch_step_class(const StepArgs& a, int max_contacts, hipStream_t stream, int grid, int waves) {
   if (grid <= 0 || !a.queue) return hipErrorInvalidValue;
-  if (max_contacts <= 128) {
-    hipLaunchKernelGGL(step_kernel<2>, dim3(grid), dim3(64), 0, stream, a);
-  } else if (max_contacts <= 256) {
-    hipLaunchKernelGGL(step_kernel<4>, dim3(grid), dim3(64), 0, stream, a);
-  } else {
-    hipLaunchKernelGGL(step_kernel<8>, dim3(grid), dim3(64), 0, stream, a);
-  }
-  return hipGetLastError();
+  return waves == 2 ? launch_class<2>(a, max_contacts, stream, grid) : launch_class<1>(a, max_contacts, stream, grid);
 }
 
 hipError_t launch_zero(int* p, int n, hipStream_t stream) {
@@ -1608,13 +1710,18 @@ hipError_t launch_zero(int* p, int n, hipStream_t stream) {
   return hipGetLastError();
 }
 
-int step_blocks_per_cu(int max_contacts) {
+template <int W>
+static int blocks_per_cu(int max_contacts) {
   int n = 0;
   hipError_t e;
-  if (max_contacts <= 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2>, 64, 0);
-  else if (max_contacts <= 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<4>, 64, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<8>, 64, 0);
+  if (max_contacts <= 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<2, W>, 64 * W, 0);
+  else if (max_contacts <= 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<4, W>, 64 * W, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<8, W>, 64 * W, 0);
   return e == hipSuccess ? n : 0;
+}
+
+int step_blocks_per_cu(int max_contacts, int waves) {
+  return waves == 2 ? blocks_per_cu<2>(max_contacts) : blocks_per_cu<1>(max_contacts);
 }
 
 hipError_t launch_pool(const PoolArgs& a, hipStream_t stream) {

@@ -267,7 +267,12 @@ pmbs_status rewards_from_pool(pmbs_sim_t* sim, const int32_t* slots, const int32
 
 static int class_index(int max_contacts) { return max_contacts <= 128 ? 0 : max_contacts <= 256 ? 1 : 2; }
 
-int class_grid(pmbs_sim_t* sim, int max_contacts, int blocks_per_cu) {
+int plan_waves(const pmbs_sim_t* sim, int max_contacts) {
+  const int w = max_contacts <= 128 ? sim->plan.small_waves : max_contacts <= 256 ? sim->plan.large_waves : 1;
+  return w == 2 ? 2 : 1;
+}
+
+int class_grid(pmbs_sim_t* sim, int max_contacts, int blocks_per_cu, int waves) {
   if (sim->cus <= 0) {
     int dev = 0;
     sim->cus = 256;
@@ -275,12 +280,12 @@ int class_grid(pmbs_sim_t* sim, int max_contacts, int blocks_per_cu) {
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
       sim->cus = prop.multiProcessorCount;
   }
-  const int k = class_index(max_contacts);
-  if (sim->occ[k] <= 0) {
-    const int o = step_blocks_per_cu(max_contacts);
-    sim->occ[k] = o > 0 ? o : 1;
+  const int k = class_index(max_contacts), w = waves == 2 ? 1 : 0;
+  if (sim->occ[k][w] <= 0) {
+    const int o = step_blocks_per_cu(max_contacts, waves == 2 ? 2 : 1);
+    sim->occ[k][w] = o > 0 ? o : 1;
   }
-  const int per_cu = blocks_per_cu > 0 && blocks_per_cu < sim->occ[k] ? blocks_per_cu : sim->occ[k];
+  const int per_cu = blocks_per_cu > 0 && blocks_per_cu < sim->occ[k][w] ? blocks_per_cu : sim->occ[k][w];
   return sim->cus * per_cu;
 }
 
@@ -301,11 +306,20 @@ static hipError_t ensure_streams(pmbs_sim_t* sim) {
 // 512-contact fallback after both.  skip_empty leaves out kernels whose
 // host-known lists are empty (never inside a captured graph, whose launches
 // must not depend on the counts).
+// the children's validity words after a queued rollout: the env count is
+// that of the two work lists in device memory, over a fixed grid, so a
+// replayed graph serves any count
+static hipError_t launch_valid_counted(pmbs_sim_t* sim, ValidArgs va, hipStream_t stream) {
+  va.count = sim->d_ctl + 8;
+  return launch_valid(va, stream, std::min(sim->cfg.max_envs, 2048));
+}
+
 hipError_t enqueue_queued(pmbs_sim_t* sim, const StepArgs& a, hipStream_t stream, bool skip_empty, int n_small,
-                          int n_large) {
+                          int n_large, const ValidArgs* va) {
   const int mc = sim->cfg.max_contacts;
   int* ctl = sim->d_ctl;
   const pmbs_launch_plan& pl = sim->plan;
+  const int ws = plan_waves(sim, 128), wl = plan_waves(sim, 256);
   hipError_t e = launch_zero(ctl, 6, stream);
   if (e != hipSuccess) return e;
   StepArgs sm = a, lg = a, f4 = a, f8 = a;
@@ -313,8 +327,10 @@ hipError_t enqueue_queued(pmbs_sim_t* sim, const StepArgs& a, hipStream_t stream
   sm.work_count = ctl + 8;
   sm.queue = ctl + 0;
   if (mc == 128) {
-    if (skip_empty && n_small == 0) return hipSuccess;
-    return launch_step_class(sm, 128, stream, class_grid(sim, 128, pl.small_blocks_per_cu));
+    if (!skip_empty || n_small > 0)
+      e = launch_step_class(sm, 128, stream, class_grid(sim, 128, pl.small_blocks_per_cu, ws), ws);
+    if (e == hipSuccess && va) e = launch_valid_counted(sim, *va, stream);
+    return e;
   }
   sm.overflow_list = sim->d_ovf4;
   sm.overflow_count = ctl + 4;
@@ -335,16 +351,20 @@ hipError_t enqueue_queued(pmbs_sim_t* sim, const StepArgs& a, hipStream_t stream
   if (run_large) {
     if ((e = hipEventRecord(sim->ev_fork, stream)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(sim->side, sim->ev_fork, 0)) != hipSuccess) return e;
-    if ((e = launch_step_class(lg, 256, sim->side, class_grid(sim, 256, pl.large_blocks_per_cu))) != hipSuccess)
+    if ((e = launch_step_class(lg, 256, sim->side, class_grid(sim, 256, pl.large_blocks_per_cu, wl), wl)) !=
+        hipSuccess)
       return e;
     if ((e = hipEventRecord(sim->ev_join, sim->side)) != hipSuccess) return e;
   }
   if (run_small) {
-    if ((e = launch_step_class(sm, 128, stream, class_grid(sim, 128, pl.small_blocks_per_cu))) != hipSuccess) return e;
-    if ((e = launch_step_class(f4, 256, stream, class_grid(sim, 256, pl.large_blocks_per_cu))) != hipSuccess) return e;
+    if ((e = launch_step_class(sm, 128, stream, class_grid(sim, 128, pl.small_blocks_per_cu, ws), ws)) != hipSuccess)
+      return e;
+    if ((e = launch_step_class(f4, 256, stream, class_grid(sim, 256, pl.large_blocks_per_cu, wl), wl)) != hipSuccess)
+      return e;
   }
   if (run_large && (e = hipStreamWaitEvent(stream, sim->ev_join, 0)) != hipSuccess) return e;
-  if (mc > 256) e = launch_step_class(f8, 512, stream, class_grid(sim, 512, 0));
+  if (mc > 256) e = launch_step_class(f8, 512, stream, class_grid(sim, 512, 0, 1), 1);
+  if (e == hipSuccess && va) e = launch_valid_counted(sim, *va, stream);
   return e;
 }
 
@@ -385,6 +405,26 @@ void share_pool(pmbs_sim_t* sim, const pmbs_sim_t* from) {
   sim->d_bconst = from->d_bconst;
   sim->cfg.pool_slots = from->cfg.pool_slots;
   sim->cfg.pool_stride = from->cfg.pool_stride;
+}
+
+ValidArgs valid_args(pmbs_sim_t* sim, const int32_t* d_src_slot) {
+  ValidArgs v;
+  std::memset(&v, 0, sizeof v);  // padding too: launch arguments are compared bytewise
+  v.state = sim->d_state;
+  v.bconst = sim->d_bconst;
+  v.env_offset = sim->d_env_offset;
+  v.src_slot = d_src_slot;
+  v.pool = sim->d_pool;
+  v.out = sim->d_valid;
+  v.n_envs = sim->n_envs;
+  v.stride = sim->cfg.max_bodies;
+  v.pool_stride = sim->cfg.pool_stride;
+  if (sim->pool_layout) {
+    v.bc_base = sim->d_bc_base;
+    v.bc_stride = sim->cfg.max_bodies;
+  }
+  v.p = params_of(sim->cfg);
+  return v;
 }
 
 StepArgs step_args(pmbs_sim_t* sim) {
@@ -516,6 +556,8 @@ pmbs_status pmbs_sim_create(const pmbs_sim_config* cfg, void* d_workspace, size_
   s->plan.small_blocks_per_cu = 0;
   s->plan.large_blocks_per_cu = 0;
   s->plan.order = 1;
+  s->plan.small_waves = 1;
+  s->plan.large_waves = 1;
   s->n_envs = 0;
   s->n_bodies = 0;
   hipError_t e = hipMemsetAsync(s->d_status, 0, (size_t)cfg->max_envs * sizeof(uint32_t), s->stream);
@@ -536,6 +578,8 @@ pmbs_status pmbs_sim_set_launch_plan(pmbs_sim_t* sim, const pmbs_launch_plan* pl
   if (plan->small_blocks_per_cu < 0 || plan->large_blocks_per_cu < 0)
     return fail(PMBS_ERR_INVALID_ARG, "blocks per CU must be >= 0");
   if (plan->order != 0 && plan->order != 1) return fail(PMBS_ERR_INVALID_ARG, "order must be 0 or 1");
+  if ((plan->small_waves != 1 && plan->small_waves != 2) || (plan->large_waves != 1 && plan->large_waves != 2))
+    return fail(PMBS_ERR_INVALID_ARG, "waves per environment must be 1 or 2");
   sim->plan = *plan;
   return PMBS_OK;
 }
@@ -619,7 +663,7 @@ pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_de
   StepArgs a = step_args(sim);
   a.push = d_push;
   a.n_substeps = n_substeps;
-  hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream);
+  hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream, plan_waves(sim, sim->cfg.max_contacts));
   if (e != hipSuccess) return hip_fail(e, "step launch");
   return PMBS_OK;
 }
@@ -761,9 +805,12 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
   a.width = width;
   a.write_state = (flags & PMBS_ROLLOUT_WRITE_STATE) ? 1 : 0;
   a.n_substeps = n_substeps;
-  if (flags & PMBS_ROLLOUT_CHILD_VALID) a.valid_out = sim->d_valid;
+  // the children's validity words, by a launch after the rollout's
+  ValidArgs va = valid_args(sim, a.child_slot);
+  const ValidArgs* vap = (flags & PMBS_ROLLOUT_CHILD_VALID) && a.child_slot ? &va : nullptr;
   if (!use_queue) {
-    hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream);
+    hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream, plan_waves(sim, sim->cfg.max_contacts));
+    if (e == hipSuccess && vap) e = launch_valid(va, sim->stream);
     if (e != hipSuccess) return hip_fail(e, "rollout launch");
     return PMBS_OK;
   }
@@ -771,21 +818,23 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
   hipError_t e = ensure_streams(sim);
   if (e != hipSuccess) return hip_fail(e, "stream creation");
   for (int mc : {128, 256, 512})
-    if (mc <= sim->cfg.max_contacts) (void)class_grid(sim, mc, 0);  // occupancy queries outside any capture
+    if (mc <= sim->cfg.max_contacts)
+      for (int w : {1, 2}) (void)class_grid(sim, mc, 0, w);  // occupancy queries outside any capture
   if (!(flags & PMBS_ROLLOUT_GRAPH)) {
-    e = enqueue_queued(sim, a, sim->stream, true, counts[0], counts[1]);
+    e = enqueue_queued(sim, a, sim->stream, true, counts[0], counts[1], vap);
     if (e != hipSuccess) return hip_fail(e, "rollout launch");
     return PMBS_OK;
   }
+  const int with_valid = vap ? 1 : 0;
   if (!sim->graph_exec || std::memcmp(&sim->graph_args, &a, sizeof a) != 0 ||
-      std::memcmp(&sim->graph_plan, &sim->plan, sizeof sim->plan) != 0) {
+      std::memcmp(&sim->graph_plan, &sim->plan, sizeof sim->plan) != 0 || sim->graph_valid != with_valid) {
     if (sim->graph_exec) (void)hipGraphExecDestroy(sim->graph_exec);
     if (sim->graph) (void)hipGraphDestroy(sim->graph);
     sim->graph_exec = nullptr;
     sim->graph = nullptr;
     e = hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "graph capture begin");
-    const hipError_t ce = enqueue_queued(sim, a, sim->cap, false, 0, 0);
+    const hipError_t ce = enqueue_queued(sim, a, sim->cap, false, 0, 0, vap);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(sim->cap, &graph);
     if (ce != hipSuccess || e != hipSuccess) {
@@ -800,6 +849,7 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
     }
     sim->graph_args = a;
     sim->graph_plan = sim->plan;
+    sim->graph_valid = with_valid;
   }
   e = hipGraphLaunch(sim->graph_exec, sim->stream);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
@@ -825,18 +875,7 @@ pmbs_status pmbs_sim_valid_pushes(pmbs_sim_t* sim, const int32_t* src_slot, int3
     hipError_t e = hipStreamSynchronize(sim->stream);
     if (e != hipSuccess) return hip_fail(e, "validity upload");
   }
-  StepArgs a = step_args(sim);
-  a.valid_only = 1;
-  a.valid_out = sim->d_valid;
-  a.src_slot = d_src;
-  a.pool = sim->d_pool;
-  a.pool_stride = sim->cfg.pool_stride;
-  if (sim->pool_layout) {
-    a.bc_base = sim->d_bc_base;
-    a.bc_stride = sim->cfg.max_bodies;
-  }
-  a.stats = nullptr;
-  hipError_t e = launch_step(a, 128, sim->stream);
+  hipError_t e = launch_valid(valid_args(sim, d_src), sim->stream);
   if (e != hipSuccess) return hip_fail(e, "validity launch");
   return PMBS_OK;
 }

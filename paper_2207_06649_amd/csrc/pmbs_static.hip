@@ -141,20 +141,24 @@ pmbs_status pmbs_sim_rollout_static(pmbs_sim_t* sim, const int32_t* actions, con
   a.width = width;
   a.write_state = (flags & PMBS_ROLLOUT_WRITE_STATE) ? 1 : 0;
   a.n_substeps = n_substeps;
-  if (flags & PMBS_ROLLOUT_CHILD_VALID) a.valid_out = sim->d_valid;
   a.n_envs = 0;  // the queued kernels take their counts from the device
 
   // the contact classes one after another on the caller's stream (no side
   // stream): 128-contact list, 256-contact list, then the fallbacks
   const int mc = sim->cfg.max_contacts;
   const pmbs_launch_plan& pl = sim->plan;
+  const int ws = plan_waves(sim, 128), wl = plan_waves(sim, 256);
   int32_t* ctl = sc + O_CTL;
+  // the children's validity words, after every class
+  const bool child_valid = (flags & PMBS_ROLLOUT_CHILD_VALID) && child_slot;
+  const ValidArgs va = valid_args(sim, sc + O_CHILD);
   StepArgs sm = a, lg = a, f4 = a, f8 = a;
   sm.order = sc + O_SMALL;
   sm.work_count = ctl + 8;
   sm.queue = ctl + 0;
   if (mc == 128) {
-    if (ns > 0) e = launch_step_class(sm, 128, s, class_grid(sim, 128, pl.small_blocks_per_cu));
+    if (ns > 0) e = launch_step_class(sm, 128, s, class_grid(sim, 128, pl.small_blocks_per_cu, ws), ws);
+    if (e == hipSuccess && child_valid) e = launch_valid(va, s);
     return e == hipSuccess ? PMBS_OK : hip_fail(e, "static rollout launch");
   }
   sm.overflow_list = sc + O_OVF4;
@@ -172,10 +176,13 @@ pmbs_status pmbs_sim_rollout_static(pmbs_sim_t* sim, const int32_t* actions, con
   f8.order = sc + O_OVF8;
   f8.work_count = ctl + 5;
   f8.queue = ctl + 3;
-  if (ns > 0) e = launch_step_class(sm, 128, s, class_grid(sim, 128, pl.small_blocks_per_cu));
-  if (e == hipSuccess && nl > 0) e = launch_step_class(lg, 256, s, class_grid(sim, 256, pl.large_blocks_per_cu));
-  if (e == hipSuccess && ns > 0) e = launch_step_class(f4, 256, s, class_grid(sim, 256, pl.large_blocks_per_cu));
-  if (e == hipSuccess && mc > 256) e = launch_step_class(f8, 512, s, class_grid(sim, 512, 0));
+  if (ns > 0) e = launch_step_class(sm, 128, s, class_grid(sim, 128, pl.small_blocks_per_cu, ws), ws);
+  if (e == hipSuccess && nl > 0)
+    e = launch_step_class(lg, 256, s, class_grid(sim, 256, pl.large_blocks_per_cu, wl), wl);
+  if (e == hipSuccess && ns > 0)
+    e = launch_step_class(f4, 256, s, class_grid(sim, 256, pl.large_blocks_per_cu, wl), wl);
+  if (e == hipSuccess && mc > 256) e = launch_step_class(f8, 512, s, class_grid(sim, 512, 0, 1), 1);
+  if (e == hipSuccess && child_valid) e = launch_valid(va, s);
   return e == hipSuccess ? PMBS_OK : hip_fail(e, "static rollout launch");
 }
 

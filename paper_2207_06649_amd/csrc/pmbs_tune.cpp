@@ -1,7 +1,8 @@
 // pmbs_tune.cpp -- autotuner of the queued-rollout launch plan.
 //
 // The tuned knobs are the body count below which an env runs in the
-// 128-contact kernel, the persistent workgroups per CU of each class, and
+// 128-contact kernel, the workgroup shape of each class (one or two waves
+// per environment), the persistent workgroups per CU of each class, and
 // the work order.  Each candidate runs the caller's rollout (from the same
 // inputs, so its outputs are unchanged) and is timed with HIP events on the
 // simulator's stream; coordinate descent keeps the fastest median.  Results
@@ -71,7 +72,9 @@ bool cache_lookup(const char* path, const std::string& key, pmbs_launch_plan* pl
     std::string k;
     pmbs_launch_plan p;
     float t;
-    if (!(in >> k >> p.small_max_bodies >> p.small_blocks_per_cu >> p.large_blocks_per_cu >> p.order >> t)) continue;
+    if (!(in >> k >> p.small_max_bodies >> p.small_blocks_per_cu >> p.large_blocks_per_cu >> p.order >> p.small_waves >>
+          p.large_waves >> t))
+      continue;
     if (k == key) {
       *plan = p;
       *ms = t;
@@ -85,7 +88,7 @@ void cache_store(const char* path, const std::string& key, const pmbs_launch_pla
   std::ofstream f(path, std::ios::app);
   if (!f) return;
   f << key << " " << p.small_max_bodies << " " << p.small_blocks_per_cu << " " << p.large_blocks_per_cu << " "
-    << p.order << " " << ms << "\n";
+    << p.order << " " << p.small_waves << " " << p.large_waves << " " << ms << "\n";
 }
 
 }  // namespace
@@ -180,7 +183,20 @@ pmbs_status pmbs_sim_autotune(pmbs_sim_t* sim, const int32_t* actions, const int
       if (T != cur.small_max_bodies) consider(p);
     }
   }
-  const int occ_s = sim->occ[0], occ_l = sim->occ[1];
+  // workgroup shape: one or two waves per environment, per class
+  for (int w : {1, 2}) {
+    pmbs_launch_plan p = win;
+    p.small_waves = w;
+    if (w != win.small_waves) consider(p);
+  }
+  if (sim->cfg.max_contacts > 128)
+    for (int w : {1, 2}) {
+      pmbs_launch_plan p = win;
+      p.large_waves = w;
+      if (w != win.large_waves) consider(p);
+    }
+  // workgroups per CU of the chosen shapes (occupancy known from the runs above)
+  const int occ_s = sim->occ[0][win.small_waves == 2 ? 1 : 0], occ_l = sim->occ[1][win.large_waves == 2 ? 1 : 0];
   for (int b = 1; b < occ_s; ++b) {
     pmbs_launch_plan p = win;
     p.small_blocks_per_cu = b;

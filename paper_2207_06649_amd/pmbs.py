@@ -31,7 +31,8 @@ MAX_BODIES_PER_ENV = 31
 
 class LaunchPlan(C.Structure):
     _fields_ = [("small_max_bodies", C.c_int32), ("small_blocks_per_cu", C.c_int32),
-                ("large_blocks_per_cu", C.c_int32), ("order", C.c_int32)]
+                ("large_blocks_per_cu", C.c_int32), ("order", C.c_int32), ("small_waves", C.c_int32),
+                ("large_waves", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -349,8 +350,9 @@ class Sim:
         self.sync()
         return rew.cpu().numpy(), cnt.cpu().numpy()
 
-    def set_launch_plan(self, small_max_bodies=16, small_blocks_per_cu=0, large_blocks_per_cu=0, order=1):
-        p = LaunchPlan(small_max_bodies, small_blocks_per_cu, large_blocks_per_cu, order)
+    def set_launch_plan(self, small_max_bodies=16, small_blocks_per_cu=0, large_blocks_per_cu=0, order=1,
+                        small_waves=1, large_waves=1):
+        p = LaunchPlan(small_max_bodies, small_blocks_per_cu, large_blocks_per_cu, order, small_waves, large_waves)
         _check(lib().pmbs_sim_set_launch_plan(self.handle, C.byref(p)))
 
     def launch_plan(self) -> dict:

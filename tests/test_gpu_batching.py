@@ -267,3 +267,39 @@ def test_queued_graph_rollouts_match_the_oracle(pm):
             n = ref["applied"]
             assert cnt[e] == n, (k, e, cnt[e], n)
             assert np.abs(rew[e, :n] - ref["rewards"]).max(initial=0.0) <= 1e-3, (k, e, rew[e, :n], ref["rewards"])
+
+
+@pytest.mark.parametrize("waves", [(2, 1), (1, 2), (2, 2)])
+def test_two_wave_workgroups_are_bitwise_one_wave(pm, case, waves):
+    """Two waves per environment (the second takes half the contact slots
+    and every second narrowphase pass) in either class: every env's
+    rewards, count, status and child state are bitwise those of one wave,
+    eagerly and replayed as a graph; the two shapes also race-check each
+    other's LDS hand-offs."""
+    b, acts, off, tgt, ref128, ref256 = case
+    r = Run(pm, b, 256)
+    r.sim.set_launch_plan(small_max_bodies=16, small_waves=waves[0], large_waves=waves[1])
+    nb = b.counts()
+    for flags in (pm.ROLLOUT_QUEUE, pm.ROLLOUT_QUEUE | pm.ROLLOUT_GRAPH, pm.ROLLOUT_QUEUE | pm.ROLLOUT_GRAPH):
+        r.rew.fill_(-2.0)
+        got = r.go(acts, off, tgt, SUB, flags)
+        for e in range(b.n_envs):
+            small_ok = nb[e] <= 16 and not (ref128[2][e] & 1)
+            assert env_equal(b, e, got, ref128 if small_ok else ref256), (waves, flags, e)
+
+
+def test_two_wave_step_is_bitwise_one_wave(pm):
+    """pmbs_sim_step (one workgroup per env) with two waves per env: the
+    state after 40 substeps of pushed 15-cuboid clutter and the env status
+    are bitwise those of one wave, in the 128- and the 256-contact class."""
+    b = scenes.clutter_batch(8, 96, 15)
+    for mc in (128, 256):
+        out = {}
+        for w in (1, 2):
+            sim = pm.Sim(max_envs=b.n_envs, max_bodies=b.n_bodies, max_contacts=mc)
+            sim.set_launch_plan(small_waves=w, large_waves=w)
+            sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+            sim.step(b.push.astype(np.float32), 40)
+            out[w] = (sim.get_state(), sim.env_status().copy())
+        assert np.array_equal(out[1][0], out[2][0]), mc
+        assert np.array_equal(out[1][1], out[2][1]), mc

@@ -104,3 +104,20 @@ def test_serial_plan_runs(pm):
     res = pm.plan(sim, tree, f32(b.state), f32(b.body), 0, 10, n_substeps=60)
     assert res["iterations"] == 10 and res["simulations"] == 10
     assert res["action"] >= 0 and res["nodes"] >= 2
+
+
+def test_plan_is_the_same_with_two_waves_per_env(pm):
+    """The planner with two waves per environment in both contact classes
+    returns bitwise the one-wave plan (tree statistics and the action)."""
+    b = scenes.retrieval_scene(5, n_others=12, region=0.3)
+    st, bd = f32(b.state), f32(b.body)
+    n = len(bd)
+    res = {}
+    for w in (1, 2):
+        sim = pm.Sim(max_envs=48, max_bodies=48 * n, pool_slots=1024, pool_stride=n, max_horizon=3,
+                     max_contacts=256)
+        sim.set_launch_plan(small_max_bodies=10, small_waves=w, large_waves=w)
+        tree = pm.Tree(n, O.reward(st, bd, 0, 0.08), n_envs=48, max_depth=3, seed=7, max_nodes=1024)
+        r = pm.plan(sim, tree, st, bd, 0, 4, n_substeps=40)
+        res[w] = (r["action"], r["value"], r["nodes"], [tree.node(i)["Q"] for i in range(r["nodes"])])
+    assert res[1] == res[2]

@@ -249,3 +249,26 @@ def test_rollout_child_validity_words(pm):
         lo, hi = b.env_offset[e], b.env_offset[e + 1]
         ok, sure = oracle_validity(st[lo:hi], f32(b.body[lo:hi]))
         assert np.array_equal(bits(words[e], len(ok))[sure], ok[sure]), e
+
+
+def test_graph_replayed_child_validity_follows_the_env_count(pm):
+    """A captured queued rollout replayed for a larger batch (the graph is
+    kept: only device-held counts change) writes the child validity words of
+    every env of the new batch, bitwise those of a validity launch on the
+    children's pool slots."""
+    sim = pm.Sim(max_envs=40, max_bodies=40 * 20, max_contacts=256, pool_slots=80, pool_stride=31, max_horizon=2)
+    for E in (12, 40):
+        b, acts, off, tgt = rollout_case(40 + E, E, (5, 20), [1], substeps=10, region=0.25)
+        sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+        src = np.arange(E, dtype=np.int32)
+        child = src + 40
+        sim.pool_scatter(src)
+        sim.rollout(acts, off, tgt, n_substeps=10, src_slot=src, child_slot=child, max_h=2,
+                    flags=pm.ROLLOUT_QUEUE | pm.ROLLOUT_GRAPH | pm.ROLLOUT_CHILD_VALID)
+        status = sim.env_status()
+        words = sim.push_valid().copy()
+        made = [e for e in range(E) if not (status[e] & pm.PMBS_ENV_PUSH_INVALID)]
+        assert len(made) >= E // 2
+        again = sim.valid_pushes(src_slot=np.where(np.isin(np.arange(E), made), child, -1).astype(np.int32))
+        for e in made:
+            assert np.array_equal(again[e], words[e]), (E, e)
