@@ -132,6 +132,19 @@ def plan_latency(pmbs, scenes, args) -> dict:
     leaves, iters = args.plan_leaves, args.plan_iters
     max_nodes = leaves * iters + 2
     sim = sim_for(leaves, max_nodes)
+    # launch plan (workgroup shape, workgroups per CU, order) chosen by the
+    # autotuner on a rollout of the planning workload's shape: every leaf a
+    # copy of the first scene with depth-many random contour pushes
+    sc0 = scenes.retrieval_scene(100, n_others=20, region=0.4)
+    tb = scenes.concat([scenes.Batch(np.array([0, n_bodies], np.int32), sc0.state, sc0.body, np.zeros((1, 4)),
+                                     np.zeros(1, np.int32))] * leaves)
+    sim.set_state(tb.env_offset, tb.state, tb.body)
+    t_acts, t_off = scenes.contour_actions(7, tb.counts(), np.full(leaves, depth))
+    t0 = time.perf_counter()
+    tuned, tuned_ms, _ = sim.autotune(t_acts, t_off, np.zeros(leaves, np.int32), n_substeps=120, max_h=depth, reps=1)
+    tune_s = time.perf_counter() - t0
+    print(f"# plan launch plan {tuned} ({tuned_ms:.1f} ms per rollout, {tune_s:.1f} s of tuning)", file=sys.stderr,
+          flush=True)
     for k in range(args.plan_scenes):
         sc = scenes.retrieval_scene(100 + k, n_others=20, region=0.4)
         tree = pmbs.Tree(n_bodies, root_reward(sc.state, sc.body), n_envs=leaves, max_depth=depth, c=1.4,
@@ -146,6 +159,7 @@ def plan_latency(pmbs, scenes, args) -> dict:
     # serial baseline: same scene as the first plan, one leaf per iteration
     sc = scenes.retrieval_scene(100, n_others=20, region=0.4)
     ssim = sim_for(1, args.serial_iters + 2)
+    ssim.set_launch_plan(**tuned)   # the same launch shape for the one-leaf search
     tree = pmbs.Tree(n_bodies, root_reward(sc.state, sc.body), n_envs=1, max_depth=depth, c=1.4, gamma=0.8,
                      seed=100, max_nodes=args.serial_iters + 2)
     sres = pmbs.plan(ssim, tree, sc.state, sc.body, 0, args.serial_iters, n_substeps=120)
@@ -163,12 +177,15 @@ def plan_latency(pmbs, scenes, args) -> dict:
         "serial": {"iterations_timed": int(sres["iterations"]), "s_per_iteration": round(per_iter, 5),
                    "projected_s_same_simulations": round(projected, 3)},
         "speedup_vs_serial": round(projected / float(np.percentile(t, 50)), 2),
+        "launch_plan": tuned,
     }
 
 
 def batched_1024(pmbs, scenes, args) -> dict:
     """The batched-step workload at 1024 envs x 15 cuboids (seed 1): the same
-    step (pool gather + fused push step + reward) timed over args.steps."""
+    step (pool gather + fused push step + reward) timed over args.steps, for
+    one and two waves per environment (about one environment per SIMD, so
+    the shape matters); the faster shape is reported."""
     import torch
     b = scenes.clutter_batch(1, args.small_envs, args.bodies)
     E = b.n_envs
@@ -187,20 +204,26 @@ def batched_1024(pmbs, scenes, args) -> dict:
         sim.step(push, args.substeps)
         sim.eval_reward(target, 0.08, rew, clr, sync=False)
 
-    for _ in range(args.warmup):
-        one()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    torch.cuda.synchronize()
-    ev[0].record(sim.stream)
-    for _ in range(args.steps):
-        one()
-    ev[1].record(sim.stream)
-    torch.cuda.synchronize()
-    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    per_shape = {}
+    for waves in (1, 2):
+        sim.set_launch_plan(small_waves=waves, large_waves=waves)
+        for _ in range(args.warmup):
+            one()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(sim.stream)
+        for _ in range(args.steps):
+            one()
+        ev[1].record(sim.stream)
+        torch.cuda.synchronize()
+        per_shape[waves] = ev[0].elapsed_time(ev[1]) / args.steps
+    waves = min(per_shape, key=per_shape.get)
+    ms = per_shape[waves]
     status = sim.env_status()
     return {"workload": f"{E} envs x {args.bodies} cuboids, one 5 cm circle push each, {args.substeps} substeps "
                         "(seed 1)",
             "env_substeps_per_s": round(E * args.substeps / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+            "waves_per_env": waves, "ms_per_step_by_waves": {str(k): round(v, 4) for k, v in per_shape.items()},
             "valid_pushes": int(np.sum((status & pmbs.PMBS_ENV_PUSH_INVALID) == 0))}
 
 
