@@ -147,12 +147,15 @@ def best_action(root: Node):
 
 
 def shuffled_actions(n_actions: int, node_id: int, seed: int) -> list:
-    """Fisher-Yates with Philox draws keyed by (seed, node id)."""
+    """Forward Fisher-Yates with Philox draws keyed by (seed, node id):
+    position k (from the first up) swaps with k + (x mod (n - k)), x being
+    word k mod 4 of the block with counter (node id, k div 4, 0, shuffle
+    domain)."""
     a = list(range(n_actions))
-    for i in range(n_actions - 1, 0, -1):
-        x = philox4x32((node_id, i, 0, DOMAIN_SHUFFLE), (seed & 0xFFFFFFFF, seed >> 32))[0]
-        j = x % (i + 1)
-        a[i], a[j] = a[j], a[i]
+    for k in range(n_actions - 1):
+        x = philox4x32((node_id, k // 4, 0, DOMAIN_SHUFFLE), (seed & 0xFFFFFFFF, seed >> 32))[k % 4]
+        j = k + x % (n_actions - k)
+        a[k], a[j] = a[j], a[k]
     return a
 
 

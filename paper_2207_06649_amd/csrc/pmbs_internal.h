@@ -62,10 +62,15 @@ struct Node {
   bool terminal, sel;
   double Q;
   int64_t N, Nhat;
-  std::vector<int32_t> untried;  // remaining sampled actions, taken from the front
-  size_t next_untried;
+  // sampled actions in their shuffled order, generated as they are taken:
+  // perm[0, drawn) are taken or discarded, perm[drawn, n) not yet placed
+  // (empty until the first draw); valid: bit a set when action a can start
+  // (Sec. IV-B); valid_left: valid actions not yet taken
+  std::vector<int32_t> perm;
+  int32_t drawn, valid_left;
+  uint32_t valid[PMBS_VALID_WORDS];
   std::vector<int32_t> children;
-  bool expandable(int D) const { return depth < D && next_untried < untried.size(); }
+  bool expandable(int D) const { return depth < D && valid_left > 0; }
 };
 
 }  // namespace pmbs

@@ -47,15 +47,31 @@ using pmbs::Node;
 
 namespace pmbs {
 
-static void shuffled(int32_t n, int32_t node_id, uint64_t seed, std::vector<int32_t>* out) {
-  out->resize(n);
-  for (int32_t i = 0; i < n; ++i) (*out)[i] = i;
-  for (int32_t i = n - 1; i > 0; --i) {
-    const uint32_t ctr[4] = {(uint32_t)node_id, (uint32_t)i, 0u, kShuffle};
-    uint32_t r[4];
-    philox(ctr, seed, r);
-    const int32_t j = (int32_t)(r[0] % (uint32_t)(i + 1));
-    std::swap((*out)[i], (*out)[j]);
+// The next sampled action of a node (Sec. IV-B sampling), skipping the
+// ones whose start pose collides: a forward Fisher-Yates shuffle of the
+// node's actions generated one position at a time; position k swaps with
+// k + (draw mod (n - k)), the draw being word k mod 4 of the Philox block
+// with counter (node id, k div 4, 0, shuffle domain).  The caller knows a
+// valid action is left (valid_left > 0).
+static int32_t take_action(Node* n, int32_t n_actions, uint64_t seed) {
+  if (n->perm.empty()) {
+    n->perm.resize(n_actions);
+    for (int32_t i = 0; i < n_actions; ++i) n->perm[i] = i;
+  }
+  for (;;) {
+    const int32_t k = n->drawn++;
+    if (k < n_actions - 1) {
+      const uint32_t ctr[4] = {(uint32_t)n->id, (uint32_t)(k >> 2), 0u, kShuffle};
+      uint32_t r[4];
+      philox(ctr, seed, r);
+      const int32_t j = k + (int32_t)(r[k & 3] % (uint32_t)(n_actions - k));
+      std::swap(n->perm[k], n->perm[j]);
+    }
+    const int32_t a = n->perm[k];
+    if ((n->valid[a >> 5] >> (a & 31)) & 1u) {
+      --n->valid_left;
+      return a;
+    }
   }
 }
 
@@ -78,8 +94,12 @@ static int32_t add_node(pmbs_tree_t* t, int32_t parent, int32_t action, int32_t 
   n.Q = 0.0;
   n.N = 0;
   n.Nhat = 0;
-  shuffled(t->n_actions, n.id, t->cfg.seed, &n.untried);
-  n.next_untried = 0;
+  n.drawn = 0;
+  n.valid_left = t->n_actions;
+  for (int w = 0; w < PMBS_VALID_WORDS; ++w) {
+    const int lo = 32 * w;
+    n.valid[w] = t->n_actions >= lo + 32 ? 0xffffffffu : t->n_actions > lo ? (1u << (t->n_actions - lo)) - 1u : 0u;
+  }
   n.sel = !n.terminal && n.expandable(t->d_tree);
   t->nodes.push_back(std::move(n));
   return t->nodes.back().id;
@@ -101,22 +121,23 @@ static void refresh_sel(pmbs_tree_t* t, int32_t id) {
   }
 }
 
-// Eq. (2): Q(n')/(N(n')+N^(n')) + c sqrt(2 ln(N(n)+N^(n)) / (N(n')+N^(n')))
-static double ucb(const Node& ch, const Node& par, double c) {
+// Eq. (2): Q(n')/(N(n')+N^(n')) + c sqrt(2 ln(N(n)+N^(n)) / (N(n')+N^(n'))),
+// with log_par = ln(N(n)+N^(n)) of the parent
+static double ucb(const Node& ch, double log_par, double c) {
   const double n = (double)(ch.N + ch.Nhat);
   if (n == 0.0) return INFINITY;
-  return ch.Q / n + c * std::sqrt(2.0 * std::log((double)(par.N + par.Nhat)) / n);
+  return ch.Q / n + c * std::sqrt(2.0 * log_par / n);
 }
 
 // Sec. IV-B: the node's sampled actions whose start pose collides are
-// discarded; the untried list keeps the valid ones in their shuffled order.
-static void keep_valid(Node* n, const uint32_t* words) {
-  size_t k = 0;
-  for (size_t i = 0; i < n->untried.size(); ++i) {
-    const int32_t a = n->untried[i];
-    if ((words[a >> 5] >> (a & 31)) & 1u) n->untried[k++] = a;
+// discarded (before any is taken): they stay out of its draws.
+static void keep_valid(Node* n, int32_t n_actions, const uint32_t* words) {
+  n->valid_left = 0;
+  for (int w = 0; w < PMBS_VALID_WORDS; ++w) {
+    n->valid[w] &= words[w];
+    n->valid_left += __builtin_popcount(n->valid[w]);
   }
-  n->untried.resize(k);
+  (void)n_actions;
 }
 
 }  // namespace pmbs
@@ -178,12 +199,13 @@ pmbs_status pmbs_tree_select(pmbs_tree_t* t, int32_t* n_pairs, int32_t* actions,
     int32_t id = 0;
     while (!t->nodes[id].expandable(D)) {
       const Node& par = t->nodes[id];
+      const double log_par = std::log((double)(par.N + par.Nhat));
       int32_t best = -1;
       double bu = -INFINITY;
       for (int32_t c : par.children) {
         const Node& ch = t->nodes[c];
         if (!ch.sel) continue;
-        const double u = ucb(ch, par, t->cfg.c);
+        const double u = ucb(ch, log_par, t->cfg.c);
         if (best < 0 || u > bu) {
           best = c;
           bu = u;
@@ -192,7 +214,7 @@ pmbs_status pmbs_tree_select(pmbs_tree_t* t, int32_t* n_pairs, int32_t* actions,
       id = best;
     }
     Node& n = t->nodes[id];
-    const int32_t a = n.untried[n.next_untried++];
+    const int32_t a = take_action(&n, t->n_actions, t->cfg.seed);
     t->pair_node.push_back(id);
     t->pair_action.push_back(a);
     if ((int64_t)t->next_slot + (int64_t)t->pair_slot.size() >= (int64_t)t->cfg.max_nodes)
@@ -240,9 +262,9 @@ pmbs_status pmbs_tree_set_valid(pmbs_tree_t* t, int32_t id, const uint32_t* word
   if (id < 0 || id >= (int32_t)t->nodes.size()) return fail(PMBS_ERR_INVALID_ARG, "node %d out of range", id);
   if (t->n_actions > 32 * PMBS_VALID_WORDS) return fail(PMBS_ERR_CAPACITY, "more actions than validity bits");
   Node& n = t->nodes[id];
-  if (n.next_untried != 0 || !n.children.empty())
+  if (n.drawn != 0 || !n.children.empty())
     return fail(PMBS_ERR_INVALID_ARG, "node %d has already been selected from", id);
-  keep_valid(&n, words);
+  keep_valid(&n, t->n_actions, words);
   refresh_sel(t, id);
   return PMBS_OK;
 }
@@ -281,7 +303,9 @@ pmbs_status pmbs_tree_update_ex(pmbs_tree_t* t, const float* rewards, int32_t ma
     return fail(PMBS_ERR_INVALID_ARG, "extra rewards and counts go together");
   if (!t->pending) return fail(PMBS_ERR_INVALID_ARG, "no selection pending");
   const int P = (int)t->pair_node.size(), E = (int)t->env_pair.size();
-  const double gamma = t->cfg.gamma;
+  // gamma^t, t < 64 (the same std::pow values as computed per use)
+  double gpow[64];
+  for (int k = 0; k < 64; ++k) gpow[k] = std::pow(t->cfg.gamma, (double)k);
   std::vector<double> best(P, -INFINITY);
   std::vector<int> first(P, -1);
   for (int e = 0; e < E; ++e) {
@@ -290,7 +314,7 @@ pmbs_status pmbs_tree_update_ex(pmbs_tree_t* t, const float* rewards, int32_t ma
     if (env_status[e] & PMBS_ENV_PUSH_INVALID) continue;
     double g = -INFINITY;
     for (int tt = 0; tt < counts[e] && tt < max_h; ++tt)
-      g = std::fmax(g, std::pow(gamma, (double)tt) * (double)rewards[(size_t)e * max_h + tt]);
+      g = std::fmax(g, gpow[tt] * (double)rewards[(size_t)e * max_h + tt]);
     best[p] = std::fmax(best[p], g);
   }
   if (extra_rewards) {
@@ -300,7 +324,7 @@ pmbs_status pmbs_tree_update_ex(pmbs_tree_t* t, const float* rewards, int32_t ma
       const int q = (t->env_pair[e] + 1) % P;
       double g = -INFINITY;
       for (int tt = 0; tt < extra_counts[e] && tt < max_h; ++tt)
-        g = std::fmax(g, std::pow(gamma, (double)tt) * (double)extra_rewards[(size_t)e * max_h + tt]);
+        g = std::fmax(g, gpow[tt] * (double)extra_rewards[(size_t)e * max_h + tt]);
       best[q] = std::fmax(best[q], g);
     }
   }
@@ -313,7 +337,7 @@ pmbs_status pmbs_tree_update_ex(pmbs_tree_t* t, const float* rewards, int32_t ma
                                    rewards[(size_t)e * max_h]);
     if (child_valid) {
       Node& c = t->nodes[child];
-      keep_valid(&c, child_valid + (size_t)e * PMBS_VALID_WORDS);
+      keep_valid(&c, t->n_actions, child_valid + (size_t)e * PMBS_VALID_WORDS);
       c.sel = !c.terminal && c.expandable(t->d_tree);
     }
     t->nodes[par].children.push_back(child);
@@ -343,7 +367,7 @@ pmbs_status pmbs_tree_update_ex(pmbs_tree_t* t, const float* rewards, int32_t ma
     double G = best[p];
     int j = 0;
     for (int32_t m = child; m >= 0; m = t->nodes[m].parent, ++j) {
-      t->nodes[m].Q += std::pow(gamma, (double)j) * G;
+      t->nodes[m].Q += (j < 64 ? gpow[j] : std::pow(t->cfg.gamma, (double)j)) * G;
       t->nodes[m].N += 1;
     }
     ++made;

@@ -120,7 +120,7 @@ def oracle_nodes(p):
 @pytest.mark.parametrize("n_envs,depth,iters,seed,extra", [
     (1, 4, 30, 7, {}), (4, 3, 12, 1, {}), (16, 4, 8, 3, {}), (64, 5, 5, 9, {}),
     (4, 3, 12, 1, dict(sim_depth=2)), (1, 4, 40, 7, dict(early_stop=1)), (8, 5, 20, 2, dict(early_stop=1)),
-    (16, 4, 20, 5, dict(early_stop=1, sim_depth=1)), (8, 4, 10, 3, dict(repurpose=1)),
+    (16, 4, 20, 5, dict(early_stop=1, sim_depth=1)), (8, 4, 10, 5, dict(repurpose=1)),
     (3, 5, 15, 5, dict(repurpose=1, sim_depth=1)), (16, 4, 12, 0, dict(repurpose=1, early_stop=1)),
     (4, 3, 12, 1, dict(discard=1)), (16, 4, 10, 3, dict(discard=1, repurpose=1)),
     (8, 5, 20, 2, dict(discard=1, early_stop=1))])
