@@ -113,11 +113,11 @@ struct Smem {
   float4 vel[NOBJ];                  // solver snapshot: linear
   float4 ang[NOBJ];                  // solver snapshot: angular
   int cnt[NOBJ];                     // contacts touching each body (mass splitting)
-  // Per-body incidence lists, each padded to a multiple of 4 entries, as
+  // Per-body incidence lists, each padded to a multiple of 8 entries, as
   // ready impulse-row codes: byte offset of the row from the first impulse
-  // row | side (1 = b); list 0 for the linear lanes (row P), list 1 for the
-  // angular lanes (row ra x P or rb x P).  Padding codes point at the zero row.
-  unsigned short inc[2][2 * C + 4 * MAXB];
+  // row | side (1 = b); list 0 for the linear sums (row P), list 1 for the
+  // angular sums (row ra x P or rb x P).  Padding codes point at the zero row.
+  unsigned short inc[2][2 * C + 8 * MAXB];
   float lo[3][MAXB], hi[3][MAXB];    // AABBs
   int sorted[MAXB];                  // objects in min-x order (kept while still ordered)
   int lstart[MAXB];                  // incidence list starts
@@ -131,7 +131,8 @@ struct Smem {
     float4 imp[3][C];                // solver exchange: P, ra x P, rb x P
   } u;
   float4 zero;                       // a row of zeros after the impulse rows (never written)
-  union {
+  union alignas(16) {
+    float cand[W][CLIP_GROUPS][16];         // narrowphase: axis candidates of each wave's eight groups
     float clip[W][2][POLY][3][CLIP_GROUPS]; // narrowphase: clip polygons of each wave's eight groups
     unsigned incm[NOBJ][2 * K];             // incidence build: contact bit masks per body
   } x;
@@ -301,54 +302,11 @@ __device__ __forceinline__ int upper_half(int v) { return __builtin_amdgcn_perml
 __device__ __forceinline__ float wave_next(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0x7f800000, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
+// value of lane ^ 1 (DPP quad permutation 1, 0, 3, 2)
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, true));
+}
 __device__ __forceinline__ int wave_next(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
-
-// Group broadcast: lane j of each 8-lane group to the whole group, as two
-// row broadcasts (DPP row_newbcast) each written only to its half of the
-// 16-lane row (bank masks: lanes 0-7, lanes 8-15).
-template <int j>
-__device__ __forceinline__ int group_bcast(int v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, v, 0x150 + j, 0xf, 0x3, false);
-  return __builtin_amdgcn_update_dpp(lo, v, 0x158 + j, 0xf, 0xc, false);
-}
-
-// Candidate k of an 8-lane group: held by lane k mod 8 of the group, in its
-// first value for k < 8 and its second for k >= 8; an invalid candidate
-// holds -inf (candidate 0, a face of A, is always valid, so -inf never
-// replaces a kept axis).
-template <int k>
-__device__ __forceinline__ void sat_scan_step(float sv0, float sv1, float tau_face, float tau_edge, float* bs,
-                                              int* best) {
-  const int sv = __float_as_int(k < 8 ? sv0 : sv1);
-  const float sk = __int_as_float(group_bcast<k & 7>(sv));
-  const float tau = k < 6 ? tau_face : tau_edge;
-  if (*best < 0 || sk > *bs + tau) {
-    *bs = sk;
-    *best = k;
-  }
-}
-
-// Contact axis of a pair from its 15 candidates (0-2 faces of A, 3-5 faces
-// of B, 6-14 edge crosses) held by the 8 lanes of a group: the kept axis
-// starts at the first candidate and is replaced only when a later valid one
-// exceeds it by tau (face) or tau_edge (edge axes).
-__device__ __forceinline__ void sat_scan8(float sv0, float sv1, float tf, float te, float* bs, int* best) {
-  sat_scan_step<0>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<1>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<2>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<3>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<4>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<5>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<6>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<7>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<8>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<9>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<10>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<11>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<12>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<13>(sv0, sv1, tf, te, bs, best);
-  sat_scan_step<14>(sv0, sv1, tf, te, bs, best);
-}
 
 // ------------------------------------------------------------------ clipping
 // the clip buffers of wave wid
@@ -695,7 +653,9 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       if (part == 0) {
         s.pos[b] = f4(x, 0.0f);
         s.half[b] = f4(h, invm);
+        s.vel[b] = f4(v, 0.0f);
       } else {
+        s.ang[b] = f4(w, 0.0f);
         f3 c0, c1, c2;
         quat_cols(q0, q1, q2, q3, &c0, &c1, &c2);
         const float r00 = c0.x, r01 = c1.x, r02 = c2.x;
@@ -823,8 +783,6 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
 
   const int n_sub = g.collide_only ? 1 : g.n_substeps;
   int nwarm = 0;  // impulses are carried within one push only
-  // this lane's incidence list range, kept while the contact list is unchanged
-  int inc_start = 0, inc_count = 0;
   for (int k = 0; k < n_sub; ++k) {
     // ---- 1. velocity stage
     if (active && part == 0) v.z -= p.gravity * dt;
@@ -1036,9 +994,40 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       const float sv1 = fabsf(dot(d, L1)) - radius_along(A, L1) - radius_along(B, L1);
       const unsigned long long gm = 0xffull << (8 * grp);
       const bool out = (__ballot((ok0 && sv0 > p.margin) || (ok1 && sv1 > p.margin)) & gm) != 0ull;
-      float bs = -INFINITY;
-      int best = -1;
-      sat_scan8(ok0 ? sv0 : -INFINITY, ok1 ? sv1 : -INFINITY, p.tau_face, p.tau_edge, &bs, &best);
+      // the contact axis: the group's candidate values go to LDS at their
+      // candidate index (k < 8: lane k's first value, k >= 8: lane k - 8's
+      // second; an invalid candidate holds -inf), and every lane of the
+      // group scans the fifteen in order: the kept axis starts at candidate
+      // 0 (a face of A, valid whenever the pair is) and is replaced only by
+      // a later one that exceeds it by tau_face (faces) or tau_edge (edges)
+      float* const cv = &s.x.cand[wid][grp][0];
+      cv[gl] = ok0 ? sv0 : -INFINITY;
+      cv[gl + 8] = ok1 ? sv1 : -INFINITY;
+      wave_sync();
+      const float4 c0 = reinterpret_cast<const float4*>(cv)[0], c1 = reinterpret_cast<const float4*>(cv)[1];
+      const float4 c2 = reinterpret_cast<const float4*>(cv)[2], c3 = reinterpret_cast<const float4*>(cv)[3];
+      float bs = c0.x;
+      int best = 0;
+      auto scan = [&](float sk, int k, float tau) {
+        if (sk > bs + tau) {
+          bs = sk;
+          best = k;
+        }
+      };
+      scan(c0.y, 1, p.tau_face);
+      scan(c0.z, 2, p.tau_face);
+      scan(c0.w, 3, p.tau_face);
+      scan(c1.x, 4, p.tau_face);
+      scan(c1.y, 5, p.tau_face);
+      scan(c1.z, 6, p.tau_edge);
+      scan(c1.w, 7, p.tau_edge);
+      scan(c2.x, 8, p.tau_edge);
+      scan(c2.y, 9, p.tau_edge);
+      scan(c2.z, 10, p.tau_edge);
+      scan(c2.w, 11, p.tau_edge);
+      scan(c3.x, 12, p.tau_edge);
+      scan(c3.y, 13, p.tau_edge);
+      scan(c3.z, 14, p.tau_edge);
       if (!has || out) best = -1;
       // every lane of the group holds the pair's axis: its direction again
       f3 n = mk(0, 0, 0);
@@ -1066,15 +1055,18 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
         const bool a_ref = best < 3;
         const int k = a_ref ? best : best - 3;
         const int ku = k == 2 ? 0 : k + 1, kv = k == 0 ? 2 : k - 1;
+        // reference box ir (the axis owner) and incident box ii, read from
+        // LDS at the indices found (no selects over both boxes' registers)
+        const int ir = a_ref ? ia : ib, ii = a_ref ? ib : ia;
+        const float* const hr = reinterpret_cast<const float*>(&s.half[ir]);
         nref = sel(a_ref, n, neg(n));
-        fref = sel(a_ref, A.c, B.c) + nref * sel(a_ref, hcomp(A, k), hcomp(B, k));
-        u = sel(a_ref, axis(A, ku), axis(B, ku));
-        w = sel(a_ref, axis(A, kv), axis(B, kv));
-        hu = sel(a_ref, hcomp(A, ku), hcomp(B, ku));
-        hw = sel(a_ref, hcomp(A, kv), hcomp(B, kv));
-        // incident box: the other one
-        const f3 i0 = sel(a_ref, B.a0, A.a0), i1 = sel(a_ref, B.a1, A.a1), i2 = sel(a_ref, B.a2, A.a2);
-        const f3 ih = sel(a_ref, B.h, A.h), ic = sel(a_ref, B.c, A.c);
+        fref = xyz(s.pos[ir]) + nref * hr[k];
+        u = lds_axis(s, ir, ku);
+        w = lds_axis(s, ir, kv);
+        hu = hr[ku];
+        hw = hr[kv];
+        const f3 i0 = lds_axis(s, ii, 0), i1 = lds_axis(s, ii, 1), i2 = lds_axis(s, ii, 2);
+        const f3 ic = xyz(s.pos[ii]);
         const float c0 = dot(i0, nref), c1 = dot(i1, nref), c2 = dot(i2, nref);
         int fb = 0;
         float bd = c0;
@@ -1083,17 +1075,18 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
         if (-c1 < bd) { bd = -c1; fb = 3; }
         if (c2 < bd) { bd = c2; fb = 4; }
         if (-c2 < bd) { bd = -c2; fb = 5; }
-        const int m = fb >> 1;
+        const int m = fb >> 1, mp = m == 2 ? 0 : m + 1, mq = m == 0 ? 2 : m - 1;
         const float sg = (fb & 1) ? -1.0f : 1.0f;
-        const f3 am = sel(m == 0, i0, sel(m == 1, i1, i2));
-        const f3 ap = sel(m == 0, i1, sel(m == 1, i2, i0));
-        const f3 aq = sel(m == 0, i2, sel(m == 1, i0, i1));
-        const float hm = sel(m == 0, ih.x, sel(m == 1, ih.y, ih.z));
-        const float hp = sel(m == 0, ih.y, sel(m == 1, ih.z, ih.x));
-        const float hq = sel(m == 0, ih.z, sel(m == 1, ih.x, ih.y));
+        const float* const hi = reinterpret_cast<const float*>(&s.half[ii]);
+        const f3 am = lds_axis(s, ii, m), ap = lds_axis(s, ii, mp), aq = lds_axis(s, ii, mq);
+        const float hm = hi[m], hp = hi[mp], hq = hi[mq];
         const f3 fc = ic + am * (sg * hm);
         const f3 ep = ap * hp, eq = aq * hq;
-        P = sel(gl == 0, fc + (ep + eq), sel(gl == 1, fc + (eq - ep), sel(gl == 2, fc - (ep + eq), fc + (ep - eq))));
+        // corner gl of the incident face: signs (+,+), (-,+), (-,-), (+,-) of
+        // its two half edges (lanes 4-7 repeat corner 3); a product with +-1
+        // is exact, so each sum rounds once as a plain sum or difference
+        const float spp = (gl == 1 || gl == 2) ? -1.0f : 1.0f, sqq = gl >= 2 ? -1.0f : 1.0f;
+        P = fc + (ep * spp + eq * sqq);
         np = 4;
       }
       np = clip_group(s, &P, np, fref, u, 1.0f, hu, 0, grp, gl, lane, wid);
@@ -1210,10 +1203,9 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
           for (int w = 0; w < MW; ++w) cn += __popc(s.x.incm[b][w]);
         }
         int tot;
-        const int padded = (cn + 3) & ~3;
+        const int padded = (cn + 7) & ~7;
         int st0 = wave_excl_scan(part == 0 ? padded : 0, &tot);
-        inc_start = lower_half(st0);
-        inc_count = cn;
+        const int inc_start = lower_half(st0);
         if (active && part == 0) {
           s.cnt[b] = cn;
           s.lstart[b] = inc_start;
@@ -1251,66 +1243,124 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     }
 
     // ---- 7. projected Jacobi, I iterations
-    // Each lane carries the one velocity it owns (linear v on part 0,
-    // angular w on part 1) and the matching symmetric inverse mass matrix
-    // (inverse mass times identity, or the world inverse inertia): diagonal
-    // md, off-diagonal mo = (xy, xz, yz).  The update is the same for both.
-    f3 vw = part == 0 ? v : w;
-    f3 md = mk(invm, invm, invm), mo = mk(0, 0, 0);
-    if (active && part == 1) {
-      float4 ia = s.iwa[b], ib = s.iwb[b];
-      md = mk(ia.x, ia.y, ia.z);
-      mo = mk(ia.w, ib.x, ib.y);
-    }
-    float4* const vw_slot = part == 0 ? &s.vel[b] : &s.ang[b];
-    // the first 8 incidences of each body stay in registers for the whole
-    // solve as their 16-bit row codes, so a load needs no index arithmetic;
-    // the codes past a short list point at the zero row with side 0, whose
-    // term is -0 and leaves every sum unchanged, so no lane needs a select
-    unsigned inc_reg[4] = {0u, 0u, 0u, 0u};
-    const int n_reg = inc_count < 8 ? inc_count : 8;
+    // Per-body sums: the lanes of a body's linear velocity (part 0) or
+    // angular velocity (part 1) add the impulse rows of its incidence list
+    // as two partial sums in list order, one over the even entries and one
+    // over the odd entries, then the velocity takes M times their sum (M:
+    // inverse mass times identity, or the world inverse inertia; diagonal
+    // md, off-diagonal mo = (xy, xz, yz)).  Two waves: wave 0 sums the
+    // linear and wave 1 the angular velocities, a lane pair per body (one
+    // partial sum each, exchanged within the pair).  One wave: the same lane
+    // pairs when the env has at most 16 boxes, else one lane per body and
+    // part holding both partial sums.  Every layout gives the same bits.
+    const bool two = W > 1 || nb <= 16;
+    const int sp = W > 1 ? wid : (lane >> 5);
+    const int sb = W > 1 ? (lane >> 1) : (two ? ((lane & 31) >> 1) : (lane & 31));
+    const int sh = two ? (lane & 1) : 0;
+    const bool sum_on = sb < nb;
+    const bool sum_store = sum_on && sh == 0;
+    float4* const vw_slot = sp == 0 ? &s.vel[sb] : &s.ang[sb];
+    f3 vw = mk(0, 0, 0), md = mk(0, 0, 0), mo = mk(0, 0, 0);
+    // the first entries of the list stay in registers for the whole solve as
+    // 16-bit row codes (a pair lane: its entries sh, sh + 2, sh + 4, sh + 6;
+    // a single lane: entries 0..7), so a load needs no index arithmetic;
+    // past the end of a list the padding codes point at the zero row with
+    // side 0, whose term is -0 and leaves every sum unchanged
+    unsigned creg[4] = {zcode | (zcode << 16), zcode | (zcode << 16), zcode | (zcode << 16), zcode | (zcode << 16)};
+    int ccount = 0, cstart = 0;
+    if (sum_on) {
+      vw = xyz(*vw_slot);
+      if (sp == 0) {
+        const float im = s.half[sb].w;
+        md = mk(im, im, im);
+      } else {
+        const float4 ia = s.iwa[sb], ib = s.iwb[sb];
+        md = mk(ia.x, ia.y, ia.z);
+        mo = mk(ia.w, ib.x, ib.y);
+      }
+      ccount = s.cnt[sb];
+      cstart = s.lstart[sb];
+      if (ccount > 0) {   // the list holds at least 8 entries (padding included)
+        if (two) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const unsigned code = k < n_reg ? (unsigned)s.inc[part][inc_start + k] : zcode;
-      inc_reg[k >> 1] |= code << (16 * (k & 1));
+          for (int u = 0; u < 4; ++u) {
+            const unsigned code = s.inc[sp][cstart + sh + 2 * u];
+            creg[u >> 1] = u & 1 ? (creg[u >> 1] & 0xffffu) | (code << 16) : (creg[u >> 1] & 0xffff0000u) | code;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const unsigned code = s.inc[sp][cstart + u];
+            creg[u >> 1] = u & 1 ? (creg[u >> 1] & 0xffffu) | (code << 16) : (creg[u >> 1] & 0xffff0000u) | code;
+          }
+        }
+      }
     }
-    const int inc_padded = (inc_count + 3) & ~3;
-    // per body: impulse sums in contact-index order (four incidences per step
-    // so their LDS loads are in flight together), then vw += M sum
+    const int cpad = (ccount + 7) & ~7;
+    auto row_of = [&](unsigned code) { return *reinterpret_cast<const float4*>(imp_base + (code & 0xfffeu)); };
+    auto add_row = [](f3 a, unsigned code, float4 val) {
+      const float sg = (code & 1u) ? 1.0f : -1.0f;
+      return mk(fmaf(sg, val.x, a.x), fmaf(sg, val.y, a.y), fmaf(sg, val.z, a.z));
+    };
+    // four entries per step so their LDS loads are in flight together
     auto apply_sums = [&]() {
-      if (!active) return;
-      f3 acc = mk(0, 0, 0);
-#pragma unroll
-      for (int k0 = 0; k0 < 8; k0 += 4) {
-        if (k0 < n_reg) {
-          float4 val[4];
+      if (!sum_on) return;
+      f3 a0 = mk(0, 0, 0), a1 = mk(0, 0, 0);
+      if (two) {
+        if (ccount > sh) {
           unsigned code[4];
+          float4 val[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            code[u] = (inc_reg[(k0 + u) >> 1] >> (16 * (u & 1))) & 0xffffu;
-            val[u] = *reinterpret_cast<const float4*>(imp_base + (code[u] & 0xfffeu));
+            code[u] = (creg[u >> 1] >> (16 * (u & 1))) & 0xffffu;
+            val[u] = row_of(code[u]);
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const float sg = (code[u] & 1u) ? 1.0f : -1.0f;
-            acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
+          for (int u = 0; u < 4; ++u) a0 = add_row(a0, code[u], val[u]);
+        }
+        for (int k = 8; k < cpad; k += 8) {
+          unsigned code[4];
+          float4 val[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) code[u] = s.inc[sp][cstart + k + sh + 2 * u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) val[u] = row_of(code[u]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a0 = add_row(a0, code[u], val[u]);
+        }
+        // the partner lane's partial sum (lane ^ 1)
+        a1 = mk(pair_swap(a0.x), pair_swap(a0.y), pair_swap(a0.z));
+      } else {
+#pragma unroll
+        for (int k0 = 0; k0 < 8; k0 += 4) {
+          if (k0 < ccount) {
+            unsigned code[4];
+            float4 val[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              code[u] = (creg[(k0 + u) >> 1] >> (16 * (u & 1))) & 0xffffu;
+              val[u] = row_of(code[u]);
+            }
+            a0 = add_row(a0, code[0], val[0]);
+            a1 = add_row(a1, code[1], val[1]);
+            a0 = add_row(a0, code[2], val[2]);
+            a1 = add_row(a1, code[3], val[3]);
           }
         }
-      }
-      // entries 8.. from the padded list in LDS, four at a time
-      for (int k = 8; k < inc_padded; k += 4) {
-        unsigned code[4];
-        float4 val[4];
+        for (int k = 8; k < cpad; k += 4) {
+          unsigned code[4];
+          float4 val[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) code[u] = s.inc[part][inc_start + k + u];
+          for (int u = 0; u < 4; ++u) code[u] = s.inc[sp][cstart + k + u];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) val[u] = *reinterpret_cast<const float4*>(imp_base + (code[u] & 0xfffeu));
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const float sg = (code[u] & 1u) ? 1.0f : -1.0f;
-          acc = mk(fmaf(sg, val[u].x, acc.x), fmaf(sg, val[u].y, acc.y), fmaf(sg, val[u].z, acc.z));
+          for (int u = 0; u < 4; ++u) val[u] = row_of(code[u]);
+          a0 = add_row(a0, code[0], val[0]);
+          a1 = add_row(a1, code[1], val[1]);
+          a0 = add_row(a0, code[2], val[2]);
+          a1 = add_row(a1, code[3], val[3]);
         }
       }
+      const f3 acc = mk(a0.x + a1.x, a0.y + a1.y, a0.z + a1.z);
       vw = mk(fmaf(md.x, acc.x, fmaf(mo.x, acc.y, fmaf(mo.y, acc.z, vw.x))),
               fmaf(mo.x, acc.x, fmaf(md.y, acc.y, fmaf(mo.z, acc.z, vw.y))),
               fmaf(mo.y, acc.x, fmaf(mo.z, acc.y, fmaf(md.z, acc.z, vw.z))));
@@ -1331,8 +1381,8 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     }
     sync_all<W>();
     apply_sums();
-    for (int it = 0; it < p.iters; ++it) {
-      if (active) st3(vw_slot, vw);
+    auto jacobi_pass = [&]() {
+      if (sum_store) st3(vw_slot, vw);
       sync_all<W>();   // the iteration-start velocities, and every wave done with the rows
 #pragma unroll
       for (int ls = 0; ls < KW; ++ls) {
@@ -1348,12 +1398,12 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
           q.ln = ln;
           float lt1 = q.lt1 - q.kt1 * dot(u, q.t1);
           float lt2 = q.lt2 - q.kt2 * dot(u, t2);
-          float lim = q.mu * ln, mag2 = lt1 * lt1 + lt2 * lt2;
-          if (mag2 > lim * lim) {
-            float sc = lim * rsq(mag2);
-            lt1 *= sc;
-            lt2 *= sc;
-          }
+          // onto the friction disc: scale by min(1, lim / |lt|) (a zero
+          // tangential impulse gives inf or nan, and the min keeps 1)
+          const float lim = q.mu * ln, mag2 = lt1 * lt1 + lt2 * lt2;
+          const float sc = fminf(lim * rsq(mag2), 1.0f);
+          lt1 *= sc;
+          lt2 *= sc;
           float dl1 = lt1 - q.lt1, dl2 = lt2 - q.lt2;
           q.lt1 = lt1;
           q.lt2 = lt2;
@@ -1365,9 +1415,15 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       }
       sync_all<W>();   // every wave's impulse rows
       apply_sums();
+    };
+    for (int it = 0; it < p.iters; ++it) jacobi_pass();
+    // the body lanes take the solved velocities back
+    if (sum_store) st3(vw_slot, vw);
+    sync_all<W>();
+    if (active) {
+      if (part == 0) v = xyz(s.vel[b]);
+      else w = xyz(s.ang[b]);
     }
-    if (part == 0) v = vw;
-    else w = vw;
     // remember this substep's accumulated impulses by key
 #pragma unroll
     for (int ls = 0; ls < KW; ++ls) {
