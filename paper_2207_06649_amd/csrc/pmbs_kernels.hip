@@ -298,9 +298,10 @@ __device__ __forceinline__ int lower_half(int v) { return __builtin_amdgcn_perml
 __device__ __forceinline__ int upper_half(int v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1]; }
 
 // Whole-wave shift by one lane (DPP wave_shl:1): lane l receives lane l + 1;
-// lane 63 receives +inf (a float) or the value's own bits (an int).
+// lane 63 receives 0 (a float) or the value's own bits (an int).  Callers
+// read only lanes below the object count (at most 33), never lane 63.
 __device__ __forceinline__ float wave_next(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0x7f800000, __float_as_int(v), 0x130, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 // value of lane ^ 1 (DPP quad permutation 1, 0, 3, 2)
 __device__ __forceinline__ float pair_swap(float v) {
@@ -792,9 +793,10 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
 
     // ---- 2. frames
     write_frames(vp);
-    wave_sync();
+    sync_all<W>();
 
-    // ---- 3.-4a. broadphase and table contacts: the lead wave only
+    // ---- 3.-4a. broadphase (the lead wave) and table contacts (the second
+    // wave when there are two, else the lead after the broadphase)
     int n_pairs = 0, nc_raw = 0;
     if (lead) {
       // ---- 3. broadphase: AABBs, rank sort on min-x, sweep
@@ -902,52 +904,52 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
         }
       }
       wave_sync();
+    }
 
-      // ---- 4a. box-plane contacts (body order, vertex order).  Corner kk
-      // of body b is tested by lane b when kk has an even number of set bits
-      // and by lane b + 32 otherwise, so every face's four corners split two
-      // and two; the body's two flag bytes give each corner its rank.
-      {
-        f3 c0 = mk(0, 0, 0), a0 = mk(0, 0, 0), a1 = mk(0, 0, 0), a2 = mk(0, 0, 0);
-        unsigned flags = 0;
-        if (active) {
-          c0 = xyz(s.pos[b]);
-          a0 = xyz(s.col[0][b]); a1 = xyz(s.col[1][b]); a2 = xyz(s.col[2][b]);
-  #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            // the j-th corner of this lane's parity class: 0, 3, 5, 6 or 1, 2, 4, 7
-            const int kk = part == 0 ? (0x6530 >> (4 * j)) & 15 : (0x7421 >> (4 * j)) & 15;
-            const float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
-            const float vz = c0.z + (a0.z * sx + a1.z * sy + a2.z * sz);
-            if (vz <= p.margin) flags |= 1u << kk;
-          }
+    // ---- 4a. box-plane contacts (body order, vertex order).  Corner kk
+    // of body b is tested by lane b when kk has an even number of set bits
+    // and by lane b + 32 otherwise, so every face's four corners split two
+    // and two; the body's two flag bytes give each corner its rank.
+    if (W == 1 || wid == 1) {
+      const bool on = b < nb;
+      const f3 hb = W == 1 ? h : (on ? xyz(s.half[b]) : mk(0, 0, 0));
+      f3 c0 = mk(0, 0, 0), a0 = mk(0, 0, 0), a1 = mk(0, 0, 0), a2 = mk(0, 0, 0);
+      unsigned flags = 0;
+      if (on) {
+        c0 = xyz(s.pos[b]);
+        a0 = xyz(s.col[0][b]); a1 = xyz(s.col[1][b]); a2 = xyz(s.col[2][b]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          // the j-th corner of this lane's parity class: 0, 3, 5, 6 or 1, 2, 4, 7
+          const int kk = part == 0 ? (0x6530 >> (4 * j)) & 15 : (0x7421 >> (4 * j)) & 15;
+          const float sx = (kk & 1) ? hb.x : -hb.x, sy = (kk & 2) ? hb.y : -hb.y, sz = (kk & 4) ? hb.z : -hb.z;
+          const float vz = c0.z + (a0.z * sx + a1.z * sy + a2.z * sz);
+          if (vz <= p.margin) flags |= 1u << kk;
         }
-        const unsigned both = (unsigned)(lower_half((int)flags) | upper_half((int)flags));
-        int total;
-        const int off0 = wave_excl_scan(part == 0 ? __popc(both) : 0, &total);
-        const int off = lower_half(off0);
-        while (flags) {
-          const int kk = __builtin_ctz(flags);
-          flags &= flags - 1;
-          float sx = (kk & 1) ? h.x : -h.x, sy = (kk & 2) ? h.y : -h.y, sz = (kk & 4) ? h.z : -h.z;
-          f3 vtx = c0 + mk(a0.x * sx + a1.x * sy + a2.x * sz, a0.y * sx + a1.y * sy + a2.y * sz,
-                           a0.z * sx + a1.z * sy + a2.z * sz);
-          const int c = off + __popc(both & ((1u << kk) - 1u));
-          if (c < C) {
-            s.u.stage[c][0] = f4(vtx - mk(0, 0, 0.5f * vtx.z), vtx.z);
-            s.u.stage[c][1] = make_float4(0, 0, 1, 0);
-            s.cab[c] = PLANE | (b << 8) | (kk << 16);
-          }
-        }
-        nc_raw = total;
       }
+      const unsigned both = (unsigned)(lower_half((int)flags) | upper_half((int)flags));
+      int total;
+      const int off0 = wave_excl_scan(part == 0 ? __popc(both) : 0, &total);
+      const int off = lower_half(off0);
+      while (flags) {
+        const int kk = __builtin_ctz(flags);
+        flags &= flags - 1;
+        float sx = (kk & 1) ? hb.x : -hb.x, sy = (kk & 2) ? hb.y : -hb.y, sz = (kk & 4) ? hb.z : -hb.z;
+        f3 vtx = c0 + mk(a0.x * sx + a1.x * sy + a2.x * sz, a0.y * sx + a1.y * sy + a2.y * sz,
+                         a0.z * sx + a1.z * sy + a2.z * sz);
+        const int c = off + __popc(both & ((1u << kk) - 1u));
+        if (c < C) {
+          s.u.stage[c][0] = f4(vtx - mk(0, 0, 0.5f * vtx.z), vtx.z);
+          s.u.stage[c][1] = make_float4(0, 0, 1, 0);
+          s.cab[c] = PLANE | (b << 8) | (kk << 16);
+        }
+      }
+      nc_raw = total;
     }
     if constexpr (W > 1) {
-      // every wave needs the pair list, the frames and the table contacts
-      if (lead && lane == 0) {
-        s.sh_pairs = n_pairs;
-        s.sh_plane = nc_raw;
-      }
+      // every wave needs the pair list and the table contacts
+      if (lead && lane == 0) s.sh_pairs = n_pairs;
+      if (wid == 1 && lane == 0) s.sh_plane = nc_raw;
       __syncthreads();
       n_pairs = s.sh_pairs;
       nc_raw = s.sh_plane;
