@@ -132,7 +132,10 @@ struct Smem {
   } u;
   float4 zero;                       // a row of zeros after the impulse rows (never written)
   union alignas(16) {
-    float cand[W][CLIP_GROUPS][16];         // narrowphase: axis candidates of each wave's eight groups
+    struct {
+      float v[CLIP_GROUPS][16];             // narrowphase: axis candidates of each wave's eight groups:
+      float ax[3][CLIP_GROUPS][16];         // separation value and unit axis (x, y, z rows)
+    } cand[W];
     float clip[W][2][POLY][3][CLIP_GROUPS]; // narrowphase: clip polygons of each wave's eight groups
     unsigned incm[NOBJ][2 * K];             // incidence build: contact bit masks per body
   } x;
@@ -976,10 +979,8 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       // candidate gl: 0-2 faces of A, 3-5 faces of B, 6-7 edge crosses A0 x B0, A0 x B1
       f3 L0;
       bool ok0 = has;
-      if (gl < 3) {
-        L0 = axis(A, gl);
-      } else if (gl < 6) {
-        L0 = axis(B, gl - 3);
+      if (gl < 6) {
+        L0 = lds_axis(s, gl < 3 ? ia : ib, gl < 3 ? gl : gl - 3);
       } else {
         const f3 v = cross(A.a0, axis(B, gl - 6));
         const float l2 = dot(v, v);
@@ -996,15 +997,22 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       const float sv1 = fabsf(dot(d, L1)) - radius_along(A, L1) - radius_along(B, L1);
       const unsigned long long gm = 0xffull << (8 * grp);
       const bool out = (__ballot((ok0 && sv0 > p.margin) || (ok1 && sv1 > p.margin)) & gm) != 0ull;
-      // the contact axis: the group's candidate values go to LDS at their
-      // candidate index (k < 8: lane k's first value, k >= 8: lane k - 8's
-      // second; an invalid candidate holds -inf), and every lane of the
+      // the contact axis: the group's candidates (separation value and unit
+      // axis) go to LDS at their candidate index (k < 8: lane k's first,
+      // k >= 8: lane k - 8's second; an invalid one holds -inf), and every lane of the
       // group scans the fifteen in order: the kept axis starts at candidate
       // 0 (a face of A, valid whenever the pair is) and is replaced only by
       // a later one that exceeds it by tau_face (faces) or tau_edge (edges)
-      float* const cv = &s.x.cand[wid][grp][0];
+      auto& cd = s.x.cand[wid];
+      float* const cv = &cd.v[grp][0];
       cv[gl] = ok0 ? sv0 : -INFINITY;
       cv[gl + 8] = ok1 ? sv1 : -INFINITY;
+      cd.ax[0][grp][gl] = L0.x;
+      cd.ax[1][grp][gl] = L0.y;
+      cd.ax[2][grp][gl] = L0.z;
+      cd.ax[0][grp][gl + 8] = L1.x;
+      cd.ax[1][grp][gl + 8] = L1.y;
+      cd.ax[2][grp][gl + 8] = L1.z;
       wave_sync();
       const float4 c0 = reinterpret_cast<const float4*>(cv)[0], c1 = reinterpret_cast<const float4*>(cv)[1];
       const float4 c2 = reinterpret_cast<const float4*>(cv)[2], c3 = reinterpret_cast<const float4*>(cv)[3];
@@ -1031,18 +1039,10 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       scan(c3.y, 13, p.tau_edge);
       scan(c3.z, 14, p.tau_edge);
       if (!has || out) best = -1;
-      // every lane of the group holds the pair's axis: its direction again
+      // every lane of the group takes the kept axis from LDS, pointing from A to B
       f3 n = mk(0, 0, 0);
       if (best >= 0) {
-        f3 Lb;
-        if (best < 3) {
-          Lb = axis(A, best);
-        } else if (best < 6) {
-          Lb = axis(B, best - 3);
-        } else {
-          const f3 v = cross(axis(A, (best - 6) / 3), axis(B, (best - 6) % 3));
-          Lb = v * rsq(dot(v, v));
-        }
+        const f3 Lb = mk(cd.ax[0][grp][best], cd.ax[1][grp][best], cd.ax[2][grp][best]);
         n = sel(dot(d, Lb) >= 0.0f, Lb, neg(Lb));
       }
       // face axis: reference face of the axis owner, incident face of the
