@@ -627,7 +627,8 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
 
   // ---- load (coalesced SoA): part 0 linear, part 1 angular; from the env
   // arrays or from the state pool slot of the node being expanded
-  f3 x = mk(0, 0, 0), v = mk(0, 0, 0), w = mk(0, 0, 0), h = mk(0, 0, 0), invI = mk(0, 0, 0);
+  // vl is the lane's own velocity: linear on part 0, angular on part 1
+  f3 x = mk(0, 0, 0), vl = mk(0, 0, 0), h = mk(0, 0, 0), invI = mk(0, 0, 0);
   float q0 = 1, q1 = 0, q2 = 0, q3 = 0, invm = 0, mu = 0;
   if (active) {
     const int i = base + b;
@@ -639,11 +640,11 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     const int bi = g.bc_base ? g.bc_base[e] + b : i;
     if (part == 0) {
       x = mk(st[0 * SN + si], st[1 * SN + si], st[2 * SN + si]);
-      v = mk(st[7 * SN + si], st[8 * SN + si], st[9 * SN + si]);
+      vl = mk(st[7 * SN + si], st[8 * SN + si], st[9 * SN + si]);
       invm = bc[3 * BN + bi];
     } else {
       q0 = st[3 * SN + si]; q1 = st[4 * SN + si]; q2 = st[5 * SN + si]; q3 = st[6 * SN + si];
-      w = mk(st[10 * SN + si], st[11 * SN + si], st[12 * SN + si]);
+      vl = mk(st[10 * SN + si], st[11 * SN + si], st[12 * SN + si]);
       invI = mk(bc[4 * BN + bi], bc[5 * BN + bi], bc[6 * BN + bi]);
     }
     h = mk(bc[0 * BN + bi], bc[1 * BN + bi], bc[2 * BN + bi]);
@@ -657,9 +658,9 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       if (part == 0) {
         s.pos[b] = f4(x, 0.0f);
         s.half[b] = f4(h, invm);
-        s.vel[b] = f4(v, 0.0f);
+        s.vel[b] = f4(vl, 0.0f);
       } else {
-        s.ang[b] = f4(w, 0.0f);
+        s.ang[b] = f4(vl, 0.0f);
         f3 c0, c1, c2;
         quat_cols(q0, q1, q2, q3, &c0, &c1, &c2);
         const float r00 = c0.x, r01 = c1.x, r02 = c2.x;
@@ -789,7 +790,7 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
   int nwarm = 0;  // impulses are carried within one push only
   for (int k = 0; k < n_sub; ++k) {
     // ---- 1. velocity stage
-    if (active && part == 0) v.z -= p.gravity * dt;
+    if (active && part == 0) vl.z -= p.gravity * dt;
     const float vs = (valid && k < n_move) ? p.push_speed : 0.0f;
     f3 vp = pdir * vs;
     if (g.collide_only) vp = mk(0, 0, 0);
@@ -1263,12 +1264,18 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     const bool sum_store = sum_on && sh == 0;
     float4* const vw_slot = sp == 0 ? &s.vel[sb] : &s.ang[sb];
     f3 vw = mk(0, 0, 0), md = mk(0, 0, 0), mo = mk(0, 0, 0);
-    // the first entries of the list stay in registers for the whole solve as
-    // 16-bit row codes (a pair lane: its entries sh, sh + 2, sh + 4, sh + 6;
-    // a single lane: entries 0..7), so a load needs no index arithmetic;
-    // past the end of a list the padding codes point at the zero row with
-    // side 0, whose term is -0 and leaves every sum unchanged
-    unsigned creg[4] = {zcode | (zcode << 16), zcode | (zcode << 16), zcode | (zcode << 16), zcode | (zcode << 16)};
+    // four entries of the list stay in registers for the whole solve as row
+    // byte offsets and signs (a pair lane: its entries sh, sh + 2, sh + 4,
+    // sh + 6; a single lane: entries 0-3), so their loads need no index
+    // arithmetic; slots past the end of a list point at the zero row, whose
+    // term leaves every sum unchanged
+    unsigned radr[4];
+    float rsg[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      radr[u] = zcode;
+      rsg[u] = -1.0f;
+    }
     int ccount = 0, cstart = 0;
     if (sum_on) {
       vw = xyz(*vw_slot);
@@ -1283,42 +1290,32 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       ccount = s.cnt[sb];
       cstart = s.lstart[sb];
       if (ccount > 0) {   // the list holds at least 8 entries (padding included)
-        if (two) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const unsigned code = s.inc[sp][cstart + sh + 2 * u];
-            creg[u >> 1] = u & 1 ? (creg[u >> 1] & 0xffffu) | (code << 16) : (creg[u >> 1] & 0xffff0000u) | code;
-          }
-        } else {
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const unsigned code = s.inc[sp][cstart + u];
-            creg[u >> 1] = u & 1 ? (creg[u >> 1] & 0xffffu) | (code << 16) : (creg[u >> 1] & 0xffff0000u) | code;
-          }
+        for (int u = 0; u < 4; ++u) {
+          const unsigned code = s.inc[sp][cstart + (two ? sh + 2 * u : u)];
+          radr[u] = code & 0xfffeu;
+          rsg[u] = (code & 1u) ? 1.0f : -1.0f;
         }
       }
     }
     const int cpad = (ccount + 7) & ~7;
     auto row_of = [&](unsigned code) { return *reinterpret_cast<const float4*>(imp_base + (code & 0xfffeu)); };
-    auto add_row = [](f3 a, unsigned code, float4 val) {
-      const float sg = (code & 1u) ? 1.0f : -1.0f;
+    auto reg_row = [&](unsigned off) { return *reinterpret_cast<const float4*>(imp_base + off); };
+    auto add_signed = [](f3 a, float sg, float4 val) {
       return mk(fmaf(sg, val.x, a.x), fmaf(sg, val.y, a.y), fmaf(sg, val.z, a.z));
     };
+    auto add_row = [&](f3 a, unsigned code, float4 val) { return add_signed(a, (code & 1u) ? 1.0f : -1.0f, val); };
     // four entries per step so their LDS loads are in flight together
     auto apply_sums = [&]() {
       if (!sum_on) return;
       f3 a0 = mk(0, 0, 0), a1 = mk(0, 0, 0);
       if (two) {
         if (ccount > sh) {
-          unsigned code[4];
           float4 val[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            code[u] = (creg[u >> 1] >> (16 * (u & 1))) & 0xffffu;
-            val[u] = row_of(code[u]);
-          }
+          for (int u = 0; u < 4; ++u) val[u] = reg_row(radr[u]);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) a0 = add_row(a0, code[u], val[u]);
+          for (int u = 0; u < 4; ++u) a0 = add_signed(a0, rsg[u], val[u]);
         }
         for (int k = 8; k < cpad; k += 8) {
           unsigned code[4];
@@ -1333,23 +1330,18 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
         // the partner lane's partial sum (lane ^ 1)
         a1 = mk(pair_swap(a0.x), pair_swap(a0.y), pair_swap(a0.z));
       } else {
+        if (ccount > 0) {
+          float4 val[4];
 #pragma unroll
-        for (int k0 = 0; k0 < 8; k0 += 4) {
-          if (k0 < ccount) {
-            unsigned code[4];
-            float4 val[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              code[u] = (creg[(k0 + u) >> 1] >> (16 * (u & 1))) & 0xffffu;
-              val[u] = row_of(code[u]);
-            }
-            a0 = add_row(a0, code[0], val[0]);
-            a1 = add_row(a1, code[1], val[1]);
-            a0 = add_row(a0, code[2], val[2]);
-            a1 = add_row(a1, code[3], val[3]);
-          }
+          for (int u = 0; u < 4; ++u) val[u] = reg_row(radr[u]);
+          a0 = add_signed(a0, rsg[0], val[0]);
+          a1 = add_signed(a1, rsg[1], val[1]);
+          a0 = add_signed(a0, rsg[2], val[2]);
+          a1 = add_signed(a1, rsg[3], val[3]);
         }
-        for (int k = 8; k < cpad; k += 4) {
+        // entries 4.. from the list in LDS (entries 4-7 add nothing to a
+        // list of at most four)
+        for (int k = 4; k < (ccount > 4 ? cpad : 0); k += 4) {
           unsigned code[4];
           float4 val[4];
 #pragma unroll
@@ -1423,8 +1415,7 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     if (sum_store) st3(vw_slot, vw);
     sync_all<W>();
     if (active) {
-      if (part == 0) v = xyz(s.vel[b]);
-      else w = xyz(s.ang[b]);
+      vl = xyz(part == 0 ? s.vel[b] : s.ang[b]);
     }
     // remember this substep's accumulated impulses by key
 #pragma unroll
@@ -1442,8 +1433,9 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     // ---- 8. position stage
     if (active) {
       if (part == 0) {
-        x = fma3(v, dt, x);
+        x = fma3(vl, dt, x);
       } else {
+        const f3 w = vl;
         float dw = -(w.x * q1 + w.y * q2 + w.z * q3);
         float dx = q0 * w.x + (w.y * q3 - w.z * q2);
         float dy = q0 * w.y + (w.z * q1 - w.x * q3);
@@ -1486,10 +1478,10 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       float* dst = g.pool + (size_t)cs * 13 * PS + opaque(b);
       if (part == 0) {
         dst[0 * PS] = x.x; dst[1 * PS] = x.y; dst[2 * PS] = x.z;
-        dst[7 * PS] = v.x; dst[8 * PS] = v.y; dst[9 * PS] = v.z;
+        dst[7 * PS] = vl.x; dst[8 * PS] = vl.y; dst[9 * PS] = vl.z;
       } else {
         dst[3 * PS] = q0; dst[4 * PS] = q1; dst[5 * PS] = q2; dst[6 * PS] = q3;
-        dst[10 * PS] = w.x; dst[11 * PS] = w.y; dst[12 * PS] = w.z;
+        dst[10 * PS] = vl.x; dst[11 * PS] = vl.y; dst[12 * PS] = vl.z;
       }
     }
     sync_all<W>();   // every wave has read the frames before they change
@@ -1509,10 +1501,10 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     const float* st = g.pool + (size_t)g.x_desc[e].x * 13 * PS + opaque(b);
     if (part == 0) {
       x = mk(st[0 * PS], st[1 * PS], st[2 * PS]);
-      v = mk(st[7 * PS], st[8 * PS], st[9 * PS]);
+      vl = mk(st[7 * PS], st[8 * PS], st[9 * PS]);
     } else {
       q0 = st[3 * PS]; q1 = st[4 * PS]; q2 = st[5 * PS]; q3 = st[6 * PS];
-      w = mk(st[10 * PS], st[11 * PS], st[12 * PS]);
+      vl = mk(st[10 * PS], st[11 * PS], st[12 * PS]);
     }
   }
   }  // jobs
@@ -1544,13 +1536,13 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     float* st = g.state;
     if (part == 0) {
       st[0 * N + i] = x.x; st[1 * N + i] = x.y; st[2 * N + i] = x.z;
-      st[7 * N + i] = v.x; st[8 * N + i] = v.y; st[9 * N + i] = v.z;
-      bad = !(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z));
+      st[7 * N + i] = vl.x; st[8 * N + i] = vl.y; st[9 * N + i] = vl.z;
+      bad = !(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(vl.x) && isfinite(vl.y) && isfinite(vl.z));
     } else {
       st[3 * N + i] = q0; st[4 * N + i] = q1; st[5 * N + i] = q2; st[6 * N + i] = q3;
-      st[10 * N + i] = w.x; st[11 * N + i] = w.y; st[12 * N + i] = w.z;
-      bad = !(isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3) && isfinite(w.x) && isfinite(w.y) &&
-              isfinite(w.z));
+      st[10 * N + i] = vl.x; st[11 * N + i] = vl.y; st[12 * N + i] = vl.z;
+      bad = !(isfinite(q0) && isfinite(q1) && isfinite(q2) && isfinite(q3) && isfinite(vl.x) && isfinite(vl.y) &&
+              isfinite(vl.z));
     }
   }
   if (__ballot(bad) != 0) status |= PMBS_ENV_NONFINITE;
