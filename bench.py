@@ -141,7 +141,8 @@ def plan_latency(pmbs, scenes, args) -> dict:
     sim.set_state(tb.env_offset, tb.state, tb.body)
     t_acts, t_off = scenes.contour_actions(7, tb.counts(), np.full(leaves, depth))
     t0 = time.perf_counter()
-    tuned, tuned_ms, _ = sim.autotune(t_acts, t_off, np.zeros(leaves, np.int32), n_substeps=120, max_h=depth, reps=3)
+    tuned, tuned_ms, _ = sim.autotune(t_acts, t_off, np.zeros(leaves, np.int32), n_substeps=120, max_h=depth, reps=3,
+                                      flags=pmbs.ROLLOUT_QUEUE)
     tune_s = time.perf_counter() - t0
     print(f"# plan launch plan {tuned} ({tuned_ms:.1f} ms per rollout, {tune_s:.1f} s of tuning)", file=sys.stderr,
           flush=True)
@@ -296,7 +297,7 @@ def uneven_batching(pmbs, scenes, args) -> dict:
     cnt = torch.empty(E, dtype=torch.int32, device=dev)
     t1 = time.perf_counter()
     plan, tune_ms, _ = sim.autotune(acts, off, tgt, n_substeps=sub, src_slot=src, child_slot=child, max_h=H,
-                                    reps=3, rewards=rew, counts=cnt)
+                                    reps=3, rewards=rew, counts=cnt, flags=pmbs.ROLLOUT_QUEUE)
     tune_s = time.perf_counter() - t1
     print(f"# autotuned plan {plan} ({tune_ms:.1f} ms per launch, {tune_s:.1f} s of tuning)",
           file=sys.stderr, flush=True)

@@ -197,7 +197,9 @@ pmbs_status pmbs_sim_get_launch_plan(const pmbs_sim_t* sim, pmbs_launch_plan* pl
  * pmbs_sim_rollout; PMBS_ROLLOUT_WRITE_STATE is refused because every
  * candidate re-runs the rollout from the same inputs).  Candidates are timed
  * with HIP events on the simulator's stream, reps runs each, by coordinate
- * descent over small_max_bodies, blocks per CU and order; the fastest plan
+ * descent over small_max_bodies and the waves per environment of each class
+ * (two passes), then blocks per CU and order; the three fastest candidates
+ * are timed again with at least five runs each, and the fastest plan
  * (median time) is installed and returned with its time in milliseconds.
  * cache_path (optional) names a text file of earlier results keyed by the
  * device, the library build, the configuration and a histogram of the

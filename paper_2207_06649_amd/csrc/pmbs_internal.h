@@ -21,7 +21,7 @@ struct pmbs_sim {
   float* d_reward;
   float* d_clearance;
   int32_t* d_slots;     // [max_envs] pool slots of the current gather/scatter
-  long long* d_stats;   // [max_envs][2]
+  long long* d_stats;   // [max_envs][3]
   float* d_pool;        // [pool_slots][13][pool_stride]
   int32_t *d_actions, *d_act_offset, *d_src_slot, *d_child_slot, *d_order;
   float* d_roll_rewards;   // [max_envs][max_horizon] rollout rewards of the planner

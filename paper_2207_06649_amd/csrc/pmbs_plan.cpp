@@ -71,24 +71,66 @@ pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_stat
   std::vector<int32_t> slots(E, -1);
   slots[0] = 0;
   if ((s = pmbs_pool_scatter(sim, slots.data(), 0)) != PMBS_OK) return s;
+  // Per-iteration transfers go through one block of pinned host memory:
+  // copies to and from it are DMA transfers queued on the stream, where a
+  // pageable copy is staged and holds the host for each array.  The host
+  // writes the select outputs only after the previous iteration's
+  // synchronisation, so no queued copy still reads them.
+  size_t total = 0;
+  const size_t ED = (size_t)E * D;
+  const size_t bytes[] = {ED * 4, (size_t)(E + 1) * 4, (size_t)E * 4, (size_t)E * 4, (size_t)E * 4, (size_t)E * 4,
+                          ED * 4, ED * 4, (size_t)E * 4, (size_t)E * 4, (size_t)E * 4, (size_t)E * 4,
+                          (size_t)E * 4, (size_t)E * 4, (size_t)E * 8, (size_t)E * 4, (size_t)E * 24,
+                          (size_t)E * PMBS_VALID_WORDS * 4};
+  for (size_t b : bytes) total += (b + 255) & ~size_t(255);
+  struct Pinned {
+    char* p = nullptr;
+    ~Pinned() {
+      if (p) (void)hipHostFree(p);
+    }
+  } pin;
+  hipError_t he = hipHostMalloc(reinterpret_cast<void**>(&pin.p), total, hipHostMallocDefault);
+  if (he != hipSuccess) return hip_fail(he, "plan host buffers");
+  size_t at = 0;
+  int k_buf = 0;
+  auto take = [&]() {
+    char* q = pin.p + at;
+    at += (bytes[k_buf++] + 255) & ~size_t(255);
+    return q;
+  };
+  int32_t* const actions = reinterpret_cast<int32_t*>(take());
+  int32_t* const act_off = reinterpret_cast<int32_t*>(take());
+  int32_t* const src = reinterpret_cast<int32_t*>(take());
+  int32_t* const child = reinterpret_cast<int32_t*>(take());
+  int32_t* const tgt = reinterpret_cast<int32_t*>(take());
+  int32_t* const counts = reinterpret_cast<int32_t*>(take());
+  float* const rewards = reinterpret_cast<float*>(take());
+  float* const x_rewards = reinterpret_cast<float*>(take());
+  int32_t* const x_src = reinterpret_cast<int32_t*>(take());
+  int32_t* const x_act = reinterpret_cast<int32_t*>(take());
+  int32_t* const x_node = reinterpret_cast<int32_t*>(take());
+  int32_t* const x_rep = reinterpret_cast<int32_t*>(take());
+  int32_t* const x_hor = reinterpret_cast<int32_t*>(take());
+  int32_t* const x_counts = reinterpret_cast<int32_t*>(take());
+  uint64_t* const x_seed = reinterpret_cast<uint64_t*>(take());
+  uint32_t* const status = reinterpret_cast<uint32_t*>(take());
+  int64_t* const stats = reinterpret_cast<int64_t*>(take());
+  uint32_t* const valid = reinterpret_cast<uint32_t*>(take());
+  for (int e = 0; e < E; ++e) {
+    tgt[e] = target;
+    x_seed[e] = tc.seed;
+  }
   // the root's sampled pushes that cannot start are discarded before any
   // selection (Sec. IV-B), from the validity words of the device
-  std::vector<uint32_t> valid((size_t)E * PMBS_VALID_WORDS);
   if (tc.discard) {
     int32_t nn = 0;
     if ((s = pmbs_tree_size(tree, &nn, nullptr, nullptr)) != PMBS_OK) return s;
     if (nn != 1) return fail(PMBS_ERR_INVALID_ARG, "pmbs_plan with discard needs a fresh tree");
     if ((s = pmbs_sim_valid_pushes(sim, slots.data(), 0)) != PMBS_OK) return s;
-    if ((s = pmbs_sim_push_valid(sim, valid.data(), 0)) != PMBS_OK) return s;
-    if ((s = pmbs_tree_set_valid(tree, 0, valid.data())) != PMBS_OK) return s;
+    if ((s = pmbs_sim_push_valid(sim, valid, 0)) != PMBS_OK) return s;
+    if ((s = pmbs_tree_set_valid(tree, 0, valid)) != PMBS_OK) return s;
   }
 
-  std::vector<int32_t> actions((size_t)E * D), act_off(E + 1), src(E), child(E), tgt(E, target), counts(E);
-  std::vector<float> rewards((size_t)E * D), x_rewards((size_t)E * D);
-  std::vector<int32_t> x_src(E), x_act(E), x_node(E), x_rep(E), x_hor(E), x_counts(E);
-  std::vector<uint64_t> x_seed(E, tc.seed);
-  std::vector<uint32_t> status(E);
-  std::vector<int64_t> stats((size_t)E * 3);
   int it = 0;
   int64_t env_substeps = 0;
   for (; it < iters; ++it) {
@@ -96,54 +138,45 @@ pmbs_status pmbs_plan(pmbs_sim_t* sim, pmbs_tree_t* tree, const float* root_stat
     if ((s = pmbs_tree_status(tree, &done, nullptr, nullptr, nullptr)) != PMBS_OK) return s;
     if (done) break;
     int32_t n_pairs = 0, n_envs = 0;
-    if ((s = pmbs_tree_select(tree, &n_pairs, actions.data(), act_off.data(), src.data(), child.data(), &n_envs)) !=
-        PMBS_OK)
+    if ((s = pmbs_tree_select(tree, &n_pairs, actions, act_off, src, child, &n_envs)) != PMBS_OK)
       return s;
     if (n_pairs == 0) break;
     pmbs_repurpose rp{};
     if (tc.repurpose) {
-      if ((s = pmbs_tree_extra(tree, x_src.data(), x_act.data(), x_node.data(), x_rep.data(), x_hor.data())) !=
-          PMBS_OK)
-        return s;
-      rp.src_slot = x_src.data();
-      rp.action = x_act.data();
-      rp.node_id = x_node.data();
-      rp.replica = x_rep.data();
-      rp.horizon = x_hor.data();
-      rp.seed = x_seed.data();
+      if ((s = pmbs_tree_extra(tree, x_src, x_act, x_node, x_rep, x_hor)) != PMBS_OK) return s;
+      rp.src_slot = x_src;
+      rp.action = x_act;
+      rp.node_id = x_node;
+      rp.replica = x_rep;
+      rp.horizon = x_hor;
+      rp.seed = x_seed;
       rp.d_rewards = sim->d_x_rewards;
       rp.d_counts = sim->d_x_counts;
     }
-    if ((s = pmbs_sim_rollout_ex(sim, actions.data(), act_off.data(), src.data(), child.data(), tgt.data(), 0,
+    if ((s = pmbs_sim_rollout_ex(sim, actions, act_off, src, child, tgt, 0,
                                  n_substeps, width, sim->d_roll_rewards, D, sim->d_roll_counts,
                                  PMBS_ROLLOUT_QUEUE | (tc.discard ? PMBS_ROLLOUT_CHILD_VALID : 0),
                                  tc.repurpose ? &rp : nullptr)) != PMBS_OK)
       return s;
-    hipError_t e = hipMemcpyAsync(rewards.data(), sim->d_roll_rewards, rewards.size() * sizeof(float),
-                                  hipMemcpyDeviceToHost, sim->stream);
+    hipError_t e = hipMemcpyAsync(rewards, sim->d_roll_rewards, ED * sizeof(float), hipMemcpyDeviceToHost, sim->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(counts.data(), sim->d_roll_counts, counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
-                         sim->stream);
+      e = hipMemcpyAsync(counts, sim->d_roll_counts, (size_t)E * sizeof(int32_t), hipMemcpyDeviceToHost, sim->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(status.data(), sim->d_status, status.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                         sim->stream);
+      e = hipMemcpyAsync(status, sim->d_status, (size_t)E * sizeof(uint32_t), hipMemcpyDeviceToHost, sim->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(stats.data(), sim->d_stats, stats.size() * sizeof(int64_t), hipMemcpyDeviceToHost, sim->stream);
+      e = hipMemcpyAsync(stats, sim->d_stats, (size_t)E * 3 * sizeof(int64_t), hipMemcpyDeviceToHost, sim->stream);
     if (e == hipSuccess && tc.repurpose)
-      e = hipMemcpyAsync(x_rewards.data(), sim->d_x_rewards, x_rewards.size() * sizeof(float), hipMemcpyDeviceToHost,
-                         sim->stream);
+      e = hipMemcpyAsync(x_rewards, sim->d_x_rewards, ED * sizeof(float), hipMemcpyDeviceToHost, sim->stream);
     if (e == hipSuccess && tc.repurpose)
-      e = hipMemcpyAsync(x_counts.data(), sim->d_x_counts, x_counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
-                         sim->stream);
+      e = hipMemcpyAsync(x_counts, sim->d_x_counts, (size_t)E * sizeof(int32_t), hipMemcpyDeviceToHost, sim->stream);
     if (e == hipSuccess && tc.discard)
-      e = hipMemcpyAsync(valid.data(), sim->d_valid, valid.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+      e = hipMemcpyAsync(valid, sim->d_valid, (size_t)E * PMBS_VALID_WORDS * sizeof(uint32_t), hipMemcpyDeviceToHost,
                          sim->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sim->stream);
     if (e != hipSuccess) return hip_fail(e, "plan readback");
     for (int k = 0; k < E; ++k) env_substeps += stats[(size_t)3 * k + 2];
-    if ((s = pmbs_tree_update_ex(tree, rewards.data(), D, counts.data(), status.data(),
-                                 tc.repurpose ? x_rewards.data() : nullptr, tc.repurpose ? x_counts.data() : nullptr,
-                                 tc.discard ? valid.data() : nullptr, nullptr)) != PMBS_OK)
+    if ((s = pmbs_tree_update_ex(tree, rewards, D, counts, status, tc.repurpose ? x_rewards : nullptr,
+                                 tc.repurpose ? x_counts : nullptr, tc.discard ? valid : nullptr, nullptr)) != PMBS_OK)
       return s;
   }
   int32_t a = -1;
