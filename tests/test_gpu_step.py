@@ -346,6 +346,46 @@ def test_clutter_settle_energy(pm):
     assert np.all(E < E0), (E - E0).max()
 
 
+def touching_cubes(layout, h=0.02, mass=0.1, mu=0.5):
+    """Equal cubes on the table with faces touching: "grid" is a 3 x 3 block
+    (the centre cube has 36 contacts), "rows" is 17 cubes, five rows of three
+    and a pair (a middle cube has 12): lists longer than the register-held
+    entries of the per-body sums."""
+    if layout == "grid":
+        xy = [((i - 1) * 2 * h, (j - 1) * 2 * h) for i in range(3) for j in range(3)]
+    else:
+        xy = [(k * 8 * h + d * 2 * h, 0.0) for k in range(5) for d in range(3)] + [(0.0, 6 * h), (2 * h, 6 * h)]
+    rows = [srow((x, y, h)) for x, y in xy]
+    return single(rows, [[h, h, h, mass, mu]] * len(rows))
+
+
+@pytest.mark.parametrize("layout,mc", [("grid", 128), ("rows", 128)])
+def test_long_incidence_lists(pm, layout, mc):
+    """Per-body sums over lists longer than the register-held entries: 9
+    cubes (one wave sums on lane pairs) and 17 cubes (one wave sums on
+    single lanes, more than 16 cuboids).  One substep matches the oracle to
+    the one-substep bars, and twenty substeps are bitwise the same with one
+    and with two waves per environment (lane pairs on both waves)."""
+    b = touching_cubes(layout)
+    c, _ = O.collide(CFG, f32(b.state), f32(b.body))
+    assert len(c) <= mc
+    per_body = np.bincount(np.concatenate([c[c[:, 0] >= 0, 0], c[:, 1]]).astype(int), minlength=b.n_bodies)
+    assert per_body.max() > 8, per_body
+    g, status, _ = run_gpu(pm, b, FAR, 1, max_contacts=mc)
+    o, _, _ = run_oracle(b, FAR, 1)
+    compare(g, o, 1e-5, 1e-5, 1e-4)
+    assert status[0] == 0
+    out = {}
+    for w in (1, 2):
+        sim = pm.Sim(max_envs=1, max_bodies=b.n_bodies, max_contacts=mc)
+        sim.set_launch_plan(small_waves=w, large_waves=w)
+        sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+        sim.step(FAR.astype(np.float32).reshape(1, 4), 20)
+        out[w] = (sim.get_state(), sim.env_status().copy())
+    assert np.array_equal(out[1][0], out[2][0]) and np.array_equal(out[1][1], out[2][1])
+    assert out[1][1][0] == 0
+
+
 def test_contact_capacity_classes_agree(pm):
     """The 128-, 256- and 512-contact kernels run the same algorithm in the
     same order, and multiply-adds are fused only where the source says so,
