@@ -49,6 +49,13 @@ struct pmbs_sim {
   pmbs::StepArgs graph_args;
   pmbs_launch_plan graph_plan;
   int graph_valid = 0;   // the captured sequence ends with the children's validity launch
+  // pinned staging of host rollout inputs: two buffers used in turn, each
+  // reusable once the event behind its last uploads has passed
+  char* h_stage[2] = {nullptr, nullptr};
+  size_t h_stage_bytes = 0;
+  hipEvent_t ev_stage[2] = {nullptr, nullptr};
+  bool stage_used[2] = {false, false};
+  int stage_k = 0;
   int32_t n_envs, n_bodies;
   std::vector<int32_t> host_offset;
   bool pool_layout = false;   // envs live only in pool slots, body constants at d_bc_base rows

@@ -445,6 +445,11 @@ StepArgs step_args(pmbs_sim_t* sim) {
 }  // namespace pmbs
 
 pmbs_sim::~pmbs_sim() {
+  for (int k = 0; k < 2; ++k) {
+    if (stage_used[k] && ev_stage[k]) (void)hipEventSynchronize(ev_stage[k]);
+    if (h_stage[k]) (void)hipHostFree(h_stage[k]);
+    if (ev_stage[k]) (void)hipEventDestroy(ev_stage[k]);
+  }
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -668,6 +673,47 @@ pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_de
   return PMBS_OK;
 }
 
+// Host rollout inputs go through one of two pinned staging buffers of the
+// simulator, used in turn: copies from pinned memory are DMA transfers
+// queued on the stream, so a call returns without waiting for them (a
+// pageable copy is staged by the runtime and holds the host for each
+// array).  A buffer is rewritten only after the event recorded behind its
+// previous uploads has passed.
+static pmbs_status stage_begin(pmbs_sim_t* sim, size_t bytes, char** base) {
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    if (!sim->ev_stage[k]) e = hipEventCreateWithFlags(&sim->ev_stage[k], hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "staging event");
+  if (bytes > sim->h_stage_bytes) {
+    for (int k = 0; k < 2; ++k) {
+      if (sim->stage_used[k] && (e = hipEventSynchronize(sim->ev_stage[k])) != hipSuccess)
+        return hip_fail(e, "staging wait");
+      sim->stage_used[k] = false;
+      if (sim->h_stage[k]) (void)hipHostFree(sim->h_stage[k]);
+      sim->h_stage[k] = nullptr;
+    }
+    sim->h_stage_bytes = 0;
+    const size_t grow = (bytes + 65535) & ~size_t(65535);
+    for (int k = 0; k < 2; ++k)
+      if ((e = hipHostMalloc(reinterpret_cast<void**>(&sim->h_stage[k]), grow, hipHostMallocDefault)) != hipSuccess)
+        return hip_fail(e, "staging buffers");
+    sim->h_stage_bytes = grow;
+  }
+  const int k = sim->stage_k;
+  if (sim->stage_used[k] && (e = hipEventSynchronize(sim->ev_stage[k])) != hipSuccess) return hip_fail(e, "staging wait");
+  *base = sim->h_stage[k];
+  return PMBS_OK;
+}
+
+static pmbs_status stage_end(pmbs_sim_t* sim) {
+  const int k = sim->stage_k;
+  const hipError_t e = hipEventRecord(sim->ev_stage[k], sim->stream);
+  if (e != hipSuccess) return hip_fail(e, "staging event");
+  sim->stage_used[k] = true;
+  sim->stage_k = 1 - k;
+  return PMBS_OK;
+}
+
 // upload a host array into a workspace region (or pass a device array through)
 static pmbs_status stage_ints(pmbs_sim_t* sim, const int32_t* src, size_t n, int32_t on_device, int32_t* region,
                               const int32_t** out) {
@@ -746,52 +792,73 @@ pmbs_status pmbs_sim_rollout_ex(pmbs_sim_t* sim, const int32_t* actions, const i
   }
   if (n == 0) return PMBS_OK;
   StepArgs a = step_args(sim);
-  const int32_t* p;
-  pmbs_status st;
-  if ((st = stage_ints(sim, actions, (size_t)total, inputs_on_device, sim->d_actions, &p)) != PMBS_OK) return st;
-  a.actions = p;
-  if ((st = stage_ints(sim, act_offset, (size_t)n + 1, inputs_on_device, sim->d_act_offset, &p)) != PMBS_OK) return st;
-  a.act_offset = p;
-  if ((st = stage_ints(sim, src_slot, (size_t)n, inputs_on_device, sim->d_src_slot, &p)) != PMBS_OK) return st;
-  a.src_slot = p;
-  if ((st = stage_ints(sim, child_slot, (size_t)n, inputs_on_device, sim->d_child_slot, &p)) != PMBS_OK) return st;
-  a.child_slot = p;
-  if ((st = stage_ints(sim, target, (size_t)n, inputs_on_device, sim->d_target, &p)) != PMBS_OK) return st;
-  a.target = p;
   const int32_t counts[2] = {(int32_t)order.size(), (int32_t)order_large.size()};
-  if (use_queue) {
-    if ((st = stage_ints(sim, order.data(), order.size(), 0, sim->d_order, &p)) != PMBS_OK) return st;
-    if ((st = stage_ints(sim, order_large.data(), order_large.size(), 0, sim->d_order + sim->cfg.max_envs, &p)) !=
-        PMBS_OK)
-      return st;
-    if ((st = stage_ints(sim, counts, 2, 0, sim->d_ctl + 8, &p)) != PMBS_OK) return st;
-  }
-  std::vector<int32_t> xdesc;
-  std::vector<uint32_t> xkey;
-  if (rp && n > 0) {
-    xdesc.resize((size_t)4 * n);
-    xkey.resize((size_t)2 * n);
-    for (int e = 0; e < n; ++e) {
-      xdesc[4 * e + 0] = rp->src_slot[e];
-      xdesc[4 * e + 1] = rp->action[e];
-      xdesc[4 * e + 2] = rp->node_id[e];
-      xdesc[4 * e + 3] = (int32_t)((uint32_t)rp->replica[e] | ((uint32_t)(rp->horizon ? rp->horizon[e] : 255) << 24));
-      xkey[2 * e + 0] = (uint32_t)rp->seed[e];
-      xkey[2 * e + 1] = (uint32_t)(rp->seed[e] >> 32);
+  if (inputs_on_device) {
+    a.actions = actions;
+    a.act_offset = act_offset;
+    a.src_slot = src_slot;
+    a.child_slot = child_slot;
+    a.target = target;
+  } else {
+    // host inputs through the simulator's pinned staging (queued DMA
+    // copies; the caller's arrays may be reused as soon as this returns)
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t n4 = (size_t)n * sizeof(int32_t);
+    size_t bytes = al((size_t)total * sizeof(int32_t)) + al(n4 + sizeof(int32_t)) + 3 * al(n4) + al(2 * sizeof(int32_t));
+    if (use_queue) bytes += al(order.size() * sizeof(int32_t)) + al(order_large.size() * sizeof(int32_t));
+    if (rp) bytes += al(4 * n4) + al(2 * n4);
+    char* base = nullptr;
+    pmbs_status st = stage_begin(sim, bytes, &base);
+    if (st != PMBS_OK) return st;
+    size_t at = 0;
+    hipError_t e = hipSuccess;
+    auto put = [&](const void* src, size_t nb, void* dst) {
+      if (e != hipSuccess || nb == 0) return;
+      std::memcpy(base + at, src, nb);
+      e = hipMemcpyAsync(dst, base + at, nb, hipMemcpyHostToDevice, sim->stream);
+      at += al(nb);
+    };
+    put(actions, (size_t)total * sizeof(int32_t), sim->d_actions);
+    a.actions = sim->d_actions;
+    put(act_offset, n4 + sizeof(int32_t), sim->d_act_offset);
+    a.act_offset = sim->d_act_offset;
+    if (src_slot) put(src_slot, n4, sim->d_src_slot);
+    a.src_slot = src_slot ? sim->d_src_slot : nullptr;
+    if (child_slot) put(child_slot, n4, sim->d_child_slot);
+    a.child_slot = child_slot ? sim->d_child_slot : nullptr;
+    put(target, n4, sim->d_target);
+    a.target = sim->d_target;
+    if (use_queue) {
+      put(order.data(), order.size() * sizeof(int32_t), sim->d_order);
+      put(order_large.data(), order_large.size() * sizeof(int32_t), sim->d_order + sim->cfg.max_envs);
+      put(counts, sizeof counts, sim->d_ctl + 8);
     }
-    hipError_t e = hipMemcpyAsync(sim->d_x_desc, xdesc.data(), xdesc.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                  sim->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(sim->d_x_key, xkey.data(), xkey.size() * sizeof(uint32_t), hipMemcpyHostToDevice, sim->stream);
-    if (e != hipSuccess) return hip_fail(e, "re-purposing upload");
+    if (rp && n > 0 && e == hipSuccess) {
+      int32_t* xdesc = reinterpret_cast<int32_t*>(base + at);
+      for (int k = 0; k < n; ++k) {
+        xdesc[4 * k + 0] = rp->src_slot[k];
+        xdesc[4 * k + 1] = rp->action[k];
+        xdesc[4 * k + 2] = rp->node_id[k];
+        xdesc[4 * k + 3] = (int32_t)((uint32_t)rp->replica[k] | ((uint32_t)(rp->horizon ? rp->horizon[k] : 255) << 24));
+      }
+      e = hipMemcpyAsync(sim->d_x_desc, xdesc, 4 * n4, hipMemcpyHostToDevice, sim->stream);
+      at += al(4 * n4);
+      uint32_t* xkey = reinterpret_cast<uint32_t*>(base + at);
+      for (int k = 0; k < n; ++k) {
+        xkey[2 * k + 0] = (uint32_t)rp->seed[k];
+        xkey[2 * k + 1] = (uint32_t)(rp->seed[k] >> 32);
+      }
+      if (e == hipSuccess) e = hipMemcpyAsync(sim->d_x_key, xkey, 2 * n4, hipMemcpyHostToDevice, sim->stream);
+      at += al(2 * n4);
+    }
+    if (e != hipSuccess) return hip_fail(e, "rollout upload");
+    if ((st = stage_end(sim)) != PMBS_OK) return st;
+  }
+  if (rp && n > 0) {
     a.x_desc = reinterpret_cast<const int4*>(sim->d_x_desc);
     a.x_key = reinterpret_cast<const uint2*>(sim->d_x_key);
     a.x_rewards = rp->d_rewards;
     a.x_count = rp->d_counts;
-  }
-  if (!inputs_on_device) {
-    hipError_t e = hipStreamSynchronize(sim->stream);
-    if (e != hipSuccess) return hip_fail(e, "rollout upload sync");
   }
   a.pool = sim->d_pool;
   a.pool_stride = sim->cfg.pool_stride;
