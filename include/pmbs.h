@@ -160,7 +160,8 @@ pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_de
  * after the first push there (the expanded tree node).  d_reward_count[e]
  * (optional, device) receives the number of rewards written.  Integer
  * inputs are host or device per inputs_on_device (PMBS_ROLLOUT_QUEUE needs
- * host inputs).  Asynchronous. */
+ * host inputs); host inputs are copied into the simulator's pinned staging
+ * before the call returns and uploaded by queued copies.  Asynchronous. */
 pmbs_status pmbs_sim_rollout(pmbs_sim_t* sim, const int32_t* actions, const int32_t* act_offset,
                              const int32_t* src_slot, const int32_t* child_slot, const int32_t* target,
                              int32_t inputs_on_device, int32_t n_substeps, float width, float* d_rewards,
