@@ -262,27 +262,22 @@ __device__ __forceinline__ Box pusher_box(const PusherPose& q, const Params& p) 
 // when its pusher start pose clears every box.  Lane w < PMBS_VALID_WORDS
 // returns word w (bit a mod 32 of word a / 32 set when action a is valid);
 // the other lanes return 0.
+// The validity bits of actions a0 .. a0 + 63 (lane k tests action a0 + k)
+// as a 64-bit ballot: bit set when the pusher at the action's start pose is
+// clear of every box.
 template <class S>
-__device__ __forceinline__ unsigned validity_word(const S& s, int nb, const Params& p, int lane) {
+__device__ __forceinline__ unsigned long long validity_bits(const S& s, int nb, const Params& p, int a0, int lane) {
   const int n_act = nb * p.n_dirs;
-  unsigned word = 0u;
-  for (int a0 = 0; a0 < n_act; a0 += 64) {
-    const int a = a0 + lane;
-    bool ok = false;
-    if (a < n_act) {
-      const int obj = a / p.n_dirs, dir = a - obj * p.n_dirs;
-      const Box P = pusher_box(pusher_pose(contour_start(s, obj, dir, p), p), p);
-      ok = true;
-      for (int j = 0; j < nb; ++j)
-        if (ok && !sat_clear(load_box(s, j), P, p.edge_eps)) ok = false;
-    }
-    const unsigned long long m = __ballot(ok);
-    // words 2 * (a0 / 64) and 2 * (a0 / 64) + 1
-    const int w = a0 >> 5;
-    if (lane == w) word = (unsigned)m;
-    if (lane == w + 1) word = (unsigned)(m >> 32);
+  const int a = a0 + lane;
+  bool ok = false;
+  if (a < n_act) {
+    const int obj = a / p.n_dirs, dir = a - obj * p.n_dirs;
+    const Box P = pusher_box(pusher_pose(contour_start(s, obj, dir, p), p), p);
+    ok = true;
+    for (int j = 0; j < nb; ++j)
+      if (ok && !sat_clear(load_box(s, j), P, p.edge_eps)) ok = false;
   }
-  return word;
+  return __ballot(ok);
 }
 
 // An opaque copy of a value: address arithmetic built from it stays where it
@@ -1686,21 +1681,23 @@ struct Frames {
   float4 half[MAXB];
 };
 
-// One wave per environment: the boxes' frames from the env state (or pool
+// Four waves per environment: the boxes' frames from the env state (or pool
 // slot src_slot[e]; < 0 skips the env) computed as the step kernel computes
 // them, then the validity words of every contour push by the step kernel's
-// own start-pose test.  Workgroups loop over the envs (the count may come
-// from device memory).
-__global__ __launch_bounds__(64) void valid_kernel(ValidArgs g) {
+// own start-pose test, wave w taking actions 64 w .. 64 w + 63 (words 2 w
+// and 2 w + 1).  Workgroups loop over the envs (the count may come from
+// device memory).
+constexpr int VALID_WAVES = PMBS_VALID_WORDS / 2;
+__global__ __launch_bounds__(64 * VALID_WAVES) void valid_kernel(ValidArgs g) {
   __shared__ Frames s;
   const int n = g.count ? g.count[0] + g.count[1] : g.n_envs;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int e = blockIdx.x; e < n; e += gridDim.x) {
     const int src = g.src_slot ? g.src_slot[e] : -1;
     if (g.src_slot && src < 0) continue;
     const int base = g.env_offset[e];
     const int nb = g.env_offset[e + 1] - base;
-    if (lane < nb) {
+    if (wid == 0 && lane < nb) {
       const float* st = src >= 0 ? g.pool + (size_t)src * 13 * g.pool_stride : g.state;
       const int SN = src >= 0 ? g.pool_stride : g.stride;
       const int si = src >= 0 ? lane : base + lane;
@@ -1714,10 +1711,11 @@ __global__ __launch_bounds__(64) void valid_kernel(ValidArgs g) {
       s.col[2][lane] = f4(c2, 0.0f);
       s.half[lane] = make_float4(g.bconst[0 * BN + bi], g.bconst[1 * BN + bi], g.bconst[2 * BN + bi], 0.0f);
     }
-    wave_sync();
-    const unsigned wd = validity_word(s, nb, g.p, lane);
-    if (lane < PMBS_VALID_WORDS) g.out[(size_t)e * PMBS_VALID_WORDS + lane] = wd;
-    wave_sync();   // the frames are read before the next env's overwrite them
+    __syncthreads();
+    const int a0 = 64 * wid;
+    const unsigned long long m = a0 < nb * g.p.n_dirs ? validity_bits(s, nb, g.p, a0, lane) : 0ull;
+    if (lane < 2) g.out[(size_t)e * PMBS_VALID_WORDS + 2 * wid + lane] = lane ? (unsigned)(m >> 32) : (unsigned)m;
+    __syncthreads();   // the frames are read before the next env's overwrite them
   }
 }
 
@@ -1725,7 +1723,7 @@ __global__ __launch_bounds__(64) void valid_kernel(ValidArgs g) {
 hipError_t launch_valid(const ValidArgs& a, hipStream_t stream, int grid) {
   const int g = grid > 0 ? grid : a.n_envs;
   if (g <= 0) return hipSuccess;
-  hipLaunchKernelGGL(valid_kernel, dim3(g), dim3(64), 0, stream, a);
+  hipLaunchKernelGGL(valid_kernel, dim3(g), dim3(64 * VALID_WAVES), 0, stream, a);
   return hipGetLastError();
 }
 
