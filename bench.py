@@ -273,10 +273,11 @@ def uneven_batching(pmbs, scenes, args) -> dict:
     """Uneven batch: envs of 5-30 cuboids, 1-5 contour pushes each, 120
     substeps per push.  Packed form: one graph-captured launch of persistent
     work-queue kernels per contact class, envs loaded from pool slots,
-    launch plan chosen by the autotuner.  Plain form: every env padded to 30
-    bodies, one launch per push index with a host round trip between
-    launches.  Both report useful env-substeps (real bodies, pushes actually
-    simulated) per second of wall time."""
+    launch plan chosen by the autotuner, batches launched back to back.
+    Plain form: every env padded to 30 bodies, one launch per push index
+    with a host round trip between launches.  Both report useful
+    env-substeps (real bodies, pushes actually simulated) per second of
+    wall time."""
     import torch
     E, sub, H = args.uneven_envs, args.substeps, 5
     t0 = time.time()
