@@ -60,6 +60,8 @@ struct StepArgs {
   // larger class (null: it finishes with the overflow status bit)
   int* overflow_list;
   int* overflow_count;
+  // cost pass (launch_cost only): [n_envs] work estimates of the pushes
+  int* cost_key;
   Params p;
 };
 
@@ -115,6 +117,12 @@ hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream, 
 // persistent queue launch of one contact class without resetting the queue
 // counter (the caller clears it, e.g. with launch_zero)
 hipError_t launch_step_class(const StepArgs& a, int max_contacts, hipStream_t stream, int grid, int waves = 1);
+// cost pass: one block per env writes a.cost_key[e], the env's work
+// estimate (contacts + candidate pairs at the start pose, + 3 for a valid
+// push); order: the envs by descending estimate into order[0, n), and the
+// queue counter cleared
+hipError_t launch_cost(const StepArgs& a, int max_contacts, hipStream_t stream, int waves = 1);
+hipError_t launch_order(const int* key, int n, int* order, int* queue, hipStream_t stream);
 hipError_t launch_zero(int* p, int n, hipStream_t stream);
 hipError_t launch_reward(const RewardArgs& a, hipStream_t stream);
 // one workgroup per env, or a fixed grid looping over the device-held count

@@ -598,7 +598,7 @@ __device__ __forceinline__ void sync_all() {
 // of W = 1.  Uniform decisions (push validity, rewards, overflow) are taken
 // by every wave from the same LDS data, so all waves run the same loops and
 // meet at the same barriers.
-template <int K, int W>
+template <int K, int W, bool COST>
 __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const int e) {
   constexpr int C = Smem<K, W>::C;
   constexpr int KW = K / W;  // contact slots per wave
@@ -972,128 +972,140 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       }
       const Box A = load_box(s, ia), B = load_box(s, ib);
       const f3 d = B.c - A.c;
-      // candidate gl: 0-2 faces of A, 3-5 faces of B, 6-7 edge crosses A0 x B0, A0 x B1
-      f3 L0;
-      bool ok0 = has;
-      if (gl < 6) {
-        L0 = lds_axis(s, gl < 3 ? ia : ib, gl < 3 ? gl : gl - 3);
-      } else {
-        const f3 v = cross(A.a0, axis(B, gl - 6));
-        const float l2 = dot(v, v);
-        ok0 = ok0 && l2 >= p.edge_eps * p.edge_eps;
-        L0 = v * rsq(l2);
-      }
-      // candidate gl + 8: edge crosses 8-14 (gl = 7 has none)
-      const int e1 = gl + 2;  // index of the edge pair (i, j) = (e1 / 3, e1 % 3)
-      const f3 v1 = cross(axis(A, e1 / 3), axis(B, e1 % 3));
-      const float l21 = dot(v1, v1);
-      const bool ok1 = has && gl < 7 && l21 >= p.edge_eps * p.edge_eps;
-      const f3 L1 = v1 * rsq(l21);
-      const float sv0 = fabsf(dot(d, L0)) - radius_along(A, L0) - radius_along(B, L0);
-      const float sv1 = fabsf(dot(d, L1)) - radius_along(A, L1) - radius_along(B, L1);
       const unsigned long long gm = 0xffull << (8 * grp);
-      const bool out = (__ballot((ok0 && sv0 > p.margin) || (ok1 && sv1 > p.margin)) & gm) != 0ull;
-      // the contact axis: the group's candidates (separation value and unit
-      // axis) go to LDS at their candidate index (k < 8: lane k's first,
-      // k >= 8: lane k - 8's second; an invalid one holds -inf), and every lane of the
-      // group scans the fifteen in order: the kept axis starts at candidate
-      // 0 (a face of A, valid whenever the pair is) and is replaced only by
-      // a later one that exceeds it by tau_face (faces) or tau_edge (edges)
-      auto& cd = s.x.cand[wid];
-      float* const cv = &cd.v[grp][0];
-      cv[gl] = ok0 ? sv0 : -INFINITY;
-      cv[gl + 8] = ok1 ? sv1 : -INFINITY;
-      cd.ax[0][grp][gl] = L0.x;
-      cd.ax[1][grp][gl] = L0.y;
-      cd.ax[2][grp][gl] = L0.z;
-      cd.ax[0][grp][gl + 8] = L1.x;
-      cd.ax[1][grp][gl + 8] = L1.y;
-      cd.ax[2][grp][gl + 8] = L1.z;
-      wave_sync();
-      const float4 c0 = reinterpret_cast<const float4*>(cv)[0], c1 = reinterpret_cast<const float4*>(cv)[1];
-      const float4 c2 = reinterpret_cast<const float4*>(cv)[2], c3 = reinterpret_cast<const float4*>(cv)[3];
-      float bs = c0.x;
-      int best = 0;
-      auto scan = [&](float sk, int k, float tau) {
-        if (sk > bs + tau) {
-          bs = sk;
-          best = k;
+      // the six face axes first (candidate gl < 6: face gl of A, gl - 3 of
+      // B; lanes 6-7 repeat two of B's here and take edge crosses below).
+      // A pair separated along a face axis by more than the margin has no
+      // contact whatever the other axes give, and a pass whose pairs are all
+      // such skips the edge axes, the axis scan and clipping.
+      const f3 Lf = lds_axis(s, gl < 3 ? ia : ib, gl < 3 ? gl : (gl < 6 ? gl - 3 : gl - 6));
+      const float svf = fabsf(dot(d, Lf)) - radius_along(A, Lf) - radius_along(B, Lf);
+      const bool live = has && (__ballot(gl < 6 && svf > p.margin) & gm) == 0ull;
+      bool keep = false, face = false;
+      f3 P = mk(0, 0, 0), nref = mk(0, 0, 1), n = mk(0, 0, 0);
+      float psep = 0.0f, bs = 0.0f;
+      int best = -1;
+      if (__ballot(live) != 0ull) {
+        // candidate gl: 0-2 faces of A, 3-5 faces of B, 6-7 edge crosses A0 x B0, A0 x B1
+        f3 L0 = Lf;
+        float sv0 = svf;
+        bool ok0 = has;
+        if (gl >= 6) {
+          const f3 v = cross(A.a0, axis(B, gl - 6));
+          const float l2 = dot(v, v);
+          ok0 = ok0 && l2 >= p.edge_eps * p.edge_eps;
+          L0 = v * rsq(l2);
+          sv0 = fabsf(dot(d, L0)) - radius_along(A, L0) - radius_along(B, L0);
         }
-      };
-      scan(c0.y, 1, p.tau_face);
-      scan(c0.z, 2, p.tau_face);
-      scan(c0.w, 3, p.tau_face);
-      scan(c1.x, 4, p.tau_face);
-      scan(c1.y, 5, p.tau_face);
-      scan(c1.z, 6, p.tau_edge);
-      scan(c1.w, 7, p.tau_edge);
-      scan(c2.x, 8, p.tau_edge);
-      scan(c2.y, 9, p.tau_edge);
-      scan(c2.z, 10, p.tau_edge);
-      scan(c2.w, 11, p.tau_edge);
-      scan(c3.x, 12, p.tau_edge);
-      scan(c3.y, 13, p.tau_edge);
-      scan(c3.z, 14, p.tau_edge);
-      if (!has || out) best = -1;
-      // every lane of the group takes the kept axis from LDS, pointing from A to B
-      f3 n = mk(0, 0, 0);
-      if (best >= 0) {
-        const f3 Lb = mk(cd.ax[0][grp][best], cd.ax[1][grp][best], cd.ax[2][grp][best]);
-        n = sel(dot(d, Lb) >= 0.0f, Lb, neg(Lb));
+        // candidate gl + 8: edge crosses 8-14 (gl = 7 has none)
+        const int e1 = gl + 2;  // index of the edge pair (i, j) = (e1 / 3, e1 % 3)
+        const f3 v1 = cross(axis(A, e1 / 3), axis(B, e1 % 3));
+        const float l21 = dot(v1, v1);
+        const bool ok1 = has && gl < 7 && l21 >= p.edge_eps * p.edge_eps;
+        const f3 L1 = v1 * rsq(l21);
+        const float sv1 = fabsf(dot(d, L1)) - radius_along(A, L1) - radius_along(B, L1);
+        const bool out = (__ballot((ok0 && sv0 > p.margin) || (ok1 && sv1 > p.margin)) & gm) != 0ull;
+        // the contact axis: the group's candidates (separation value and unit
+        // axis) go to LDS at their candidate index (k < 8: lane k's first,
+        // k >= 8: lane k - 8's second; an invalid one holds -inf), and every lane of the
+        // group scans the fifteen in order: the kept axis starts at candidate
+        // 0 (a face of A, valid whenever the pair is) and is replaced only by
+        // a later one that exceeds it by tau_face (faces) or tau_edge (edges)
+        auto& cd = s.x.cand[wid];
+        float* const cv = &cd.v[grp][0];
+        cv[gl] = ok0 ? sv0 : -INFINITY;
+        cv[gl + 8] = ok1 ? sv1 : -INFINITY;
+        cd.ax[0][grp][gl] = L0.x;
+        cd.ax[1][grp][gl] = L0.y;
+        cd.ax[2][grp][gl] = L0.z;
+        cd.ax[0][grp][gl + 8] = L1.x;
+        cd.ax[1][grp][gl + 8] = L1.y;
+        cd.ax[2][grp][gl + 8] = L1.z;
+        wave_sync();
+        const float4 c0 = reinterpret_cast<const float4*>(cv)[0], c1 = reinterpret_cast<const float4*>(cv)[1];
+        const float4 c2 = reinterpret_cast<const float4*>(cv)[2], c3 = reinterpret_cast<const float4*>(cv)[3];
+        bs = c0.x;
+        best = 0;
+        auto scan = [&](float sk, int k, float tau) {
+          if (sk > bs + tau) {
+            bs = sk;
+            best = k;
+          }
+        };
+        scan(c0.y, 1, p.tau_face);
+        scan(c0.z, 2, p.tau_face);
+        scan(c0.w, 3, p.tau_face);
+        scan(c1.x, 4, p.tau_face);
+        scan(c1.y, 5, p.tau_face);
+        scan(c1.z, 6, p.tau_edge);
+        scan(c1.w, 7, p.tau_edge);
+        scan(c2.x, 8, p.tau_edge);
+        scan(c2.y, 9, p.tau_edge);
+        scan(c2.z, 10, p.tau_edge);
+        scan(c2.w, 11, p.tau_edge);
+        scan(c3.x, 12, p.tau_edge);
+        scan(c3.y, 13, p.tau_edge);
+        scan(c3.z, 14, p.tau_edge);
+        if (!has || out) best = -1;
+        // every lane of the group takes the kept axis from LDS, pointing from A to B
+        if (best >= 0) {
+          const f3 Lb = mk(cd.ax[0][grp][best], cd.ax[1][grp][best], cd.ax[2][grp][best]);
+          n = sel(dot(d, Lb) >= 0.0f, Lb, neg(Lb));
+        }
+        // face axis: reference face of the axis owner, incident face of the
+        // other box (most anti-parallel, ties to +x, -x, +y, -y, +z, -z), its
+        // four corners one per lane, clipped by the reference face's side
+        // planes +u, -u, +v, -v
+        face = best >= 0 && best < 6;
+        f3 fref = mk(0, 0, 0), u = mk(1, 0, 0), w = mk(0, 1, 0);
+        float hu = 0.0f, hw = 0.0f;
+        int np = 0;
+        if (face) {
+          const bool a_ref = best < 3;
+          const int k = a_ref ? best : best - 3;
+          const int ku = k == 2 ? 0 : k + 1, kv = k == 0 ? 2 : k - 1;
+          // reference box ir (the axis owner) and incident box ii, read from
+          // LDS at the indices found (no selects over both boxes' registers)
+          const int ir = a_ref ? ia : ib, ii = a_ref ? ib : ia;
+          const float* const hr = reinterpret_cast<const float*>(&s.half[ir]);
+          nref = sel(a_ref, n, neg(n));
+          fref = xyz(s.pos[ir]) + nref * hr[k];
+          u = lds_axis(s, ir, ku);
+          w = lds_axis(s, ir, kv);
+          hu = hr[ku];
+          hw = hr[kv];
+          const f3 i0 = lds_axis(s, ii, 0), i1 = lds_axis(s, ii, 1), i2 = lds_axis(s, ii, 2);
+          const f3 ic = xyz(s.pos[ii]);
+          const float c0 = dot(i0, nref), c1 = dot(i1, nref), c2 = dot(i2, nref);
+          int fb = 0;
+          float bd = c0;
+          if (-c0 < bd) { bd = -c0; fb = 1; }
+          if (c1 < bd) { bd = c1; fb = 2; }
+          if (-c1 < bd) { bd = -c1; fb = 3; }
+          if (c2 < bd) { bd = c2; fb = 4; }
+          if (-c2 < bd) { bd = -c2; fb = 5; }
+          const int m = fb >> 1, mp = m == 2 ? 0 : m + 1, mq = m == 0 ? 2 : m - 1;
+          const float sg = (fb & 1) ? -1.0f : 1.0f;
+          const float* const hi = reinterpret_cast<const float*>(&s.half[ii]);
+          const f3 am = lds_axis(s, ii, m), ap = lds_axis(s, ii, mp), aq = lds_axis(s, ii, mq);
+          const float hm = hi[m], hp = hi[mp], hq = hi[mq];
+          const f3 fc = ic + am * (sg * hm);
+          const f3 ep = ap * hp, eq = aq * hq;
+          // corner gl of the incident face: signs (+,+), (-,+), (-,-), (+,-) of
+          // its two half edges (lanes 4-7 repeat corner 3); a product with +-1
+          // is exact, so each sum rounds once as a plain sum or difference
+          const float spp = (gl == 1 || gl == 2) ? -1.0f : 1.0f, sqq = gl >= 2 ? -1.0f : 1.0f;
+          P = fc + (ep * spp + eq * sqq);
+          np = 4;
+        }
+        np = clip_group(s, &P, np, fref, u, 1.0f, hu, 0, grp, gl, lane, wid);
+        np = clip_group(s, &P, np, fref, u, -1.0f, hu, 1, grp, gl, lane, wid);
+        np = clip_group(s, &P, np, fref, w, 1.0f, hw, 0, grp, gl, lane, wid);
+        np = clip_group(s, &P, np, fref, w, -1.0f, hw, 1, grp, gl, lane, wid);
+        // contacts: kept polygon points (face) or one edge-edge point
+        psep = dot(nref, P - fref);
+        keep = face ? (gl < np && psep <= p.margin) : (best >= 6 && gl == 0);
       }
-      // face axis: reference face of the axis owner, incident face of the
-      // other box (most anti-parallel, ties to +x, -x, +y, -y, +z, -z), its
-      // four corners one per lane, clipped by the reference face's side
-      // planes +u, -u, +v, -v
-      const bool face = best >= 0 && best < 6;
-      f3 P = mk(0, 0, 0), nref = mk(0, 0, 1), fref = mk(0, 0, 0), u = mk(1, 0, 0), w = mk(0, 1, 0);
-      float hu = 0.0f, hw = 0.0f;
-      int np = 0;
-      if (face) {
-        const bool a_ref = best < 3;
-        const int k = a_ref ? best : best - 3;
-        const int ku = k == 2 ? 0 : k + 1, kv = k == 0 ? 2 : k - 1;
-        // reference box ir (the axis owner) and incident box ii, read from
-        // LDS at the indices found (no selects over both boxes' registers)
-        const int ir = a_ref ? ia : ib, ii = a_ref ? ib : ia;
-        const float* const hr = reinterpret_cast<const float*>(&s.half[ir]);
-        nref = sel(a_ref, n, neg(n));
-        fref = xyz(s.pos[ir]) + nref * hr[k];
-        u = lds_axis(s, ir, ku);
-        w = lds_axis(s, ir, kv);
-        hu = hr[ku];
-        hw = hr[kv];
-        const f3 i0 = lds_axis(s, ii, 0), i1 = lds_axis(s, ii, 1), i2 = lds_axis(s, ii, 2);
-        const f3 ic = xyz(s.pos[ii]);
-        const float c0 = dot(i0, nref), c1 = dot(i1, nref), c2 = dot(i2, nref);
-        int fb = 0;
-        float bd = c0;
-        if (-c0 < bd) { bd = -c0; fb = 1; }
-        if (c1 < bd) { bd = c1; fb = 2; }
-        if (-c1 < bd) { bd = -c1; fb = 3; }
-        if (c2 < bd) { bd = c2; fb = 4; }
-        if (-c2 < bd) { bd = -c2; fb = 5; }
-        const int m = fb >> 1, mp = m == 2 ? 0 : m + 1, mq = m == 0 ? 2 : m - 1;
-        const float sg = (fb & 1) ? -1.0f : 1.0f;
-        const float* const hi = reinterpret_cast<const float*>(&s.half[ii]);
-        const f3 am = lds_axis(s, ii, m), ap = lds_axis(s, ii, mp), aq = lds_axis(s, ii, mq);
-        const float hm = hi[m], hp = hi[mp], hq = hi[mq];
-        const f3 fc = ic + am * (sg * hm);
-        const f3 ep = ap * hp, eq = aq * hq;
-        // corner gl of the incident face: signs (+,+), (-,+), (-,-), (+,-) of
-        // its two half edges (lanes 4-7 repeat corner 3); a product with +-1
-        // is exact, so each sum rounds once as a plain sum or difference
-        const float spp = (gl == 1 || gl == 2) ? -1.0f : 1.0f, sqq = gl >= 2 ? -1.0f : 1.0f;
-        P = fc + (ep * spp + eq * sqq);
-        np = 4;
-      }
-      np = clip_group(s, &P, np, fref, u, 1.0f, hu, 0, grp, gl, lane, wid);
-      np = clip_group(s, &P, np, fref, u, -1.0f, hu, 1, grp, gl, lane, wid);
-      np = clip_group(s, &P, np, fref, w, 1.0f, hw, 0, grp, gl, lane, wid);
-      np = clip_group(s, &P, np, fref, w, -1.0f, hw, 1, grp, gl, lane, wid);
-      // contacts: kept polygon points (face) or one edge-edge point
-      const float psep = dot(nref, P - fref);
-      const bool keep = face ? (gl < np && psep <= p.margin) : (best >= 6 && gl == 0);
       const unsigned long long km = __ballot(keep);
       const unsigned long long below = (1ull << lane) - 1ull;
       int before = 0, round_total = __popcll(km);
@@ -1134,6 +1146,13 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       }
     }
     const int nc = nc_raw < C ? nc_raw : C;
+    if constexpr (COST) {
+      // the work estimate of the env's push from its start pose: contacts
+      // and candidate pairs (the per-substep solver and narrowphase work)
+      // plus 3 for a pusher that moves (a changing scene); nothing else is written
+      if (lead && lane == 0) g.cost_key[e] = nc + n_pairs + (valid ? 3 : 0);
+      return;
+    }
     stat_nc += nc;
     stat_pairs += n_pairs;
     stat_sub += 1;
@@ -1262,8 +1281,9 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     // four entries of the list stay in registers for the whole solve as row
     // byte offsets and signs (a pair lane: its entries sh, sh + 2, sh + 4,
     // sh + 6; a single lane: entries 0-3), so their loads need no index
-    // arithmetic; slots past the end of a list point at the zero row, whose
-    // term leaves every sum unchanged
+    // arithmetic and no guard; slots past the end of a list point at the
+    // zero row, whose term (-1 times +0) leaves every sum unchanged, an
+    // empty list's sum included (+0)
     unsigned radr[4];
     float rsg[4];
 #pragma unroll
@@ -1305,7 +1325,7 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       if (!sum_on) return;
       f3 a0 = mk(0, 0, 0), a1 = mk(0, 0, 0);
       if (two) {
-        if (ccount > sh) {
+        {
           float4 val[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) val[u] = reg_row(radr[u]);
@@ -1325,7 +1345,7 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
         // the partner lane's partial sum (lane ^ 1)
         a1 = mk(pair_swap(a0.x), pair_swap(a0.y), pair_swap(a0.z));
       } else {
-        if (ccount > 0) {
+        {
           float4 val[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) val[u] = reg_row(radr[u]);
@@ -1602,10 +1622,59 @@ __global__ __launch_bounds__(64 * W, 2) void step_kernel(StepArgs g) {
       __syncthreads();
     }
     if (wi >= n_work) break;
-    run_env<K, W>(s, g, g.order ? g.order[wi] : wi);   // the only call site: one inlined copy
+    run_env<K, W, false>(s, g, g.order ? g.order[wi] : wi);
     if (!g.queue) break;
     __syncthreads();
   }
+}
+
+// The cost pass of a queued step: one block per env runs the push begin
+// and the first substep's collision detection and writes the env's work
+// estimate to cost_key (the rest of run_env is not compiled in).
+template <int K, int W>
+__global__ __launch_bounds__(64 * W, 2) void cost_kernel(StepArgs g) {
+  __shared__ Smem<K, W> s;
+  init_plane(s, g.p);
+  const int e = g.env_base + xcd_item(blockIdx.x, gridDim.x);
+  if (e < g.n_envs) run_env<K, W, true>(s, g, e);
+}
+
+// Schedule of a queued step: the envs by descending work estimate, a
+// counting sort of the estimates clamped to [0, ORDER_BINS).  Equal
+// estimates come in the order of the LDS atomics (an env's result does
+// not depend on when it runs).  One workgroup of ORDER_BINS threads; it
+// also clears the queue counter the step kernel pulls from.
+constexpr int ORDER_BINS = 1024;
+__global__ __launch_bounds__(ORDER_BINS) void order_kernel(const int* __restrict__ key, int n, int* __restrict__ order,
+                                                          int* queue) {
+  __shared__ int start[ORDER_BINS];
+  __shared__ int wsum[ORDER_BINS / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  auto bin = [&](int e) {
+    const int k = key[e];
+    return k < 0 ? 0 : (k >= ORDER_BINS ? ORDER_BINS - 1 : k);
+  };
+  start[t] = 0;
+  __syncthreads();
+  for (int e = t; e < n; e += ORDER_BINS) atomicAdd(&start[bin(e)], 1);
+  __syncthreads();
+  // thread t owns bin ORDER_BINS - 1 - t (largest first): the envs of
+  // larger bins come before its own
+  const int r = ORDER_BINS - 1 - t;
+  const int c = start[r];
+  int v = c;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(v, d, 64);
+    if (lane >= d) v += y;
+  }
+  if (lane == 63) wsum[w] = v;
+  __syncthreads();
+  int before = 0;
+  for (int k = 0; k < w; ++k) before += wsum[k];
+  start[r] = before + v - c;
+  __syncthreads();
+  for (int e = t; e < n; e += ORDER_BINS) order[atomicAdd(&start[bin(e)], 1)] = e;
+  if (t == 0) *queue = 0;
 }
 
 __global__ void zero_kernel(int* p, int n) {
@@ -1750,6 +1819,30 @@ hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream, 
 hipError_t launch_step_class(const StepArgs& a, int max_contacts, hipStream_t stream, int grid, int waves) {
   if (grid <= 0 || !a.queue) return hipErrorInvalidValue;
   return waves == 2 ? launch_class<2>(a, max_contacts, stream, grid) : launch_class<1>(a, max_contacts, stream, grid);
+}
+
+hipError_t launch_cost(const StepArgs& a, int max_contacts, hipStream_t stream, int waves) {
+  const int n = a.n_envs - a.env_base;
+  if (n <= 0 || !a.cost_key) return n <= 0 ? hipSuccess : hipErrorInvalidValue;
+  StepArgs c = a;
+  if (c.n_substeps < 1) c.n_substeps = 1;   // the estimate comes from the first substep
+  const dim3 block(64 * (waves == 2 ? 2 : 1));
+  if (waves == 2) {
+    if (max_contacts <= 128) hipLaunchKernelGGL((cost_kernel<2, 2>), dim3(n), block, 0, stream, c);
+    else if (max_contacts <= 256) hipLaunchKernelGGL((cost_kernel<4, 2>), dim3(n), block, 0, stream, c);
+    else hipLaunchKernelGGL((cost_kernel<8, 2>), dim3(n), block, 0, stream, c);
+  } else {
+    if (max_contacts <= 128) hipLaunchKernelGGL((cost_kernel<2, 1>), dim3(n), block, 0, stream, c);
+    else if (max_contacts <= 256) hipLaunchKernelGGL((cost_kernel<4, 1>), dim3(n), block, 0, stream, c);
+    else hipLaunchKernelGGL((cost_kernel<8, 1>), dim3(n), block, 0, stream, c);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const int* key, int n, int* order, int* queue, hipStream_t stream) {
+  if (n <= 0 || !key || !order || !queue) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(ORDER_BINS), 0, stream, key, n, order, queue);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero(int* p, int n, hipStream_t stream) {

@@ -668,7 +668,24 @@ pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_de
   StepArgs a = step_args(sim);
   a.push = d_push;
   a.n_substeps = n_substeps;
-  hipError_t e = launch_step(a, sim->cfg.max_contacts, sim->stream, plan_waves(sim, sim->cfg.max_contacts));
+  const int mc = sim->cfg.max_contacts, waves = plan_waves(sim, mc);
+  hipError_t e = hipSuccess;
+  const int grid = class_grid(sim, mc, 0, waves);
+  if (sim->plan.order != 0 && n_substeps > 0 && sim->n_envs > grid) {
+    // more envs than resident workgroups: a cost pass estimates each env's
+    // work at its start pose, and persistent workgroups take the envs from
+    // a queue, largest estimate first, so the short ones fill the end of
+    // the launch (the key array is the large-class half of the order list)
+    StepArgs c = a;
+    c.cost_key = sim->d_order + sim->cfg.max_envs;
+    e = launch_cost(c, mc, sim->stream, waves);
+    if (e == hipSuccess) e = launch_order(c.cost_key, sim->n_envs, sim->d_order, sim->d_ctl, sim->stream);
+    a.order = sim->d_order;
+    a.queue = sim->d_ctl;
+    if (e == hipSuccess) e = launch_step_class(a, mc, sim->stream, grid, waves);
+  } else {
+    e = launch_step(a, mc, sim->stream, waves);
+  }
   if (e != hipSuccess) return hip_fail(e, "step launch");
   return PMBS_OK;
 }

@@ -458,6 +458,26 @@ def test_headline_shape_sampled_parity(pm):
         assert pen <= 1e-3, (e, pen)
 
 
+def test_work_ordered_step_bitwise(pm):
+    """With more envs than resident workgroups a step runs a cost pass and
+    takes the envs from a queue, largest work estimate first: every env's
+    result (state, status, contact statistics) is bitwise that of the plain
+    launch, at the benchmark's shape and on an uneven batch in the
+    256-contact class, with one and two waves per env."""
+    cases = ((scenes.clutter_batch(2, 4096, 15), 128, 30), (scenes.clutter_batch(6, 2400, (5, 30)), 256, 20))
+    for b, mc, n_sub in cases:
+        sim = pm.Sim(max_envs=b.n_envs, max_bodies=b.n_bodies, max_contacts=mc)
+        out = []
+        for order, waves in ((0, 1), (1, 1), (1, 2)):
+            sim.set_launch_plan(order=order, small_waves=waves, large_waves=waves)
+            sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+            sim.step(b.push.astype(np.float32), n_sub)
+            out.append((sim.get_state(), sim.env_status(), sim.stats()))
+        for g, st, stats in out[1:]:
+            assert np.array_equal(g, out[0][0]) and np.array_equal(st, out[0][1])
+            assert np.array_equal(stats, out[0][2])
+
+
 # ------------------------------------------------------------- determinism / packing
 def test_run_twice_bitwise_and_alone_vs_packed(pm):
     b = scenes.clutter_batch(5, 96, (5, 30))
