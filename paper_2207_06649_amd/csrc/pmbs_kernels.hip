@@ -118,7 +118,7 @@ struct Smem {
   // row | side (1 = b); list 0 for the linear sums (row P), list 1 for the
   // angular sums (row ra x P or rb x P).  Padding codes point at the zero row.
   unsigned short inc[2][2 * C + 8 * MAXB];
-  float lo[3][MAXB], hi[3][MAXB];    // AABBs
+  float4 lo[MAXB], hi[MAXB];         // AABBs: min and max corner (x, y, z, -)
   int sorted[MAXB];                  // objects in min-x order (kept while still ordered)
   int lstart[MAXB];                  // incidence list starts
   unsigned mask[MAXB];
@@ -132,11 +132,16 @@ struct Smem {
   } u;
   float4 zero;                       // a row of zeros after the impulse rows (never written)
   union alignas(16) {
-    struct {
-      float v[CLIP_GROUPS][16];             // narrowphase: axis candidates of each wave's eight groups:
-      float ax[3][CLIP_GROUPS][16];         // separation value and unit axis (x, y, z rows)
-    } cand[W];
-    float clip[W][2][POLY][3][CLIP_GROUPS]; // narrowphase: clip polygons of each wave's eight groups
+    // each wave's own narrowphase scratch (no wave writes another's):
+    // first the axis candidates of its eight groups (separation value and
+    // unit axis, x, y, z rows), then their clip polygons
+    union alignas(16) {
+      struct {
+        float v[CLIP_GROUPS][16];
+        float ax[3][CLIP_GROUPS][16];
+      } cand;
+      float clip[2][POLY][3][CLIP_GROUPS];
+    } wave[W];
     unsigned incm[NOBJ][2 * K];             // incidence build: contact bit masks per body
   } x;
   // counts the waves of an environment exchange: candidate pairs, table
@@ -311,13 +316,13 @@ __device__ __forceinline__ int wave_next(int v) { return __builtin_amdgcn_update
 // the clip buffers of wave wid
 template <class S>
 __device__ __forceinline__ f3 cl_get(const S& s, int wid, int buf, int i, int grp) {
-  return mk(s.x.clip[wid][buf][i][0][grp], s.x.clip[wid][buf][i][1][grp], s.x.clip[wid][buf][i][2][grp]);
+  return mk(s.x.wave[wid].clip[buf][i][0][grp], s.x.wave[wid].clip[buf][i][1][grp], s.x.wave[wid].clip[buf][i][2][grp]);
 }
 template <class S>
 __device__ __forceinline__ void cl_put(S& s, int wid, int buf, int i, int grp, f3 v) {
-  s.x.clip[wid][buf][i][0][grp] = v.x;
-  s.x.clip[wid][buf][i][1][grp] = v.y;
-  s.x.clip[wid][buf][i][2][grp] = v.z;
+  s.x.wave[wid].clip[buf][i][0][grp] = v.x;
+  s.x.wave[wid].clip[buf][i][1][grp] = v.y;
+  s.x.wave[wid].clip[buf][i][2][grp] = v.z;
 }
 
 // Previous lane of each 8-lane group, lane 0 of a group taking lane 7: DPP
@@ -798,7 +803,8 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     // wave when there are two, else the lead after the broadphase)
     int n_pairs = 0, nc_raw = 0;
     if (lead) {
-      // ---- 3. broadphase: AABBs, rank sort on min-x, sweep
+      // ---- 3. broadphase: AABBs; up to 16 objects every pair directly, more
+      // by a rank sort on min-x and a sweep
       if (lane < n_obj) {
         f3 c = xyz(s.pos[lane]);
         f3 a0 = xyz(s.col[0][lane]), a1 = xyz(s.col[1][lane]), a2 = xyz(s.col[2][lane]);
@@ -806,100 +812,121 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
         float ex = fabsf(a0.x) * hh.x + fabsf(a1.x) * hh.y + fabsf(a2.x) * hh.z + p.margin;
         float ey = fabsf(a0.y) * hh.x + fabsf(a1.y) * hh.y + fabsf(a2.y) * hh.z + p.margin;
         float ez = fabsf(a0.z) * hh.x + fabsf(a1.z) * hh.y + fabsf(a2.z) * hh.z + p.margin;
-        s.lo[0][lane] = c.x - ex; s.hi[0][lane] = c.x + ex;
-        s.lo[1][lane] = c.y - ey; s.hi[1][lane] = c.y + ey;
-        s.lo[2][lane] = c.z - ez; s.hi[2][lane] = c.z + ez;
+        s.lo[lane] = make_float4(c.x - ex, c.y - ey, c.z - ez, 0.0f);
+        s.hi[lane] = make_float4(c.x + ex, c.y + ey, c.z + ez, 0.0f);
         s.mask[lane] = 0u;
       }
       wave_sync();
-      // the previous substep's order is still the order when every object
-      // precedes the next one by (key, index); then the ranks need no update
-      bool order_ok = order_kept;
-      if (order_ok) {
-        const bool in = lane < n_obj;
-        const int o = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
-        float kx = in ? s.lo[0][o] : INFINITY;
-        kx = kx == kx ? kx : INFINITY;
-        const float kn = wave_next(kx);
-        const int on = wave_next(o);
-        const bool bad = lane + 1 < n_obj && !(kx < kn || (kx == kn && o < on));
-        order_ok = __ballot(bad) == 0ull;
-      }
-      order_kept = true;
-      if (!order_ok) {
-        // rank of each object's min-x key (ties by index; NaN keys sort last,
-        // so the ranks stay a permutation whatever the state holds)
-        float key = lane < n_obj ? s.lo[0][lane] : INFINITY;
-        key = key == key ? key : INFINITY;
-        // lanes past n_obj hold +inf keys and never count, so the loop runs
-        // over fixed lanes (independent readlanes, two counters) with no guard
-        const int ikey = __float_as_int(key);
-        int r0 = 0, r1 = 0;
-  #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
-          const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
-          if (j & 1) r1 += c;
-          else r0 += c;
+      if (n_obj <= 16) {
+        // at most 16 objects: every pair (i, j), i < j, is tested directly,
+        // four rows i of sixteen columns j per pass (lane 16 (i - 4 q) + j),
+        // so lane order within a pass and pass order are the pairs'
+        // lexicographic order and a ballot lists the overlapping ones
+        const int jj = lane & 15;
+        const bool jin = jj < n_obj;
+        const float4 jl = s.lo[jj], jh = s.hi[jj];
+        for (int q = 0; 4 * q < n_obj - 1; ++q) {
+          const int ii = 4 * q + (lane >> 4);
+          const float4 il = s.lo[ii], ih = s.hi[ii];
+          const bool hit = jin && ii < jj && il.x <= jh.x && jl.x <= ih.x && il.y <= jh.y && jl.y <= ih.y &&
+                           il.z <= jh.z && jl.z <= ih.z;
+          const unsigned long long hm = __ballot(hit);
+          // rank among the lower lanes' hits (mbcnt)
+          const int rk = __builtin_amdgcn_mbcnt_hi((unsigned)(hm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)hm, 0u));
+          if (hit) s.pairs[n_pairs + rk] = (unsigned short)((ii << 8) | jj);
+          n_pairs += __popcll(hm);
         }
-        if (n_obj > 16) {
-  #pragma unroll
-          for (int j = 16; j < 32; ++j) {
+      } else {
+        // the previous substep's order is still the order when every object
+        // precedes the next one by (key, index); then the ranks need no update
+        bool order_ok = order_kept;
+        if (order_ok) {
+          const bool in = lane < n_obj;
+          const int o = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
+          float kx = in ? s.lo[o].x : INFINITY;
+          kx = kx == kx ? kx : INFINITY;
+          const float kn = wave_next(kx);
+          const int on = wave_next(o);
+          const bool bad = lane + 1 < n_obj && !(kx < kn || (kx == kn && o < on));
+          order_ok = __ballot(bad) == 0ull;
+        }
+        order_kept = true;
+        if (!order_ok) {
+          // rank of each object's min-x key (ties by index; NaN keys sort last,
+          // so the ranks stay a permutation whatever the state holds)
+          float key = lane < n_obj ? s.lo[lane].x : INFINITY;
+          key = key == key ? key : INFINITY;
+          // lanes past n_obj hold +inf keys and never count, so the loop runs
+          // over fixed lanes (independent readlanes, two counters) with no guard
+          const int ikey = __float_as_int(key);
+          int r0 = 0, r1 = 0;
+    #pragma unroll
+          for (int j = 0; j < 16; ++j) {
             const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
             const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
             if (j & 1) r1 += c;
             else r0 += c;
           }
-        }
-        const int rank = r0 + r1;
-        if (lane < n_obj) s.sorted[rank] = lane;
-      }
-      wave_sync();
-      {
-        // sweep: lane r holds the box at sorted position r and compares it with
-        // the boxes d = 1, 2, ... positions later until every lane has passed
-        // its box's max-x; the later boxes' bounds move down one lane per step
-        // (DPP whole-wave shift, no LDS round trip)
-        const bool in = lane < n_obj;
-        const int oi = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
-        const float lox = in ? s.lo[0][oi] : INFINITY, hix = in ? s.hi[0][oi] : -INFINITY;
-        const float loy = in ? s.lo[1][oi] : 0.0f, hiy = in ? s.hi[1][oi] : 0.0f;
-        const float loz = in ? s.lo[2][oi] : 0.0f, hiz = in ? s.hi[2][oi] : 0.0f;
-        float lox_q = lox, loy_q = loy, hiy_q = hiy, loz_q = loz, hiz_q = hiz;
-        int oj = oi;
-        // two steps per trip: sorted min-x makes a lane that fails at step d
-        // fail at every later step, so a trip whose second step has no lane
-        // left ends the sweep
-        for (int d = 1; d < n_obj; d += 2) {
-          bool more = false;
-  #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            lox_q = wave_next(lox_q);
-            loy_q = wave_next(loy_q);
-            hiy_q = wave_next(hiy_q);
-            loz_q = wave_next(loz_q);
-            hiz_q = wave_next(hiz_q);
-            oj = wave_next(oj);
-            const bool go = lane + d + h < n_obj && lox_q <= hix;
-            if (go && loy <= hiy_q && loy_q <= hiy && loz <= hiz_q && loz_q <= hiz) {
-              const int lo_i = oi < oj ? oi : oj, hi_i = oi < oj ? oj : oi;
-              atomicOr(&s.mask[lo_i], 1u << hi_i);
+          if (n_obj > 16) {
+    #pragma unroll
+            for (int j = 16; j < 32; ++j) {
+              const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
+              const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
+              if (j & 1) r1 += c;
+              else r0 += c;
             }
-            if (h == 1) more = __ballot(go) != 0ull;
           }
-          if (!more) break;
+          const int rank = r0 + r1;
+          if (lane < n_obj) s.sorted[rank] = lane;
         }
-      }
-      wave_sync();
-      {
-        unsigned m = lane < n_obj ? s.mask[lane] : 0u;
-        int off = wave_excl_scan(__popc(m), &n_pairs);
-        int t = 0;
-        while (m) {
-          int j = __builtin_ctz(m);
-          m &= m - 1;
-          if (off + t < MAX_PAIRS) s.pairs[off + t] = (unsigned short)((lane << 8) | j);
-          ++t;
+        wave_sync();
+        {
+          // sweep: lane r holds the box at sorted position r and compares it with
+          // the boxes d = 1, 2, ... positions later until every lane has passed
+          // its box's max-x; the later boxes' bounds move down one lane per step
+          // (DPP whole-wave shift, no LDS round trip)
+          const bool in = lane < n_obj;
+          const int oi = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
+          const float4 lb = s.lo[oi], hb4 = s.hi[oi];
+          const float lox = in ? lb.x : INFINITY, hix = in ? hb4.x : -INFINITY;
+          const float loy = in ? lb.y : 0.0f, hiy = in ? hb4.y : 0.0f;
+          const float loz = in ? lb.z : 0.0f, hiz = in ? hb4.z : 0.0f;
+          float lox_q = lox, loy_q = loy, hiy_q = hiy, loz_q = loz, hiz_q = hiz;
+          int oj = oi;
+          // two steps per trip: sorted min-x makes a lane that fails at step d
+          // fail at every later step, so a trip whose second step has no lane
+          // left ends the sweep
+          for (int d = 1; d < n_obj; d += 2) {
+            bool more = false;
+    #pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              lox_q = wave_next(lox_q);
+              loy_q = wave_next(loy_q);
+              hiy_q = wave_next(hiy_q);
+              loz_q = wave_next(loz_q);
+              hiz_q = wave_next(hiz_q);
+              oj = wave_next(oj);
+              const bool go = lane + d + h < n_obj && lox_q <= hix;
+              if (go && loy <= hiy_q && loy_q <= hiy && loz <= hiz_q && loz_q <= hiz) {
+                const int lo_i = oi < oj ? oi : oj, hi_i = oi < oj ? oj : oi;
+                atomicOr(&s.mask[lo_i], 1u << hi_i);
+              }
+              if (h == 1) more = __ballot(go) != 0ull;
+            }
+            if (!more) break;
+          }
+        }
+        wave_sync();
+        {
+          unsigned m = lane < n_obj ? s.mask[lane] : 0u;
+          int off = wave_excl_scan(__popc(m), &n_pairs);
+          int t = 0;
+          while (m) {
+            int j = __builtin_ctz(m);
+            m &= m - 1;
+            if (off + t < MAX_PAIRS) s.pairs[off + t] = (unsigned short)((lane << 8) | j);
+            ++t;
+          }
         }
       }
       wave_sync();
@@ -1011,7 +1038,7 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
         // group scans the fifteen in order: the kept axis starts at candidate
         // 0 (a face of A, valid whenever the pair is) and is replaced only by
         // a later one that exceeds it by tau_face (faces) or tau_edge (edges)
-        auto& cd = s.x.cand[wid];
+        auto& cd = s.x.wave[wid].cand;
         float* const cv = &cd.v[grp][0];
         cv[gl] = ok0 ? sv0 : -INFINITY;
         cv[gl + 8] = ok1 ? sv1 : -INFINITY;
