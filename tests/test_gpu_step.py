@@ -386,6 +386,33 @@ def test_long_incidence_lists(pm, layout, mc):
     assert out[1][1][0] == 0
 
 
+def test_two_waves_bitwise_on_many_touching_scenes(pm):
+    """Both waves of an env run narrowphase passes with live face pairs at
+    once (touching cubes, pushed into): each wave's candidate axes and clip
+    polygons live in its own LDS region, so 512 such envs in one launch give
+    bitwise the results of one wave per env (a shared region raced here)."""
+    parts = []
+    rng = np.random.default_rng(11)
+    for k in range(512):
+        b = touching_cubes("grid" if k % 2 == 0 else "rows")
+        # a push from outside the first cube's -x face toward it, offset in y
+        y = b.state[0, 1] + rng.uniform(-0.015, 0.015)
+        x0 = b.state[0, 0] - 0.02 - 0.016
+        b = scenes.Batch(b.env_offset, b.state, b.body, np.array([[x0, y, x0 + 0.05, y]]), b.target)
+        parts.append(b)
+    b = scenes.concat(parts)
+    out = []
+    for w in (1, 2):
+        sim = pm.Sim(max_envs=b.n_envs, max_bodies=b.n_bodies, max_contacts=256)
+        sim.set_launch_plan(small_waves=w, large_waves=w)
+        sim.set_state(b.env_offset, f32(b.state), f32(b.body))
+        sim.step(b.push.astype(np.float32), 20)
+        out.append((sim.get_state(), sim.env_status().copy(), sim.stats()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+    assert out[0][2][:, 1].sum() > 512 * 20 * 8   # many candidate pairs per substep
+
+
 def test_contact_capacity_classes_agree(pm):
     """The 128-, 256- and 512-contact kernels run the same algorithm in the
     same order, and multiply-adds are fused only where the source says so,
