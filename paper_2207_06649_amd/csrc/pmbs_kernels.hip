@@ -119,9 +119,7 @@ struct Smem {
   // angular sums (row ra x P or rb x P).  Padding codes point at the zero row.
   unsigned short inc[2][2 * C + 8 * MAXB];
   float4 lo[MAXB], hi[MAXB];         // AABBs: min and max corner (x, y, z, -)
-  int sorted[MAXB];                  // objects in min-x order (kept while still ordered)
   int lstart[MAXB];                  // incidence list starts
-  unsigned mask[MAXB];
   unsigned short pairs[MAX_PAIRS];
   int cab[C];                        // packed a | b << 8 | feature << 16 of each contact
   int wkey[C];                       // previous substep's contact keys (sorted)
@@ -300,17 +298,10 @@ __device__ __forceinline__ int opaque(int x) {
 __device__ __forceinline__ int lower_half(int v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false)[0]; }
 __device__ __forceinline__ int upper_half(int v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1]; }
 
-// Whole-wave shift by one lane (DPP wave_shl:1): lane l receives lane l + 1;
-// lane 63 receives 0 (a float) or the value's own bits (an int).  Callers
-// read only lanes below the object count (at most 33), never lane 63.
-__device__ __forceinline__ float wave_next(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
-}
 // value of lane ^ 1 (DPP quad permutation 1, 0, 3, 2)
 __device__ __forceinline__ float pair_swap(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, true));
 }
-__device__ __forceinline__ int wave_next(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
 
 // ------------------------------------------------------------------ clipping
 // the clip buffers of wave wid
@@ -689,7 +680,6 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
   int n_rewards = 0;
   long long stat_nc = 0, stat_pairs = 0, stat_sub = 0;
   const int n_obj = nb + 1;
-  bool order_kept = false;  // s.sorted holds a permutation of this env's objects
 
   // job 0 is the env's own simulation; job 1 (re-purposing) is one extra
   // simulation of another pair that spends the pushes left when job 0
@@ -803,8 +793,7 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     // wave when there are two, else the lead after the broadphase)
     int n_pairs = 0, nc_raw = 0;
     if (lead) {
-      // ---- 3. broadphase: AABBs; up to 16 objects every pair directly, more
-      // by a rank sort on min-x and a sweep
+      // ---- 3. broadphase: AABBs, then every pair of objects tested directly
       if (lane < n_obj) {
         f3 c = xyz(s.pos[lane]);
         f3 a0 = xyz(s.col[0][lane]), a1 = xyz(s.col[1][lane]), a2 = xyz(s.col[2][lane]);
@@ -814,19 +803,19 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
         float ez = fabsf(a0.z) * hh.x + fabsf(a1.z) * hh.y + fabsf(a2.z) * hh.z + p.margin;
         s.lo[lane] = make_float4(c.x - ex, c.y - ey, c.z - ez, 0.0f);
         s.hi[lane] = make_float4(c.x + ex, c.y + ey, c.z + ez, 0.0f);
-        s.mask[lane] = 0u;
       }
       wave_sync();
-      if (n_obj <= 16) {
-        // at most 16 objects: every pair (i, j), i < j, is tested directly,
-        // four rows i of sixteen columns j per pass (lane 16 (i - 4 q) + j),
+      {
+        // every pair (i, j), i < j, tested directly: columns j on the lanes
+        // (16 of them up to 16 objects, else 32) and 4 or 2 rows i per pass,
         // so lane order within a pass and pass order are the pairs'
         // lexicographic order and a ballot lists the overlapping ones
-        const int jj = lane & 15;
+        const int cs = n_obj <= 16 ? 4 : 5;   // log2 of the columns
+        const int jj = lane & ((1 << cs) - 1);
         const bool jin = jj < n_obj;
         const float4 jl = s.lo[jj], jh = s.hi[jj];
-        for (int q = 0; 4 * q < n_obj - 1; ++q) {
-          const int ii = 4 * q + (lane >> 4);
+        for (int i0 = 0; i0 < n_obj - 1; i0 += 64 >> cs) {
+          const int ii = i0 + (lane >> cs);
           const float4 il = s.lo[ii], ih = s.hi[ii];
           const bool hit = jin && ii < jj && il.x <= jh.x && jl.x <= ih.x && il.y <= jh.y && jl.y <= ih.y &&
                            il.z <= jh.z && jl.z <= ih.z;
@@ -835,98 +824,6 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
           const int rk = __builtin_amdgcn_mbcnt_hi((unsigned)(hm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)hm, 0u));
           if (hit) s.pairs[n_pairs + rk] = (unsigned short)((ii << 8) | jj);
           n_pairs += __popcll(hm);
-        }
-      } else {
-        // the previous substep's order is still the order when every object
-        // precedes the next one by (key, index); then the ranks need no update
-        bool order_ok = order_kept;
-        if (order_ok) {
-          const bool in = lane < n_obj;
-          const int o = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
-          float kx = in ? s.lo[o].x : INFINITY;
-          kx = kx == kx ? kx : INFINITY;
-          const float kn = wave_next(kx);
-          const int on = wave_next(o);
-          const bool bad = lane + 1 < n_obj && !(kx < kn || (kx == kn && o < on));
-          order_ok = __ballot(bad) == 0ull;
-        }
-        order_kept = true;
-        if (!order_ok) {
-          // rank of each object's min-x key (ties by index; NaN keys sort last,
-          // so the ranks stay a permutation whatever the state holds)
-          float key = lane < n_obj ? s.lo[lane].x : INFINITY;
-          key = key == key ? key : INFINITY;
-          // lanes past n_obj hold +inf keys and never count, so the loop runs
-          // over fixed lanes (independent readlanes, two counters) with no guard
-          const int ikey = __float_as_int(key);
-          int r0 = 0, r1 = 0;
-    #pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
-            const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
-            if (j & 1) r1 += c;
-            else r0 += c;
-          }
-          if (n_obj > 16) {
-    #pragma unroll
-            for (int j = 16; j < 32; ++j) {
-              const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
-              const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
-              if (j & 1) r1 += c;
-              else r0 += c;
-            }
-          }
-          const int rank = r0 + r1;
-          if (lane < n_obj) s.sorted[rank] = lane;
-        }
-        wave_sync();
-        {
-          // sweep: lane r holds the box at sorted position r and compares it with
-          // the boxes d = 1, 2, ... positions later until every lane has passed
-          // its box's max-x; the later boxes' bounds move down one lane per step
-          // (DPP whole-wave shift, no LDS round trip)
-          const bool in = lane < n_obj;
-          const int oi = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
-          const float4 lb = s.lo[oi], hb4 = s.hi[oi];
-          const float lox = in ? lb.x : INFINITY, hix = in ? hb4.x : -INFINITY;
-          const float loy = in ? lb.y : 0.0f, hiy = in ? hb4.y : 0.0f;
-          const float loz = in ? lb.z : 0.0f, hiz = in ? hb4.z : 0.0f;
-          float lox_q = lox, loy_q = loy, hiy_q = hiy, loz_q = loz, hiz_q = hiz;
-          int oj = oi;
-          // two steps per trip: sorted min-x makes a lane that fails at step d
-          // fail at every later step, so a trip whose second step has no lane
-          // left ends the sweep
-          for (int d = 1; d < n_obj; d += 2) {
-            bool more = false;
-    #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              lox_q = wave_next(lox_q);
-              loy_q = wave_next(loy_q);
-              hiy_q = wave_next(hiy_q);
-              loz_q = wave_next(loz_q);
-              hiz_q = wave_next(hiz_q);
-              oj = wave_next(oj);
-              const bool go = lane + d + h < n_obj && lox_q <= hix;
-              if (go && loy <= hiy_q && loy_q <= hiy && loz <= hiz_q && loz_q <= hiz) {
-                const int lo_i = oi < oj ? oi : oj, hi_i = oi < oj ? oj : oi;
-                atomicOr(&s.mask[lo_i], 1u << hi_i);
-              }
-              if (h == 1) more = __ballot(go) != 0ull;
-            }
-            if (!more) break;
-          }
-        }
-        wave_sync();
-        {
-          unsigned m = lane < n_obj ? s.mask[lane] : 0u;
-          int off = wave_excl_scan(__popc(m), &n_pairs);
-          int t = 0;
-          while (m) {
-            int j = __builtin_ctz(m);
-            m &= m - 1;
-            if (off + t < MAX_PAIRS) s.pairs[off + t] = (unsigned short)((lane << 8) | j);
-            ++t;
-          }
         }
       }
       wave_sync();
