@@ -29,7 +29,8 @@ struct pmbs_sim {
   // queued rollouts: d_order holds the small-class list at [0, max_envs) and
   // the large-class list at [max_envs, 2 max_envs); d_ctl holds the queue
   // counters [0..3] (small, large, fallback 256, fallback 512), the
-  // overflow counts [4..5] and the list lengths [8..9]; d_ovf4 / d_ovf8 are
+  // overflow counts [4..5] and the list lengths [8..9] (a work-ordered
+  // step uses [16..23], its per-XCD queues); d_ovf4 / d_ovf8 are
   // the overflow lists feeding the 256- and 512-contact fallbacks
   int32_t *d_ctl, *d_ovf4, *d_ovf8;
   int32_t *d_bc_base;      // [max_envs] optional body-constant rows per env

@@ -54,6 +54,7 @@ struct StepArgs {
   // work distribution
   const int* order;         // work item -> env (null: identity)
   int* queue;               // device counter (null: one block per work item)
+  int xcd_queues;           // eight counters queue[0..7], one per XCD's contiguous run of work items
   const int* work_count;    // device count of work items (null: n_envs)
   // an env whose contacts overflow this instantiation's capacity stops
   // before writing anything and appends itself here, for a re-run in a
@@ -119,8 +120,8 @@ hipError_t launch_step(const StepArgs& a, int max_contacts, hipStream_t stream, 
 hipError_t launch_step_class(const StepArgs& a, int max_contacts, hipStream_t stream, int grid, int waves = 1);
 // cost pass: one block per env writes a.cost_key[e], the env's work
 // estimate (contacts + candidate pairs at the start pose, + 3 for a valid
-// push); order: the envs by descending estimate into order[0, n), and the
-// queue counter cleared
+// push); order: each XCD's contiguous run of envs by descending estimate
+// into order[0, n), and the eight queue counters queue[0..7] cleared
 hipError_t launch_cost(const StepArgs& a, int max_contacts, hipStream_t stream, int waves = 1);
 hipError_t launch_order(const int* key, int n, int* order, int* queue, hipStream_t stream);
 hipError_t launch_zero(int* p, int n, hipStream_t stream);

@@ -1500,18 +1500,21 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
 // XCD has its own L2.  Neighbouring envs share the cache lines of every SoA
 // row, so XCD x gets one contiguous run of the n items: block i takes item
 // start(i mod 8) + i / 8 (a permutation of 0..n-1 for any n).
-__device__ __forceinline__ int xcd_item(int bid, int n) {
-  constexpr int X = 8;
-  const int q = n / X, r = n - q * X;
-  const int x = bid % X, j = bid / X;
-  return x * q + (x < r ? x : r) + j;
+__device__ __forceinline__ int xcd_start(int x, int n) {
+  const int q = n / 8, r = n - q * 8;
+  return x * q + (x < r ? x : r);
 }
+__device__ __forceinline__ int xcd_item(int bid, int n) { return xcd_start(bid % 8, n) + bid / 8; }
 
 // ------------------------------------------------------------------ the step kernel
 // One wave per environment.  Without a work queue block i runs work item
 // env_base + xcd_item(i); with one, blocks pull work items from the device counter
 // until it passes n_envs (every block reaches that exit).  order[] maps
 // work items to environments (longest horizon first for uneven rollouts).
+// With XCD queues (xcd_queues, a grid of at least eight blocks) block i
+// pulls from counter queue[i mod 8] the items of XCD i mod 8's own
+// contiguous run, order[start(x) ..], so each XCD's L2 holds its own envs'
+// state rows, as without a queue.
 // The table's LDS entries: the same for every env, and no phase writes
 // them, so a workgroup sets them once.
 template <class S>
@@ -1536,17 +1539,25 @@ __global__ __launch_bounds__(64 * W, 2) void step_kernel(StepArgs g) {
   __shared__ Smem<K, W> s;
   __shared__ int next;
   init_plane(s, g.p);
-  const int n_work = g.work_count ? *g.work_count : g.n_envs;
+  int n_work = g.work_count ? *g.work_count : g.n_envs;
+  int* queue = g.queue;
+  int seg = 0;
+  if (g.xcd_queues) {
+    const int x = blockIdx.x % 8;
+    seg = xcd_start(x, n_work);
+    n_work = xcd_start(x + 1, n_work) - seg;
+    queue += x;
+  }
   int wi = g.queue ? 0 : g.env_base + xcd_item(blockIdx.x, gridDim.x);
   for (;;) {
     if (g.queue) {
-      if (threadIdx.x == 0) next = atomicAdd(g.queue, 1);
+      if (threadIdx.x == 0) next = atomicAdd(queue, 1);
       __syncthreads();
       wi = next;
       __syncthreads();
     }
     if (wi >= n_work) break;
-    run_env<K, W, false>(s, g, g.order ? g.order[wi] : wi);
+    run_env<K, W, false>(s, g, g.order ? g.order[seg + wi] : wi);
     if (!g.queue) break;
     __syncthreads();
   }
@@ -1563,24 +1574,27 @@ __global__ __launch_bounds__(64 * W, 2) void cost_kernel(StepArgs g) {
   if (e < g.n_envs) run_env<K, W, true>(s, g, e);
 }
 
-// Schedule of a queued step: the envs by descending work estimate, a
-// counting sort of the estimates clamped to [0, ORDER_BINS).  Equal
-// estimates come in the order of the LDS atomics (an env's result does
-// not depend on when it runs).  One workgroup of ORDER_BINS threads; it
-// also clears the queue counter the step kernel pulls from.
+// Schedule of a queued step: each XCD's contiguous run of envs (xcd_start)
+// by descending work estimate, a counting sort of the estimates clamped to
+// [0, ORDER_BINS).  Equal estimates come in the order of the LDS atomics
+// (an env's result does not depend on when it runs).  Block x of eight
+// (ORDER_BINS threads each) sorts run x into order[start(x) ..] and clears
+// the XCD's queue counter queue[x].
 constexpr int ORDER_BINS = 1024;
 __global__ __launch_bounds__(ORDER_BINS) void order_kernel(const int* __restrict__ key, int n, int* __restrict__ order,
                                                           int* queue) {
   __shared__ int start[ORDER_BINS];
   __shared__ int wsum[ORDER_BINS / 64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int e0 = xcd_start(blockIdx.x, n), e1 = xcd_start(blockIdx.x + 1, n);
+  order += e0;
   auto bin = [&](int e) {
     const int k = key[e];
     return k < 0 ? 0 : (k >= ORDER_BINS ? ORDER_BINS - 1 : k);
   };
   start[t] = 0;
   __syncthreads();
-  for (int e = t; e < n; e += ORDER_BINS) atomicAdd(&start[bin(e)], 1);
+  for (int e = e0 + t; e < e1; e += ORDER_BINS) atomicAdd(&start[bin(e)], 1);
   __syncthreads();
   // thread t owns bin ORDER_BINS - 1 - t (largest first): the envs of
   // larger bins come before its own
@@ -1597,8 +1611,8 @@ __global__ __launch_bounds__(ORDER_BINS) void order_kernel(const int* __restrict
   for (int k = 0; k < w; ++k) before += wsum[k];
   start[r] = before + v - c;
   __syncthreads();
-  for (int e = t; e < n; e += ORDER_BINS) order[atomicAdd(&start[bin(e)], 1)] = e;
-  if (t == 0) *queue = 0;
+  for (int e = e0 + t; e < e1; e += ORDER_BINS) order[atomicAdd(&start[bin(e)], 1)] = e;
+  if (t == 0) queue[blockIdx.x] = 0;
 }
 
 __global__ void zero_kernel(int* p, int n) {
@@ -1765,7 +1779,7 @@ hipError_t launch_cost(const StepArgs& a, int max_contacts, hipStream_t stream, 
 
 hipError_t launch_order(const int* key, int n, int* order, int* queue, hipStream_t stream) {
   if (n <= 0 || !key || !order || !queue) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(ORDER_BINS), 0, stream, key, n, order, queue);
+  hipLaunchKernelGGL(order_kernel, dim3(8), dim3(ORDER_BINS), 0, stream, key, n, order, queue);
   return hipGetLastError();
 }
 

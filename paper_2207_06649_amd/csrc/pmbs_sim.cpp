@@ -671,17 +671,20 @@ pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_de
   const int mc = sim->cfg.max_contacts, waves = plan_waves(sim, mc);
   hipError_t e = hipSuccess;
   const int grid = class_grid(sim, mc, 0, waves);
-  if (sim->plan.order != 0 && n_substeps > 0 && sim->n_envs > grid) {
+  if (sim->plan.order != 0 && n_substeps > 0 && sim->n_envs > grid && grid >= 8) {
     // more envs than resident workgroups: a cost pass estimates each env's
     // work at its start pose, and persistent workgroups take the envs from
-    // a queue, largest estimate first, so the short ones fill the end of
-    // the launch (the key array is the large-class half of the order list)
+    // queues, largest estimate first, so the short ones fill the end of the
+    // launch; one queue per XCD over its own contiguous run of envs (the
+    // key array is the large-class half of the order list, the counters
+    // are d_ctl[16..23], which rollouts leave alone)
     StepArgs c = a;
     c.cost_key = sim->d_order + sim->cfg.max_envs;
     e = launch_cost(c, mc, sim->stream, waves);
-    if (e == hipSuccess) e = launch_order(c.cost_key, sim->n_envs, sim->d_order, sim->d_ctl, sim->stream);
+    if (e == hipSuccess) e = launch_order(c.cost_key, sim->n_envs, sim->d_order, sim->d_ctl + 16, sim->stream);
     a.order = sim->d_order;
-    a.queue = sim->d_ctl;
+    a.queue = sim->d_ctl + 16;
+    a.xcd_queues = 1;
     if (e == hipSuccess) e = launch_step_class(a, mc, sim->stream, grid, waves);
   } else {
     e = launch_step(a, mc, sim->stream, waves);
