@@ -132,7 +132,12 @@ pmbs_status pmbs_sim_get_state(pmbs_sim_t* sim, float* state_out, int32_t dst_is
  * moves at push_speed for round(|e - s| / (push_speed dt)) substeps and then
  * stays.  A push whose start pose overlaps a box is discarded (Sec. IV-B):
  * the pusher is parked away, the substeps still run and the env status gets
- * PMBS_ENV_PUSH_INVALID.  Asynchronous. */
+ * PMBS_ENV_PUSH_INVALID.  With more envs than resident workgroups and launch
+ * plan order 1 (the default) the step is three launches on the stream: a
+ * cost pass (each env's contacts + candidate pairs at its start pose, + 3
+ * for a valid push), a sort of each XCD's envs by that estimate, and
+ * persistent workgroups taking the envs largest first; every env's result
+ * is bitwise that of one workgroup per env (order 0).  Asynchronous. */
 pmbs_status pmbs_sim_step(pmbs_sim_t* sim, const float* push, int32_t push_is_device,
                           int32_t n_substeps);
 
@@ -181,7 +186,8 @@ typedef struct pmbs_launch_plan {
   int32_t small_max_bodies;    /* -1: no env in the 128-contact kernel */
   int32_t small_blocks_per_cu; /* persistent workgroups per CU, 0: as many as fit */
   int32_t large_blocks_per_cu;
-  int32_t order;               /* 0: horizon first; 1: horizon x (bodies + 4) first */
+  int32_t order;               /* queued rollouts: 0 horizon first, 1 horizon x (bodies + 4) first;
+                                  pmbs_sim_step: 1 largest work estimate first (see there), 0 index order */
   int32_t small_waves;         /* workgroup shape of the 128-contact class: waves per environment (1 or
                                   2: a second wave takes half the contact slots and every second
                                   narrowphase pass; bitwise the same result) */
