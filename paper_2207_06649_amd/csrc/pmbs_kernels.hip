@@ -9,14 +9,14 @@
 //   lane b + 32  owns body b's orientation, angular velocity, world inverse
 //                inertia (so two lanes carry every body)
 //   lane l       holds contacts l, l+64, l+128, ... in VGPR slots (K slots)
-// Shared state goes through LDS: body frames, the broadphase order and pair
-// list, the contact staging array (reused for the impulse exchange of the
+// Shared state goes through LDS: body frames, AABBs and the pair list, the
+// contact staging array (reused for the impulse exchange of the
 // solver), per-body incidence lists, warm-start keys and impulses, and the
 // clip polygons of face clipping.
 //
 // Per substep (all in one launch, state stays in registers/LDS; HBM is
 // touched once in and once out per call):
-//   velocity stage -> frames -> sort-and-sweep broadphase -> box-plane and
+//   velocity stage -> frames -> all-pairs AABB broadphase -> box-plane and
 //   box-box/pusher-box contacts (15-axis SAT, Sutherland-Hodgman face
 //   clipping or edge-edge closest points) -> contact prep (mass splitting,
 //   Tonge et al. 2012) -> I projected-Jacobi iterations (normal clamp, then
