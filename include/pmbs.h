@@ -202,7 +202,9 @@ pmbs_status pmbs_sim_get_launch_plan(const pmbs_sim_t* sim, pmbs_launch_plan* pl
 
 /* Autotuner of the launch plan for one rollout workload (same arguments as
  * pmbs_sim_rollout; PMBS_ROLLOUT_WRITE_STATE is refused because every
- * candidate re-runs the rollout from the same inputs).  Candidates are timed
+ * candidate re-runs the rollout from the same inputs).  Candidates run
+ * queued, as replayed graphs when flags hold PMBS_ROLLOUT_GRAPH (after an
+ * untimed run that captures the plan's graph), and are timed
  * with HIP events on the simulator's stream, reps runs each, by coordinate
  * descent over small_max_bodies and the waves per environment of each class
  * (two passes), then blocks per CU and order; the three fastest candidates

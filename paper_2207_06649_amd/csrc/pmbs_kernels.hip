@@ -9,14 +9,14 @@
 //   lane b + 32  owns body b's orientation, angular velocity, world inverse
 //                inertia (so two lanes carry every body)
 //   lane l       holds contacts l, l+64, l+128, ... in VGPR slots (K slots)
-// Shared state goes through LDS: body frames, AABBs and the pair list, the
-// contact staging array (reused for the impulse exchange of the
+// Shared state goes through LDS: body frames, AABBs, the broadphase order
+// and pair list, the contact staging array (reused for the impulse exchange of the
 // solver), per-body incidence lists, warm-start keys and impulses, and the
 // clip polygons of face clipping.
 //
 // Per substep (all in one launch, state stays in registers/LDS; HBM is
 // touched once in and once out per call):
-//   velocity stage -> frames -> all-pairs AABB broadphase -> box-plane and
+//   velocity stage -> frames -> AABB broadphase -> box-plane and
 //   box-box/pusher-box contacts (15-axis SAT, Sutherland-Hodgman face
 //   clipping or edge-edge closest points) -> contact prep (mass splitting,
 //   Tonge et al. 2012) -> I projected-Jacobi iterations (normal clamp, then
@@ -119,7 +119,9 @@ struct Smem {
   // angular sums (row ra x P or rb x P).  Padding codes point at the zero row.
   unsigned short inc[2][2 * C + 8 * MAXB];
   float4 lo[MAXB], hi[MAXB];         // AABBs: min and max corner (x, y, z, -)
+  int sorted[W > 1 ? MAXB : 1];      // two waves: objects in min-x order (kept while still ordered)
   int lstart[MAXB];                  // incidence list starts
+  unsigned mask[W > 1 ? MAXB : 1];   // two waves: sweep pair masks
   unsigned short pairs[MAX_PAIRS];
   int cab[C];                        // packed a | b << 8 | feature << 16 of each contact
   int wkey[C];                       // previous substep's contact keys (sorted)
@@ -298,10 +300,17 @@ __device__ __forceinline__ int opaque(int x) {
 __device__ __forceinline__ int lower_half(int v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false)[0]; }
 __device__ __forceinline__ int upper_half(int v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1]; }
 
+// Whole-wave shift by one lane (DPP wave_shl:1): lane l receives lane l + 1;
+// lane 63 receives 0 (a float) or the value's own bits (an int).  Callers
+// read only lanes below the object count (at most 33), never lane 63.
+__device__ __forceinline__ float wave_next(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
 // value of lane ^ 1 (DPP quad permutation 1, 0, 3, 2)
 __device__ __forceinline__ float pair_swap(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, true));
 }
+__device__ __forceinline__ int wave_next(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
 
 // ------------------------------------------------------------------ clipping
 // the clip buffers of wave wid
@@ -421,11 +430,8 @@ __device__ __forceinline__ float eff_mass_side(const S& s, int i, f3 r, f3 d) {
   return s.half[i].w + dot(cr, m);
 }
 
-// side_a: some contact of the lane's slot has a body on side a (else every
-// one touches the table there, whose effective-mass terms are exactly zero:
-// ca x 0 + cb x m_b rounds as cb x m_b alone, so skipping them changes no bit)
 template <class S>
-__device__ __forceinline__ void prep_contact(const S& s, int c, const Params& p, int nwarm, bool side_a, Contact* ct) {
+__device__ __forceinline__ void prep_contact(const S& s, int c, const Params& p, int nwarm, Contact* ct) {
   float4 s0 = s.u.stage[c][0], s1 = s.u.stage[c][1];
   f3 pt = xyz(s0);
   float sep = s0.w;
@@ -445,15 +451,9 @@ __device__ __forceinline__ void prep_contact(const S& s, int c, const Params& p,
   ct->t2 = t2;
   ct->t1 = t1;
   float ca = (float)s.cnt[a], cb = (float)s.cnt[b];
-  if (side_a) {
-    ct->kn = rcp(ca * eff_mass_side(s, a, ct->ra, n) + cb * eff_mass_side(s, b, ct->rb, n));
-    ct->kt1 = rcp(ca * eff_mass_side(s, a, ct->ra, t1) + cb * eff_mass_side(s, b, ct->rb, t1));
-    ct->kt2 = rcp(ca * eff_mass_side(s, a, ct->ra, t2) + cb * eff_mass_side(s, b, ct->rb, t2));
-  } else {
-    ct->kn = rcp(cb * eff_mass_side(s, b, ct->rb, n));
-    ct->kt1 = rcp(cb * eff_mass_side(s, b, ct->rb, t1));
-    ct->kt2 = rcp(cb * eff_mass_side(s, b, ct->rb, t2));
-  }
+  ct->kn = rcp(ca * eff_mass_side(s, a, ct->ra, n) + cb * eff_mass_side(s, b, ct->rb, n));
+  ct->kt1 = rcp(ca * eff_mass_side(s, a, ct->ra, t1) + cb * eff_mass_side(s, b, ct->rb, t1));
+  ct->kt2 = rcp(ca * eff_mass_side(s, a, ct->ra, t2) + cb * eff_mass_side(s, b, ct->rb, t2));
   ct->mu = 0.5f * (s.iwb[a].z + s.iwb[b].z);
   ct->vstar = sep > 0.0f ? -sep * p.inv_dt : p.beta * fmaxf(-sep - p.slop, 0.0f) * p.inv_dt;
   // warm start from the previous substep's contact with the same key
@@ -689,6 +689,7 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
   int n_rewards = 0;
   long long stat_nc = 0, stat_pairs = 0, stat_sub = 0;
   const int n_obj = nb + 1;
+  bool order_kept = false;  // s.sorted holds a permutation of this env's objects
 
   // job 0 is the env's own simulation; job 1 (re-purposing) is one extra
   // simulation of another pair that spends the pushes left when job 0
@@ -803,6 +804,8 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     int n_pairs = 0, nc_raw = 0;
     if (lead) {
       // ---- 3. broadphase: AABBs, then every pair of objects tested directly
+      // (with two waves per env and more than 16 objects: a rank sort on
+      // min-x and a sweep)
       if (lane < n_obj) {
         f3 c = xyz(s.pos[lane]);
         f3 a0 = xyz(s.col[0][lane]), a1 = xyz(s.col[1][lane]), a2 = xyz(s.col[2][lane]);
@@ -812,13 +815,17 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
         float ez = fabsf(a0.z) * hh.x + fabsf(a1.z) * hh.y + fabsf(a2.z) * hh.z + p.margin;
         s.lo[lane] = make_float4(c.x - ex, c.y - ey, c.z - ez, 0.0f);
         s.hi[lane] = make_float4(c.x + ex, c.y + ey, c.z + ez, 0.0f);
+        if constexpr (W > 1) s.mask[lane] = 0u;
       }
       wave_sync();
-      {
+      if (W == 1 || n_obj <= 16) {
         // every pair (i, j), i < j, tested directly: columns j on the lanes
         // (16 of them up to 16 objects, else 32) and 4 or 2 rows i per pass,
         // so lane order within a pass and pass order are the pairs'
-        // lexicographic order and a ballot lists the overlapping ones
+        // lexicographic order and a ballot lists the overlapping ones.  With
+        // two waves per env (an env's latency, not throughput, counts) more
+        // than 16 objects take the sort and sweep below, whose DPP steps
+        // have no LDS round trip per pass.
         const int cs = n_obj <= 16 ? 4 : 5;   // log2 of the columns
         const int jj = lane & ((1 << cs) - 1);
         const bool jin = jj < n_obj;
@@ -833,6 +840,98 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
           const int rk = __builtin_amdgcn_mbcnt_hi((unsigned)(hm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)hm, 0u));
           if (hit) s.pairs[n_pairs + rk] = (unsigned short)((ii << 8) | jj);
           n_pairs += __popcll(hm);
+        }
+      } else {
+        // the previous substep's order is still the order when every object
+        // precedes the next one by (key, index); then the ranks need no update
+        bool order_ok = order_kept;
+        if (order_ok) {
+          const bool in = lane < n_obj;
+          const int o = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
+          float kx = in ? s.lo[o].x : INFINITY;
+          kx = kx == kx ? kx : INFINITY;
+          const float kn = wave_next(kx);
+          const int on = wave_next(o);
+          const bool bad = lane + 1 < n_obj && !(kx < kn || (kx == kn && o < on));
+          order_ok = __ballot(bad) == 0ull;
+        }
+        order_kept = true;
+        if (!order_ok) {
+          // rank of each object's min-x key (ties by index; NaN keys sort last,
+          // so the ranks stay a permutation whatever the state holds)
+          float key = lane < n_obj ? s.lo[lane].x : INFINITY;
+          key = key == key ? key : INFINITY;
+          // lanes past n_obj hold +inf keys and never count, so the loop runs
+          // over fixed lanes (independent readlanes, two counters) with no guard
+          const int ikey = __float_as_int(key);
+          int r0 = 0, r1 = 0;
+    #pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
+            const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
+            if (j & 1) r1 += c;
+            else r0 += c;
+          }
+          if (n_obj > 16) {
+    #pragma unroll
+            for (int j = 16; j < 32; ++j) {
+              const float kj = __int_as_float(__builtin_amdgcn_readlane(ikey, j));
+              const int c = (kj < key || (kj == key && j < lane)) ? 1 : 0;
+              if (j & 1) r1 += c;
+              else r0 += c;
+            }
+          }
+          const int rank = r0 + r1;
+          if (lane < n_obj) s.sorted[rank] = lane;
+        }
+        wave_sync();
+        {
+          // sweep: lane r holds the box at sorted position r and compares it with
+          // the boxes d = 1, 2, ... positions later until every lane has passed
+          // its box's max-x; the later boxes' bounds move down one lane per step
+          // (DPP whole-wave shift, no LDS round trip)
+          const bool in = lane < n_obj;
+          const int oi = in ? (s.sorted[lane] & (MAXB - 1)) : 0;
+          const float4 lb = s.lo[oi], hb4 = s.hi[oi];
+          const float lox = in ? lb.x : INFINITY, hix = in ? hb4.x : -INFINITY;
+          const float loy = in ? lb.y : 0.0f, hiy = in ? hb4.y : 0.0f;
+          const float loz = in ? lb.z : 0.0f, hiz = in ? hb4.z : 0.0f;
+          float lox_q = lox, loy_q = loy, hiy_q = hiy, loz_q = loz, hiz_q = hiz;
+          int oj = oi;
+          // two steps per trip: sorted min-x makes a lane that fails at step d
+          // fail at every later step, so a trip whose second step has no lane
+          // left ends the sweep
+          for (int d = 1; d < n_obj; d += 2) {
+            bool more = false;
+    #pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              lox_q = wave_next(lox_q);
+              loy_q = wave_next(loy_q);
+              hiy_q = wave_next(hiy_q);
+              loz_q = wave_next(loz_q);
+              hiz_q = wave_next(hiz_q);
+              oj = wave_next(oj);
+              const bool go = lane + d + h < n_obj && lox_q <= hix;
+              if (go && loy <= hiy_q && loy_q <= hiy && loz <= hiz_q && loz_q <= hiz) {
+                const int lo_i = oi < oj ? oi : oj, hi_i = oi < oj ? oj : oi;
+                atomicOr(&s.mask[lo_i], 1u << hi_i);
+              }
+              if (h == 1) more = __ballot(go) != 0ull;
+            }
+            if (!more) break;
+          }
+        }
+        wave_sync();
+        {
+          unsigned m = lane < n_obj ? s.mask[lane] : 0u;
+          int off = wave_excl_scan(__popc(m), &n_pairs);
+          int t = 0;
+          while (m) {
+            int j = __builtin_ctz(m);
+            m &= m - 1;
+            if (off + t < MAX_PAIRS) s.pairs[off + t] = (unsigned short)((lane << 8) | j);
+            ++t;
+          }
         }
       }
       wave_sync();
@@ -1189,8 +1288,7 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
 #pragma unroll
     for (int ls = 0; ls < KW; ++ls) {
       const int c = 64 * (ls * W + wid) + lane;
-      const bool side_a = __ballot(c < nc && (s.cab[c < nc ? c : 0] & 255) != PLANE) != 0ull;
-      if (c < nc) prep_contact(s, c, p, nwarm, side_a, &ct[ls]);
+      if (c < nc) prep_contact(s, c, p, nwarm, &ct[ls]);
     }
 
     // ---- 7. projected Jacobi, I iterations
@@ -1248,11 +1346,6 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       }
     }
     const int cpad = (ccount + 7) & ~7;
-    // lane pairs whose lists all hold at most four entries (bodies touched by
-    // at most four contacts, e.g. boxes resting on the table alone): entries
-    // sh + 4 and sh + 6 are zero rows, whose terms change no sum (a partial
-    // sum is never -0), so the wave skips them
-    const bool short_lists = two && __ballot(sum_on && ccount > 4) == 0ull;
     auto row_of = [&](unsigned code) { return *reinterpret_cast<const float4*>(imp_base + (code & 0xfffeu)); };
     auto reg_row = [&](unsigned off) { return *reinterpret_cast<const float4*>(imp_base + off); };
     auto add_signed = [](f3 a, float sg, float4 val) {
@@ -1263,12 +1356,7 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     auto apply_sums = [&]() {
       if (!sum_on) return;
       f3 a0 = mk(0, 0, 0), a1 = mk(0, 0, 0);
-      if (two && short_lists) {
-        const float4 v0 = reg_row(radr[0]), v1 = reg_row(radr[1]);
-        a0 = add_signed(a0, rsg[0], v0);
-        a0 = add_signed(a0, rsg[1], v1);
-        a1 = mk(pair_swap(a0.x), pair_swap(a0.y), pair_swap(a0.z));
-      } else if (two) {
+      if (two) {
         {
           float4 val[4];
 #pragma unroll

@@ -4,8 +4,9 @@
 // 128-contact kernel, the workgroup shape of each class (one or two waves
 // per environment), the persistent workgroups per CU of each class, and
 // the work order.  Each candidate runs the caller's rollout (from the same
-// inputs, so its outputs are unchanged) and is timed with HIP events on the
-// simulator's stream; coordinate descent keeps the fastest median, and the
+// inputs, so its outputs are unchanged) in the caller's launch form (graph
+// replay or not) and is timed with HIP events on the simulator's stream;
+// coordinate descent keeps the fastest median, and the
 // three fastest candidates are timed again (at least five runs each) before
 // the winner is installed.  Results are cached in a text file, one line per
 // workload key.
@@ -30,10 +31,10 @@ using namespace pmbs;
 
 namespace {
 
-// device, library build, configuration and a coarse histogram of the
-// workload (body counts in buckets of 4, horizons, env count rounded to a
-// power of two)
-std::string workload_key(pmbs_sim_t* sim, const int32_t* act_offset, int32_t n_substeps, int32_t max_h) {
+// device, library build, configuration, graph or eager launches and a
+// coarse histogram of the workload (body counts in buckets of 4, horizons,
+// env count rounded to a power of two)
+std::string workload_key(pmbs_sim_t* sim, const int32_t* act_offset, int32_t n_substeps, int32_t max_h, bool graph) {
   std::ostringstream k;
   int dev = 0;
   hipDeviceProp_t prop;
@@ -49,7 +50,7 @@ std::string workload_key(pmbs_sim_t* sim, const int32_t* act_offset, int32_t n_s
   int e2 = 1;
   while (e2 < n) e2 <<= 1;
   k << arch << "/" << cus << "cu/" << PMBS_BUILD_ID << "/mc" << sim->cfg.max_contacts << "/it" << sim->cfg.solver_iters
-    << "/sub" << n_substeps << "/h" << max_h << "/E" << e2;
+    << "/sub" << n_substeps << "/h" << max_h << "/E" << e2 << (graph ? "/graph" : "/eager");
   std::vector<int> nb_hist(8, 0), h_hist(std::min(max_h, 16) + 1, 0);
   for (int e = 0; e < n; ++e) {
     const int nb = sim->host_offset[e + 1] - sim->host_offset[e];
@@ -107,9 +108,13 @@ pmbs_status pmbs_sim_autotune(pmbs_sim_t* sim, const int32_t* actions, const int
   if (flags & PMBS_ROLLOUT_WRITE_STATE)
     return fail(PMBS_ERR_INVALID_ARG, "autotune re-runs the rollout: PMBS_ROLLOUT_WRITE_STATE is not allowed");
   if (reps < 1 || reps > 100) return fail(PMBS_ERR_INVALID_ARG, "reps must be in [1, 100]");
-  flags = (flags | PMBS_ROLLOUT_QUEUE) & ~PMBS_ROLLOUT_GRAPH;
+  // candidates run in the caller's form: queued, and replayed as a graph
+  // when PMBS_ROLLOUT_GRAPH is given (a plan can be faster as separate
+  // launches than as a replayed graph, or the other way round)
+  flags |= PMBS_ROLLOUT_QUEUE;
+  const bool graph = (flags & PMBS_ROLLOUT_GRAPH) != 0;
   if (cached) *cached = 0;
-  const std::string key = workload_key(sim, act_offset, n_substeps, max_h);
+  const std::string key = workload_key(sim, act_offset, n_substeps, max_h, graph);
   if (cache_path) {
     pmbs_launch_plan p;
     float t = 0.0f;
@@ -139,6 +144,12 @@ pmbs_status pmbs_sim_autotune(pmbs_sim_t* sim, const int32_t* actions, const int
   auto time_plan = [&](const pmbs_launch_plan& p, float* med) -> pmbs_status {
     pmbs_status s = pmbs_sim_set_launch_plan(sim, &p);
     if (s != PMBS_OK) return s;
+    if (graph) {
+      // untimed run: the graph of a new plan is captured on its first use
+      s = pmbs_sim_rollout(sim, actions, act_offset, src_slot, child_slot, target, 0, n_substeps, width, d_rewards,
+                           max_h, d_reward_count, flags);
+      if (s != PMBS_OK) return s;
+    }
     std::vector<float> ts;
     for (int r = 0; r < reps; ++r) {
       hipError_t he = hipEventRecord(t0, sim->stream);
