@@ -320,6 +320,14 @@ hipError_t enqueue_queued(pmbs_sim_t* sim, const StepArgs& a, hipStream_t stream
   int* ctl = sim->d_ctl;
   const pmbs_launch_plan& pl = sim->plan;
   const int ws = plan_waves(sim, 128), wl = plan_waves(sim, 256);
+  // persistent workgroups of the two classes; with the counts known (no
+  // capture) never more than the class has envs, so a batch of at most one
+  // env per CU gets one workgroup per CU (none sharing a CU with another)
+  int grid_s = class_grid(sim, 128, pl.small_blocks_per_cu, ws), grid_l = class_grid(sim, 256, pl.large_blocks_per_cu, wl);
+  if (skip_empty) {
+    grid_s = std::max(1, std::min(grid_s, n_small));
+    grid_l = std::max(1, std::min(grid_l, n_large));
+  }
   hipError_t e = launch_zero(ctl, 6, stream);
   if (e != hipSuccess) return e;
   StepArgs sm = a, lg = a, f4 = a, f8 = a;
@@ -327,8 +335,7 @@ hipError_t enqueue_queued(pmbs_sim_t* sim, const StepArgs& a, hipStream_t stream
   sm.work_count = ctl + 8;
   sm.queue = ctl + 0;
   if (mc == 128) {
-    if (!skip_empty || n_small > 0)
-      e = launch_step_class(sm, 128, stream, class_grid(sim, 128, pl.small_blocks_per_cu, ws), ws);
+    if (!skip_empty || n_small > 0) e = launch_step_class(sm, 128, stream, grid_s, ws);
     if (e == hipSuccess && va) e = launch_valid_counted(sim, *va, stream);
     return e;
   }
@@ -351,14 +358,11 @@ hipError_t enqueue_queued(pmbs_sim_t* sim, const StepArgs& a, hipStream_t stream
   if (run_large) {
     if ((e = hipEventRecord(sim->ev_fork, stream)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(sim->side, sim->ev_fork, 0)) != hipSuccess) return e;
-    if ((e = launch_step_class(lg, 256, sim->side, class_grid(sim, 256, pl.large_blocks_per_cu, wl), wl)) !=
-        hipSuccess)
-      return e;
+    if ((e = launch_step_class(lg, 256, sim->side, grid_l, wl)) != hipSuccess) return e;
     if ((e = hipEventRecord(sim->ev_join, sim->side)) != hipSuccess) return e;
   }
   if (run_small) {
-    if ((e = launch_step_class(sm, 128, stream, class_grid(sim, 128, pl.small_blocks_per_cu, ws), ws)) != hipSuccess)
-      return e;
+    if ((e = launch_step_class(sm, 128, stream, grid_s, ws)) != hipSuccess) return e;
     if ((e = launch_step_class(f4, 256, stream, class_grid(sim, 256, pl.large_blocks_per_cu, wl), wl)) != hipSuccess)
       return e;
   }
