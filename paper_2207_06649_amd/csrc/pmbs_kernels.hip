@@ -430,8 +430,11 @@ __device__ __forceinline__ float eff_mass_side(const S& s, int i, f3 r, f3 d) {
   return s.half[i].w + dot(cr, m);
 }
 
+// side_a: some contact of the lane's slot has a body on side a (else every
+// one touches the table there, whose effective-mass terms are exactly zero:
+// ca x 0 + cb x m_b rounds as cb x m_b alone, so skipping them changes no bit)
 template <class S>
-__device__ __forceinline__ void prep_contact(const S& s, int c, const Params& p, int nwarm, Contact* ct) {
+__device__ __forceinline__ void prep_contact(const S& s, int c, const Params& p, int nwarm, bool side_a, Contact* ct) {
   float4 s0 = s.u.stage[c][0], s1 = s.u.stage[c][1];
   f3 pt = xyz(s0);
   float sep = s0.w;
@@ -451,9 +454,15 @@ __device__ __forceinline__ void prep_contact(const S& s, int c, const Params& p,
   ct->t2 = t2;
   ct->t1 = t1;
   float ca = (float)s.cnt[a], cb = (float)s.cnt[b];
-  ct->kn = rcp(ca * eff_mass_side(s, a, ct->ra, n) + cb * eff_mass_side(s, b, ct->rb, n));
-  ct->kt1 = rcp(ca * eff_mass_side(s, a, ct->ra, t1) + cb * eff_mass_side(s, b, ct->rb, t1));
-  ct->kt2 = rcp(ca * eff_mass_side(s, a, ct->ra, t2) + cb * eff_mass_side(s, b, ct->rb, t2));
+  if (side_a) {
+    ct->kn = rcp(ca * eff_mass_side(s, a, ct->ra, n) + cb * eff_mass_side(s, b, ct->rb, n));
+    ct->kt1 = rcp(ca * eff_mass_side(s, a, ct->ra, t1) + cb * eff_mass_side(s, b, ct->rb, t1));
+    ct->kt2 = rcp(ca * eff_mass_side(s, a, ct->ra, t2) + cb * eff_mass_side(s, b, ct->rb, t2));
+  } else {
+    ct->kn = rcp(cb * eff_mass_side(s, b, ct->rb, n));
+    ct->kt1 = rcp(cb * eff_mass_side(s, b, ct->rb, t1));
+    ct->kt2 = rcp(cb * eff_mass_side(s, b, ct->rb, t2));
+  }
   ct->mu = 0.5f * (s.iwb[a].z + s.iwb[b].z);
   ct->vstar = sep > 0.0f ? -sep * p.inv_dt : p.beta * fmaxf(-sep - p.slop, 0.0f) * p.inv_dt;
   // warm start from the previous substep's contact with the same key
@@ -1288,7 +1297,11 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
 #pragma unroll
     for (int ls = 0; ls < KW; ++ls) {
       const int c = 64 * (ls * W + wid) + lane;
-      if (c < nc) prep_contact(s, c, p, nwarm, &ct[ls]);
+      // one wave per env (throughput) skips the table side's terms; with two
+      // (one env's latency) the extra branch cost more than it saved
+      bool side_a = true;
+      if constexpr (W == 1) side_a = __ballot(c < nc && (s.cab[c < nc ? c : 0] & 255) != PLANE) != 0ull;
+      if (c < nc) prep_contact(s, c, p, nwarm, side_a, &ct[ls]);
     }
 
     // ---- 7. projected Jacobi, I iterations
@@ -1346,6 +1359,11 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
       }
     }
     const int cpad = (ccount + 7) & ~7;
+    // one wave per env: lane pairs whose lists all hold at most four entries
+    // (bodies touched by at most four contacts, e.g. boxes resting on the
+    // table alone) skip entries sh + 4 and sh + 6, zero rows whose terms
+    // change no sum (a partial sum is never -0)
+    const bool short_lists = W == 1 && two && __ballot(sum_on && ccount > 4) == 0ull;
     auto row_of = [&](unsigned code) { return *reinterpret_cast<const float4*>(imp_base + (code & 0xfffeu)); };
     auto reg_row = [&](unsigned off) { return *reinterpret_cast<const float4*>(imp_base + off); };
     auto add_signed = [](f3 a, float sg, float4 val) {
@@ -1356,7 +1374,12 @@ __device__ __forceinline__ void run_env(Smem<K, W>& s, const StepArgs& g, const 
     auto apply_sums = [&]() {
       if (!sum_on) return;
       f3 a0 = mk(0, 0, 0), a1 = mk(0, 0, 0);
-      if (two) {
+      if (two && short_lists) {
+        const float4 v0 = reg_row(radr[0]), v1 = reg_row(radr[1]);
+        a0 = add_signed(a0, rsg[0], v0);
+        a0 = add_signed(a0, rsg[1], v1);
+        a1 = mk(pair_swap(a0.x), pair_swap(a0.y), pair_swap(a0.z));
+      } else if (two) {
         {
           float4 val[4];
 #pragma unroll
